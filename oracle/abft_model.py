@@ -1,0 +1,170 @@
+"""CPU reference model of two-side ABFT with location encoding -- TEST INFRASTRUCTURE ONLY.
+
+Follows TurboFFT Sec. 2.2 (checksum identity (e^T W) x = e^T (W x), Eq. 1-2,
+the encoding-vector discussion and the threshold test), Sec. 4.1 (two-side
+checksum X^c = [X, Xe], Y^c = W^c X^c, Eq. 4-5; location encoding with the
+weights e_3 = (1, 2, ...); delayed batched correction) and Sec. 4.3
+(multi-transaction groups, location weight = the signal's index in the group).
+All arithmetic here is fp64 numpy plus the oracle FFT of this package.
+
+Readings taken where the paper is silent (each one is listed in the design doc):
+  * encoding vector e_k = w_M^k, w_M = exp(-2 pi i / M), M = 3 (Wang's vector),
+    switched to M = 5 when 3 | N (then w_3 makes e^T W vanish almost everywhere);
+  * left vector a = e^T W = W e (W is symmetric), closed form
+    a_n = (1 - w_M^N) / (1 - w_M w_N^n);
+  * location weights are group-local, 1-based: w_b = b + 1;
+  * absolute threshold tau = kappa * u * sqrt(N log2 N) * sqrt(nu) with nu the
+    group's input energy, instead of the relative test, which fails when the
+    checksum is near zero;
+  * an output value that is not finite or exceeds the magnitude cap H marks its
+    signal as corrupted directly (exponent flips);
+  * correction adds c = W(Xe) - Ye to the located signal when c is small
+    (max |c| <= rms output norm of one signal), otherwise rebuilds the signal
+    as W(Xe) - sum of the other outputs.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import fft as _oracle_fft
+
+UNIT_ROUNDOFF = {"fp32": 2.0 ** -24, "fp64": 2.0 ** -53}
+MAG_CAP = {"fp32": 2.0 ** 64, "fp64": 2.0 ** 512}
+
+
+def choose_M(N: int) -> int:
+    """Period of the encoding vector: 3, or 5 when 3 divides N."""
+    return 5 if N % 3 == 0 else 3
+
+
+def encoding_vector(N: int, M: int, sign: int = -1) -> np.ndarray:
+    """e_k = exp(sign 2 pi i k / M), k = 0..N-1 (Wang-type vector)."""
+    k = np.arange(N) % M
+    return np.exp(sign * 2j * np.pi * k / M)
+
+
+def left_vector(N: int, M: int, dir: int = -1) -> np.ndarray:
+    """a = e^T W_dir computed as the transform of e (W_dir is symmetric)."""
+    e = encoding_vector(N, M)
+    return _oracle_fft(e, dir=dir, scale=1.0)
+
+
+def left_vector_closed_form(N: int, M: int, dir: int = -1) -> np.ndarray:
+    """a_n = (1 - w_M^N) / (1 - w_M w_N^{dir n}) -- geometric series in k."""
+    wm = np.exp(-2j * np.pi / M)
+    n = np.arange(N)
+    wn = np.exp(dir * 2j * np.pi * n / N)
+    return (1 - wm ** N) / (1 - wm * wn)
+
+
+def threshold(N: int, nu: float, precision: str, kappa: float) -> float:
+    """tau = kappa * u * sqrt(N log2 N) * sqrt(nu)."""
+    u = UNIT_ROUNDOFF[precision]
+    lg = math.log2(N) if N > 1 else 1.0
+    return kappa * u * math.sqrt(N * lg) * math.sqrt(max(nu, 0.0))
+
+
+def flip_bit(value: complex, part: int, bit: int, precision: str) -> complex:
+    """Flip one bit of the real (part=0) or imaginary (part=1) component,
+    as stored in binary32 or binary64 (Sec. 5.3 injection protocol)."""
+    if precision == "fp32":
+        arr = np.array([value.real, value.imag], dtype=np.float32)
+        u = arr.view(np.uint32)
+        u[part] ^= np.uint32(1 << bit)
+    else:
+        arr = np.array([value.real, value.imag], dtype=np.float64)
+        u = arr.view(np.uint64)
+        u[part] ^= np.uint64(1 << bit)
+    return complex(float(arr[0]), float(arr[1]))
+
+
+def group_checksums(X: np.ndarray, Y: np.ndarray, M: int, dir: int = -1):
+    """Left/right, plain/location-weighted checksums of one group (Eq. 4-5).
+
+    X, Y: [G, N].  Returns dict with s_in, l_in, s_out, l_out (complex),
+    x_s = X e_c, y_s = Y e_c (the right-side sums, e_c = ones), nu = sum |x|^2.
+    """
+    G, N = X.shape
+    a = left_vector(N, M, dir)
+    e = encoding_vector(N, M)
+    w = np.arange(1, G + 1, dtype=np.float64)
+    with np.errstate(all="ignore"):
+        p = X @ a            # a^T x_b per signal
+        q = Y @ e            # e^T y_b per signal
+        return {
+            "s_in": p.sum(), "l_in": (w * p).sum(),
+            "s_out": q.sum(), "l_out": (w * q).sum(),
+            "x_s": X.sum(axis=0), "y_s": Y.sum(axis=0),
+            "nu": float(np.sum(np.abs(X) ** 2)),
+        }
+
+
+def abft_group(X, Yp, precision: str = "fp32", kappa: float = 32.0, dir: int = -1,
+               M: int | None = None, rho: float = 0.25):
+    """Detect, locate and correct one group (Sec. 4.1-4.3).
+
+    X  : [G, N] inputs of the group's signals.
+    Yp : [G, N] unscaled transforms as produced, possibly with one fault.
+    Returns a dict: action in {"clean", "corrected", "rebuilt", "uncorrectable",
+    "unchecked"}, located index b (or None), corrected outputs Y, D0, D1, tau.
+    """
+    X = np.asarray(X, dtype=np.complex128)
+    Y = np.array(Yp, dtype=np.complex128, copy=True)
+    G, N = X.shape
+    if M is None:
+        M = choose_M(N)
+    cs = group_checksums(X, Y, M, dir)
+    nu = cs["nu"]
+    res = {"action": "clean", "b": None, "Y": Y, "tau": None, "D0": None, "D1": None}
+    if not math.isfinite(nu):
+        res["action"] = "unchecked"      # non-finite input: nothing to protect
+        return res
+    tau = threshold(N, nu, precision, kappa)
+    cap = MAG_CAP[precision]
+    with np.errstate(all="ignore"):
+        D0 = cs["s_out"] - cs["s_in"]
+        D1 = cs["l_out"] - cs["l_in"]
+        bad = ~(np.abs(Y.real) <= cap) | ~(np.abs(Y.imag) <= cap)
+    res.update(tau=tau, D0=D0, D1=D1)
+    nf = sorted(set(np.nonzero(bad.any(axis=1))[0].tolist()))
+    if len(nf) > 1:
+        res["action"] = "uncorrectable"
+        return res
+    if len(nf) == 1:
+        b = nf[0]
+    elif not (abs(D0) <= tau):
+        r = D1 / D0
+        b = int(round(r.real)) - 1
+        if not (0 <= b < G and abs(r - (b + 1)) <= rho):
+            res["action"] = "uncorrectable"
+            return res
+    else:
+        return res
+    res["b"] = b
+    # Right-side correction: c = W (X e_c) - Y' e_c = -(fault) under SEU (Eq. 5).
+    Wxs = _oracle_fft(cs["x_s"], dir=dir, scale=1.0)
+    with np.errstate(all="ignore"):
+        c = Wxs - cs["y_s"]
+        y_rms = math.sqrt(N * nu / G)
+        small = bool(np.all(np.isfinite(c))) and float(np.max(np.abs(c))) <= y_rms and not nf
+    e = encoding_vector(N, M)
+    if small:
+        Y[b] = Y[b] + c
+        ok = abs(np.dot(e, c) + D0) <= tau
+        res["action"] = "corrected" if ok else "uncorrectable"
+    else:
+        others = np.delete(Y, b, axis=0).sum(axis=0)
+        Y[b] = Wxs - others
+        ok = bool(np.all(np.abs(Y[b].real) <= cap) and np.all(np.abs(Y[b].imag) <= cap))
+        res["action"] = "rebuilt" if ok else "uncorrectable"
+    res["Y"] = Y
+    return res
+
+
+def grad_sum_w_abs2(x, w) -> np.ndarray:
+    """Gradient of L = sum w * |FFT(x)|^2 w.r.t. complex x, PyTorch convention
+    (dL/dRe + i dL/dIm): 2 * conj(W)^T (w * y) = 2 * (unscaled inverse DFT)(w * y)."""
+    y = _oracle_fft(x, dir=-1, scale=1.0)
+    return _oracle_fft(2.0 * np.asarray(w) * y, dir=+1, scale=1.0)

@@ -1,0 +1,288 @@
+"""Pins for the CPU ABFT reference model (TurboFFT Sec. 2.2, Sec. 4.1-4.3).
+
+The checks come from the mathematics of the paper's equations, not from the
+model's own code: closed forms and brute-force sums written here, the error
+propagation of real FFT stage orders written here (radix-2 DIT and the radix-16
+Stockham order the GPU kernels use), the location identity, the correction
+identity of Eq. 5, and finite differences for the gradient.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import abft_model as am
+from paper_2412_05824_amd import synth
+
+
+def brute_left(N, M, dir=-1):
+    """(e^T W)_n = sum_k e_k w_N^{dir k n}, summed term by term."""
+    k = np.arange(N)
+    e = np.exp(-2j * np.pi * (k % M) / M)
+    out = np.empty(N, complex)
+    for n in range(N):
+        out[n] = np.sum(e * np.exp(dir * 2j * np.pi * ((k * n) % N) / N))
+    return out
+
+
+@pytest.mark.parametrize("N,M", [(8, 3), (64, 3), (256, 3), (12, 5), (96, 5), (48, 7), (1024, 5)])
+def test_left_vector_closed_form_and_norm(N, M):
+    for d in (-1, +1):
+        ref = brute_left(N, M, d)
+        np.testing.assert_allclose(am.left_vector(N, M, d), ref, rtol=0, atol=1e-10 * N)
+        np.testing.assert_allclose(am.left_vector_closed_form(N, M, d), ref, rtol=0, atol=1e-10 * N)
+        # ||e^T W||_2 = N (Parseval with ||e||^2 = N)
+        assert abs(np.linalg.norm(am.left_vector(N, M, d)) - N) <= 1e-9 * N
+
+
+def test_m3_degenerates_when_3_divides_N():
+    # with 3 | N, w_3^N = 1 and e^T W collapses onto a single index, like the
+    # all-ones vector; the model then switches to M = 5
+    for N in (12, 48, 96, 3 << 10):
+        a3 = brute_left(N, 3)
+        assert np.sum(np.abs(a3) > 1e-6 * N) == 1
+        assert am.choose_M(N) == 5
+        assert np.min(np.abs(am.left_vector(N, 5))) > 0.1
+    for N in (64, 1 << 12):
+        assert am.choose_M(N) == 3
+        assert np.min(np.abs(am.left_vector(N, 3))) > 0.1
+
+
+def test_checksum_identity_fault_free():
+    # (e^T W) x = e^T (W x)  (Eq. 1-2), two-side form Eq. 4-5
+    N, G = 256, 8
+    X = synth.signals(G, N, seed=5, dtype=np.complex128)
+    Y = oracle.fft(X)
+    cs = am.group_checksums(X, Y, 3)
+    scale = math.sqrt(N * cs["nu"])
+    assert abs(cs["s_out"] - cs["s_in"]) <= 1e-13 * scale
+    assert abs(cs["l_out"] - cs["l_in"]) <= 1e-12 * scale
+    np.testing.assert_allclose(oracle.fft(cs["x_s"]), cs["y_s"], rtol=0, atol=1e-12 * scale)
+
+
+# --- stage-ordered FFTs written here to inject errors between stages -------
+
+def dit_radix2_with_fault(x, stage, pos, eps):
+    """Iterative radix-2 DIT; adds eps to element pos after `stage` butterflies."""
+    N = len(x)
+    lg = int(math.log2(N))
+    idx = np.array([int(format(i, f"0{lg}b")[::-1], 2) for i in range(N)])
+    a = np.array(x, complex)[idx]
+    if stage == 0:
+        a[pos] += eps
+    m = 1
+    for s in range(1, lg + 1):
+        w = np.exp(-2j * np.pi * np.arange(m) / (2 * m))
+        for start in range(0, N, 2 * m):
+            u = a[start:start + m].copy()
+            v = a[start + m:start + 2 * m] * w
+            a[start:start + m] = u + v
+            a[start + m:start + 2 * m] = u - v
+        m *= 2
+        if s == stage:
+            a[pos] += eps
+    return a
+
+
+def stockham_with_fault(x, radices, stage, pos, eps):
+    """Stockham autosort: stage s combines L = prod(radices[:s]) into L*R.
+    Adds eps to buffer element pos after stage `stage` (0 = on the input)."""
+    N = len(x)
+    a = np.array(x, complex)
+    if stage == 0:
+        a[pos] += eps
+    L = 1
+    for s, R in enumerate(radices, start=1):
+        out = np.empty_like(a)
+        F = np.exp(-2j * np.pi * np.outer(np.arange(R), np.arange(R)) / R)
+        for beta in range(N // R):
+            k, g = beta % L, beta // L
+            v = a[beta + np.arange(R) * (N // R)] * np.exp(-2j * np.pi * np.arange(R) * k / (L * R))
+            out[g * L * R + k + np.arange(R) * L] = F @ v
+        a = out
+        L *= R
+        if s == stage:
+            a[pos] += eps
+    return a
+
+
+def _d0_single(x, y_faulty, M):
+    N = len(x)
+    cs = am.group_checksums(x[None, :], y_faulty[None, :], M)
+    return cs["s_out"] - cs["s_in"]
+
+
+@pytest.mark.parametrize("N", [16, 64])
+def test_detection_bound_radix2_every_stage_and_position(N):
+    # any single additive fault eps between stages gives |D0| >= |eps| |1 - w_M^N| / 2
+    x = synth.signals(1, N, seed=N, dtype=np.complex128)[0]
+    np.testing.assert_allclose(dit_radix2_with_fault(x, -1, 0, 0), np.fft.fft(x), atol=1e-12)
+    M = 3
+    bound = abs(1 - np.exp(-2j * np.pi * N / M)) / 2
+    eps = 1e-3 * (0.6 - 0.8j)
+    lg = int(math.log2(N))
+    worst = np.inf
+    for stage in range(lg + 1):
+        for pos in range(N):
+            y = dit_radix2_with_fault(x, stage, pos, eps)
+            worst = min(worst, abs(_d0_single(x, y, M)) / abs(eps))
+    assert worst >= bound * (1 - 1e-6)
+    assert worst <= bound * 1.5   # the bound is attained up to a small factor
+
+
+def test_detection_bound_stockham_radix16():
+    N, radices = 256, [16, 16]
+    x = synth.signals(1, N, seed=3, dtype=np.complex128)[0]
+    np.testing.assert_allclose(stockham_with_fault(x, radices, -1, 0, 0), np.fft.fft(x), atol=1e-11)
+    for M in (3, 5):
+        bound = abs(1 - np.exp(-2j * np.pi * N / M)) / 2
+        eps = 2e-3 * (1 + 0.5j)
+        worst = np.inf
+        for stage in range(len(radices) + 1):
+            for pos in range(N):
+                y = stockham_with_fault(x, radices, stage, pos, eps)
+                worst = min(worst, abs(_d0_single(x, y, M)) / abs(eps))
+        assert worst >= bound * (1 - 1e-6)
+
+
+def test_ones_vector_misses_faults():
+    # Sec. 2.2: the all-ones vector misses some propagated faults; w_3 misses none
+    N = 16
+    x = synth.signals(1, N, seed=1, dtype=np.complex128)[0]
+    eps = 1e-2
+    missed_ones = missed_w3 = 0
+    for stage in range(int(math.log2(N)) + 1):
+        for pos in range(N):
+            y = dit_radix2_with_fault(x, stage, pos, eps)
+            y0 = np.fft.fft(x)
+            d_ones = np.sum(y) - np.sum(y0)
+            missed_ones += abs(d_ones) < 1e-9
+            missed_w3 += abs(_d0_single(x, y, 3)) < 1e-9
+    assert missed_ones > 0
+    assert missed_w3 == 0
+
+
+def test_location_identity():
+    # D1 / D0 = b* + 1 for one fault in signal b* (location weights 1, 2, ...)
+    N, G = 64, 8
+    X = synth.signals(G, N, seed=9, dtype=np.complex128)
+    Y = oracle.fft(X)
+    for bstar in range(G):
+        for stage in (0, 3, 6):
+            Yf = Y.copy()
+            Yf[bstar] = dit_radix2_with_fault(X[bstar], stage, (5 * bstar + 1) % N, 0.7 - 0.2j)
+            cs = am.group_checksums(X, Yf, 3)
+            r = (cs["l_out"] - cs["l_in"]) / (cs["s_out"] - cs["s_in"])
+            assert abs(r - (bstar + 1)) < 1e-9
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_correction_restores_fault_free_output(precision):
+    N, G = 128, 8
+    X = synth.signals(G, N, seed=21, dtype=np.complex128)
+    Y = oracle.fft(X)
+    # fault-free group is clean
+    assert am.abft_group(X, Y, precision)["action"] == "clean"
+    for bstar, stage in [(0, 7), (3, 2), (7, 0)]:
+        Yf = Y.copy()
+        Yf[bstar] = dit_radix2_with_fault(X[bstar], stage, 17, 0.05 + 0.3j)
+        r = am.abft_group(X, Yf, precision)
+        assert r["action"] == "corrected"
+        assert r["b"] == bstar
+        # Eq. 5: W(Xe) - Y'e = -(fault), so the corrected output is the DFT
+        assert oracle.rel_l2(r["Y"], Y) < 1e-13
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_bit_flip_paths(precision):
+    # An undetected flip changes one signal by at most tau, i.e. by a relative
+    # kappa * u * sqrt(G log2 N) of its norm: in fp32 that stays below 2e-6 only
+    # for small kappa * sqrt(G log2 N), which bounds the group size G.
+    N = 256
+    G, kappa = (4, 4.0) if precision == "fp32" else (8, 32.0)
+    dt = np.complex64 if precision == "fp32" else np.complex128
+    X = synth.signals(G, N, seed=33, dtype=dt).astype(np.complex128)
+    Y = oracle.fft(X).astype(dt).astype(np.complex128)   # outputs as stored
+    nbits = 31 if precision == "fp32" else 63
+    tol = 2e-6 if precision == "fp32" else 1e-13
+    kinds = set()
+    for bit in range(nbits):
+        for part in (0, 1):
+            Yf = Y.copy()
+            b, k = bit % G, (7 * bit + part) % N
+            Yf[b, k] = am.flip_bit(complex(Y[b, k]), part, bit, precision)
+            delta = abs(Yf[b, k] - Y[b, k])
+            r = am.abft_group(X, Yf, precision, kappa=kappa)
+            kinds.add(r["action"])
+            if r["action"] == "clean":
+                # undetected flips are below the threshold and harmless
+                assert delta <= r["tau"]
+                assert oracle.rel_l2(Yf[b], Y[b]) < tol
+            else:
+                assert r["action"] in ("corrected", "rebuilt")
+                assert r["b"] == b
+                assert oracle.rel_l2(r["Y"][b], Y[b]) < tol
+            if np.isfinite(delta) and delta > 4 * r["tau"]:
+                assert r["action"] != "clean"
+    assert {"clean", "corrected", "rebuilt"} <= kinds
+
+
+def test_non_finite_and_two_faults():
+    N, G = 64, 4
+    X = synth.signals(G, N, seed=2, dtype=np.complex128)
+    Y = oracle.fft(X)
+    Yf = Y.copy()
+    Yf[2, 5] = complex(np.inf, 0)
+    r = am.abft_group(X, Yf, "fp32")
+    assert r["action"] == "rebuilt" and r["b"] == 2
+    assert oracle.rel_l2(r["Y"], Y) < 1e-12
+    Yf = Y.copy()
+    Yf[1, 3] = np.nan
+    Yf[3, 4] = np.inf
+    assert am.abft_group(X, Yf, "fp32")["action"] == "uncorrectable"
+    # two finite faults in different signals: ratio D1/D0 is not an index
+    Yf = Y.copy()
+    Yf[0, 1] += 1.0
+    Yf[1, 9] += 1.0j
+    r = am.abft_group(X, Yf, "fp32")
+    assert r["action"] == "uncorrectable"
+    # non-finite input: the group is not checked
+    Xn = X.copy()
+    Xn[0, 0] = np.nan
+    assert am.abft_group(Xn, Y, "fp32")["action"] == "unchecked"
+
+
+def test_flip_bit_helper():
+    assert am.flip_bit(1.5 + 2j, 0, 31, "fp32") == complex(-1.5, 2)
+    assert am.flip_bit(1.5 + 2j, 1, 63, "fp64") == complex(1.5, -2)
+    assert am.flip_bit(1.0 + 0j, 0, 23, "fp32") == complex(0.5, 0)     # exponent LSB
+    assert am.flip_bit(1.0 + 0j, 0, 52, "fp64") == complex(0.5, 0)
+    assert am.flip_bit(1.0 + 0j, 0, 22, "fp32") == complex(1.5, 0)     # mantissa MSB
+
+
+def test_gradient_closed_form_vs_finite_differences_and_torch():
+    import torch
+    rows, N = 3, 64
+    x = synth.signals(rows, N, seed=4, dtype=np.complex128)
+    w = synth.weights((rows, N), seed=5, dtype=np.float64)
+
+    def loss(z):
+        return float(np.sum(w * np.abs(oracle.fft(z)) ** 2))
+
+    g = am.grad_sum_w_abs2(x, w)
+    h = 1e-6
+    fd = np.empty_like(x)
+    for r in range(rows):
+        for n in range(0, N, 7):
+            e = np.zeros_like(x)
+            e[r, n] = h
+            dre = (loss(x + e) - loss(x - e)) / (2 * h)
+            dim = (loss(x + 1j * e) - loss(x - 1j * e)) / (2 * h)
+            fd[r, n] = dre + 1j * dim
+    sel = (slice(None), slice(0, N, 7))
+    assert oracle.rel_l2(g[sel], fd[sel]) < 1e-8
+    xt = torch.tensor(x, requires_grad=True)
+    lt = (torch.tensor(w) * torch.fft.fft(xt).abs() ** 2).sum()
+    lt.backward()
+    assert oracle.rel_l2(g, xt.grad.numpy()) < 1e-12
