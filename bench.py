@@ -1,0 +1,227 @@
+"""Benchmark: batched fp32 C2C FFT with fused two-side ABFT on one MI355X.
+
+Workload (the headline sweep): complex64 forward transforms, N = 2^6 .. 2^22,
+batch = 2^27 / N (1 GiB per buffer), inputs U[-1, 1) re/im, ABFT on
+(TFFT_FT_CORRECT).  One step = one launch per N over its whole 1 GiB batch,
+inputs resident in HBM.  value = algorithmic bytes (read x + write y,
+2 * N * batch * 8 per launch) summed over the sweep / step time, in GB/s.
+
+Printed as ONE JSON line, with:
+  * sweep: per N, effective GB/s with ABFT off, on, and on under injection
+    (one seeded single-bit flip per 100 launches), ABFT overhead and counts;
+  * roofline: the kernel that takes most of the step, HBM-bound, achieved
+    GB/s from HIP events on the launch stream against 8 TB/s;
+  * cpu_baseline: the fp64 CPU oracle on a bounded sample of the same sweep.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+TOTAL_ELEMS = 1 << 27          # 1 GiB of complex64 per buffer
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=10)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--sizes", type=str, default="", help="comma list of log2 N (default 6..22)")
+    p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--no-extra", action="store_true", help="skip the off/injection sweep")
+    p.add_argument("--cpu-seconds", type=float, default=15.0)
+    return p.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2412_05824_amd as tf
+    from paper_2412_05824_amd import synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    logs = [int(s) for s in args.sizes.split(",") if s] if args.sizes else list(range(6, 23))
+    sizes = [1 << k for k in logs if tf.supported(1 << k, torch.complex64)]
+    skipped = [1 << k for k in logs if (1 << k) not in sizes]
+
+    # one seeded 1 GiB input, viewed as [2^27 / N, N] for every N
+    t0 = time.time()
+    x_host = synth.signals(1, TOTAL_ELEMS, seed=2000, dtype=np.complex64).reshape(-1)
+    x = torch.from_numpy(x_host).to(dev)
+    y = torch.empty_like(x)
+    counts = tf.new_counts(dev)
+    print(f"# input ready in {time.time() - t0:.1f}s; sizes {sizes}", file=sys.stderr, flush=True)
+
+    def launch(N, ft):
+        xv = x.view(-1, N)
+        yv = y.view(-1, N)
+        tf.fft_c2c(xv, dir=tf.FORWARD, ft_mode=ft, out=yv, counts=counts)
+
+    for N in sizes:
+        tf.prepare(N, torch.complex64, tf.FT_CORRECT)
+        tf.prepare(N, torch.complex64, tf.FT_OFF)
+
+    def time_sweep(ft, steps, warmup, per_kernel=None):
+        for _ in range(warmup):
+            for N in sizes:
+                launch(N, ft)
+        torch.cuda.synchronize()
+        ev = {N: [] for N in sizes}
+        start = torch.cuda.Event(enable_timing=True)
+        end = torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        for _ in range(steps):
+            for N in sizes:
+                if per_kernel is not None:
+                    a = torch.cuda.Event(enable_timing=True)
+                    b = torch.cuda.Event(enable_timing=True)
+                    a.record(stream)
+                    launch(N, ft)
+                    b.record(stream)
+                    ev[N].append((a, b))
+                else:
+                    launch(N, ft)
+        end.record(stream)
+        torch.cuda.synchronize()
+        total_ms = start.elapsed_time(end)
+        if per_kernel is not None:
+            for N in sizes:
+                per_kernel[N] = sum(a.elapsed_time(b) for a, b in ev[N]) / len(ev[N])
+        return total_ms
+
+    # ---- timed region: K steps of the ABFT sweep ----
+    torch.cuda.synchronize()
+    per_kernel_ms = {}
+    total_ms = time_sweep(tf.FT_CORRECT, args.steps, args.warmup, per_kernel=per_kernel_ms)
+    ms_per_step = total_ms / args.steps
+    bytes_per_step = sum(2 * TOTAL_ELEMS * 8 for _ in sizes)
+    value = bytes_per_step / (ms_per_step * 1e-3) / 1e9
+    c_clean = tf.counts_dict(counts)
+
+    sweep = {}
+    for N in sizes:
+        sweep[N] = {"ft_ms": per_kernel_ms[N],
+                    "ft_gbs": 2 * TOTAL_ELEMS * 8 / (per_kernel_ms[N] * 1e-3) / 1e9}
+
+    # ---- context (outside the timed region): ABFT off, and under injection ----
+    if not args.no_extra:
+        off_ms = {}
+        time_sweep(tf.FT_OFF, max(3, args.steps // 2), 1, per_kernel=off_ms)
+        rng = np.random.default_rng(2024)
+        inj_ms = {}
+        for N in sizes:
+            counts.zero_()
+            batch = TOTAL_ELEMS // N
+            n_launch = 100
+            hit = int(rng.integers(0, n_launch))
+            flips = []
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for i in range(n_launch):
+                if i == hit:
+                    sig = int(rng.integers(0, batch))
+                    elem = int(rng.integers(0, N))
+                    part = int(rng.integers(0, 2))
+                    bit = int(rng.integers(0, 31))
+                    tf.inject_arm(sig, elem, part, bit, dtype=torch.complex64)
+                    flips.append((sig, elem, part, bit))
+                launch(N, tf.FT_CORRECT)
+            b.record(stream)
+            torch.cuda.synchronize()
+            inj_ms[N] = a.elapsed_time(b) / n_launch
+            cd = tf.counts_dict(counts)
+            sweep[N].update({
+                "off_ms": off_ms[N],
+                "off_gbs": 2 * TOTAL_ELEMS * 8 / (off_ms[N] * 1e-3) / 1e9,
+                "ft_overhead_pct": 100.0 * (per_kernel_ms[N] / off_ms[N] - 1.0),
+                "inj_ms": inj_ms[N],
+                "inj_overhead_pct": 100.0 * (inj_ms[N] / per_kernel_ms[N] - 1.0),
+                "inj_flips": flips,
+                "inj_counts": {k: cd[k] for k in ("detected", "corrected", "rebuilt", "uncorrectable")},
+            })
+
+    # ---- roofline of the kernel that dominates the step ----
+    dom = max(sizes, key=lambda n: per_kernel_ms[n])
+    achieved = 2 * TOTAL_ELEMS * 8 / (per_kernel_ms[dom] * 1e-3) / 1e9
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tpath):
+        try:
+            traffic = json.load(open(tpath)).get(f"fp32_ft_N{dom}")
+        except Exception:
+            traffic = None
+
+    # ---- CPU oracle baseline on a bounded sample (rank 0, N=1) ----
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        threads = min(16, os.cpu_count() or 1)
+        per_n_elems = 1 << 20
+        t_total = 0.0
+        bytes_total = 0
+        done = []
+        budget = args.cpu_seconds
+        for N in sizes:
+            nsig = max(1, per_n_elems // N)
+            xs = x_host[: nsig * N].reshape(nsig, N)
+            t1 = time.perf_counter()
+            oracle.fft(xs, threads=threads)
+            dt = time.perf_counter() - t1
+            t_total += dt
+            bytes_total += 2 * nsig * N * 8
+            done.append(N)
+            if t_total > budget:
+                break
+        cpu = {"value": bytes_total / t_total / 1e9, "unit": "GB/s", "cores": threads,
+               "kind": "oracle",
+               "sample": f"{per_n_elems} elements per N for N in {done[0]}..{done[-1]} "
+                         f"({len(done)} sizes, {t_total:.1f}s, fp64 recursive radix-2 FFT)"}
+
+    out = {
+        "metric": "batched C2C FFT GB/s & % HBM peak (FP32/FP64); ABFT overhead %; ragged vs per-size",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "fp32 complex64 forward C2C FFT sweep N=2^6..2^22, "
+                               "batch=2^27/N (1 GiB/buffer), two-side ABFT on",
+                   "sizes": sizes, "sizes_missing": skipped, "ft_mode": "correct",
+                   "pct_hbm_peak": round(100 * value / HBM_PEAK_GBS, 2)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "kernel": f"k_single fp32 N={dom} ft=correct"},
+        "cpu_baseline": cpu,
+        "clean_counts": c_clean,
+        "sweep": {str(k): v for k, v in sweep.items()},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,129 @@
+/*
+ * tfft.h -- C ABI of the MI355X (gfx950) batched complex-to-complex FFT with
+ * fused two-side ABFT (algorithm-based fault tolerance).
+ *
+ * Method: TurboFFT (Wu et al., PPoPP'25, arXiv:2412.05824).
+ *   Transform, Sec. 2.2 "DFT and FFT":
+ *     forward  y_k = sum_n x_n exp(-2 pi i k n / N)
+ *     inverse  x_k = (1/N) sum_n y_n exp(+2 pi i k n / N)
+ *   Fault tolerance, Sec. 4.1-4.3: checksums e^T W x (left side) and W X e
+ *   (right side, batch sum), location weights 1, 2, ... per signal, detection
+ *   by comparing e^T y with (e^T W) x, correction by adding W(Xe) - Ye to the
+ *   located signal after the group of transactions ("delayed batched
+ *   correction"), under the single-event-upset assumption (Sec. 2.2 fault
+ *   model): at most one faulty signal per group.
+ *
+ * Conventions for every entry point:
+ *   - Complex data are interleaved (re, im), batch-major: signal b occupies
+ *     elements [b*N, (b+1)*N).  TFFT_FP32 = complex64 (8 bytes per element),
+ *     TFFT_FP64 = complex128 (16 bytes per element).
+ *   - Pointers named x, y, counts, offsets, sizes are DEVICE pointers owned by
+ *     the caller.  hip_stream is a hipStream_t (NULL = the default stream).
+ *   - Calls are asynchronous on hip_stream and never synchronise the device.
+ *   - Return value: TFFT_OK or a negative tfft_status.  No exception crosses
+ *     the ABI.  Detected and corrected soft errors are data (counters), not
+ *     error returns.
+ *   - The library owns its twiddle and checksum tables, allocated by
+ *     tfft_prepare* (or lazily by the first call outside stream capture) and
+ *     freed when the library is unloaded.  A call made while hip_stream is
+ *     being captured into a graph never allocates: if its tables are missing
+ *     it returns TFFT_ECAPTURE.
+ */
+#ifndef TFFT_H
+#define TFFT_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TFFT_OK = 0,
+    TFFT_EINVAL = -1,       /* null pointer, N < 1, batch < 0, unknown enum value */
+    TFFT_EUNSUPPORTED = -2, /* size or mode without a kernel in this build */
+    TFFT_EALIGN = -3,       /* x or y not aligned to the element size */
+    TFFT_EHIP = -4,         /* HIP runtime error, see tfft_last_hip_error() */
+    TFFT_ENOMEM = -5,       /* table allocation failed */
+    TFFT_ECAPTURE = -6      /* would allocate during stream capture */
+} tfft_status;
+
+enum { TFFT_FORWARD = -1, TFFT_INVERSE = +1 };       /* sign of the exponent */
+enum { TFFT_FP32 = 0, TFFT_FP64 = 1 };
+enum { TFFT_FT_OFF = 0, TFFT_FT_DETECT = 1, TFFT_FT_CORRECT = 2 };
+
+/* Device-resident counters, accumulated by every ABFT call (the caller zeroes
+ * them).  detected: groups whose checksums disagreed (or held a non-finite /
+ * oversized output); corrected: fixed by adding W(Xe)-Ye; rebuilt: fixed by
+ * recomputing the located signal as W(Xe) minus the group's other outputs;
+ * uncorrectable: detected but not located or not verified (for example two
+ * faults in one group); last_signal: global index of the most recently
+ * located signal. */
+typedef struct {
+    unsigned long long detected, corrected, rebuilt, uncorrectable, last_signal, reserved[3];
+} tfft_ft_counts;
+
+/* Batched 1-D C2C transform of `batch` signals of length N.
+ *   x, y      device buffers of batch*N elements; x == y (in place) allowed,
+ *             partial overlap is not.
+ *   dir       TFFT_FORWARD or TFFT_INVERSE.
+ *   precision TFFT_FP32 or TFFT_FP64.
+ *   ft_mode   TFFT_FT_OFF, TFFT_FT_DETECT (one-side check with location) or
+ *             TFFT_FT_CORRECT (two-side check, location and correction).
+ *   scale     multiplies every output; 0 selects 1 (forward) or 1/N (inverse).
+ *   counts    device tfft_ft_counts, required unless ft_mode is TFFT_FT_OFF.
+ * N must be 2^k or 3*2^k within the sizes this build supports
+ * (tfft_supported()).  batch = 0 is a no-op. */
+int tfft_c2c(const void* x, void* y, long long N, long long batch, int dir, int precision,
+             int ft_mode, double scale, tfft_ft_counts* counts, void* hip_stream);
+
+/* Ragged batch: `count` signals of different lengths packed back to back in
+ * one persistent launch.  offsets[i] is the first element of signal i
+ * (offsets has count+1 entries, offsets[count] = total elements) and sizes[i]
+ * its length; both are device arrays of int64.  The plan for this exact list
+ * must have been built by tfft_prepare_ragged (outside stream capture); the
+ * call itself allocates nothing and may be captured into a hipGraph.
+ * Semantics per signal are those of tfft_c2c. */
+int tfft_c2c_ragged(const void* x, void* y, const long long* offsets, const long long* sizes,
+                    long long count, int dir, int precision, int ft_mode,
+                    tfft_ft_counts* counts, void* hip_stream);
+
+/* Build (and cache) tables and plans for length N.  Host call, allocates.
+ * Call before capturing tfft_c2c into a graph. */
+int tfft_prepare(long long N, int precision, int ft_mode);
+
+/* Build the schedule for a ragged list (host array sizes_host[count]).
+ * Allocates device work-queue state; call outside capture. */
+int tfft_prepare_ragged(const long long* sizes_host, long long count, int precision, int ft_mode);
+
+/* 1 if N (and precision) has a kernel in this build, else 0. */
+int tfft_supported(long long N, int precision);
+
+/* Test hook (Sec. 5.3 injection protocol): arm a single-bit flip for the NEXT
+ * tfft_c2c call only.  The flip hits output element `element` of signal
+ * `signal` (real part if part == 0, imaginary if 1), bit `bit` of its IEEE
+ * representation, inside the kernel after the last butterfly and before the
+ * output checksum, i.e. as a compute-unit fault.  Returns TFFT_EINVAL for a
+ * bit outside the element's width. */
+int tfft_inject_arm(long long signal, long long element, int part, int bit, int precision);
+int tfft_inject_disarm(void);
+
+/* Override the plan choices for (N, precision): transactions per slot T
+ * (1..32) and the detection threshold factor kappa (> 0); pass 0 to keep a
+ * value.  Used by the autotuner and by tests. */
+int tfft_set_tuning(long long N, int precision, int T, double kappa);
+int tfft_get_tuning(long long N, int precision, int* T, double* kappa);
+
+/* Calibration of the detection threshold (Sec. 5.3 ROC protocol): while on,
+ * every ABFT call also records in counts->reserved[0] the largest ratio
+ * |D0| / tau over its fault-free groups, as the bits of an IEEE double
+ * (atomic max; the caller zeroes it).  D0 is the left-side checksum
+ * difference and tau the threshold.  Off by default; costs one atomic per
+ * group. */
+int tfft_calibration(int on);
+
+const char* tfft_strerror(int status);
+int tfft_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TFFT_H */

@@ -1,0 +1,9 @@
+"""MI355X-native batched C2C FFT with fused two-side ABFT (TurboFFT method).
+
+The transform runs in hand-written HIP kernels (libtfft.so, gfx950) behind the
+C ABI of include/tfft.h; this package is a thin binding over it.
+"""
+from ._lib import (FORWARD, INVERSE, FP32, FP64, FT_OFF, FT_DETECT, FT_CORRECT,  # noqa: F401
+                   TfftError)
+from .fft import (fft_c2c, prepare, supported, inject_arm, inject_disarm,  # noqa: F401
+                  set_tuning, get_tuning, new_counts, counts_dict)

@@ -1,0 +1,85 @@
+"""ctypes binding of libtfft.so (the C ABI in include/tfft.h).
+
+Argument marshalling only: every step of the transform runs in the HIP
+kernels of the library.  Importing fails loudly when the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtfft.so")
+
+TFFT_OK = 0
+TFFT_EINVAL = -1
+TFFT_EUNSUPPORTED = -2
+TFFT_EALIGN = -3
+TFFT_EHIP = -4
+TFFT_ENOMEM = -5
+TFFT_ECAPTURE = -6
+
+FORWARD = -1
+INVERSE = +1
+FP32 = 0
+FP64 = 1
+FT_OFF = 0
+FT_DETECT = 1
+FT_CORRECT = 2
+
+# exported symbols and their signatures, as declared in include/tfft.h
+_LL = ctypes.c_longlong
+_VP = ctypes.c_void_p
+_I = ctypes.c_int
+_D = ctypes.c_double
+SIGNATURES = {
+    "tfft_c2c": ([_VP, _VP, _LL, _LL, _I, _I, _I, _D, _VP, _VP], _I),
+    "tfft_c2c_ragged": ([_VP, _VP, _VP, _VP, _LL, _I, _I, _I, _VP, _VP], _I),
+    "tfft_prepare": ([_LL, _I, _I], _I),
+    "tfft_prepare_ragged": ([_VP, _LL, _I, _I], _I),
+    "tfft_supported": ([_LL, _I], _I),
+    "tfft_inject_arm": ([_LL, _LL, _I, _I, _I], _I),
+    "tfft_inject_disarm": ([], _I),
+    "tfft_set_tuning": ([_LL, _I, _I, _D], _I),
+    "tfft_get_tuning": ([_LL, _I, ctypes.POINTER(_I), ctypes.POINTER(_D)], _I),
+    "tfft_calibration": ([_I], _I),
+    "tfft_strerror": ([_I], ctypes.c_char_p),
+    "tfft_last_hip_error": ([], _I),
+}
+
+
+class TfftError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {strerror(status)} (status {status}, hip error {last_hip_error()})")
+
+
+_lib = None
+
+
+def load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() (hipcc, gfx950)")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (args, res) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def strerror(status: int) -> str:
+    return load().tfft_strerror(status).decode()
+
+
+def last_hip_error() -> int:
+    return load().tfft_last_hip_error()
+
+
+def check(status: int, what: str) -> None:
+    if status != TFFT_OK:
+        raise TfftError(status, what)

@@ -1,0 +1,196 @@
+// tfft_device.hpp -- device building blocks for the batched C2C FFT on gfx950.
+//
+// Complex arithmetic on float2/double2, the in-register small DFTs used as
+// radix-R butterflies (TurboFFT Sec. 3.1: thread-level radix-n macro kernels),
+// the XOR-swizzled LDS addressing that replaces padding (Sec. 3.2), and
+// wavefront reductions for the ABFT checksums (Sec. 4.2).
+//
+// Every transform here is the forward DFT  y_k = sum_n x_n w^{kn},
+// w = exp(-2 pi i / R)  (Sec. 2.2); the inverse is obtained by the caller by
+// conjugating on load and on store.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tfft {
+
+constexpr int kWave = 64;
+
+template <typename R> struct Vec;
+template <> struct Vec<float>  { using type = float2; };
+template <> struct Vec<double> { using type = double2; };
+
+template <class V> struct RealOf;
+template <> struct RealOf<float2>  { using type = float; };
+template <> struct RealOf<double2> { using type = double; };
+
+template <class V> __device__ __forceinline__ V cadd(V a, V b) { return V{a.x + b.x, a.y + b.y}; }
+template <class V> __device__ __forceinline__ V csub(V a, V b) { return V{a.x - b.x, a.y - b.y}; }
+template <class V> __device__ __forceinline__ V cmul(V a, V b) {
+    return V{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// multiply by -i and +i
+template <class V> __device__ __forceinline__ V mul_mi(V a) { return V{a.y, -a.x}; }
+template <class V> __device__ __forceinline__ V mul_pi(V a) { return V{-a.y, a.x}; }
+template <class V, class R> __device__ __forceinline__ V cscale(V a, R s) { return V{a.x * s, a.y * s}; }
+template <class V> __device__ __forceinline__ V cconj(V a) { return V{a.x, -a.y}; }
+
+// multiply by (c - i s), i.e. by exp(-i theta) with c = cos theta, s = sin theta
+template <class V, class R> __device__ __forceinline__ V mul_cis(V a, R c, R s) {
+    return V{a.x * c + a.y * s, a.y * c - a.x * s};
+}
+
+// ---------------------------------------------------------------------------
+// Small forward DFTs, natural order in and out.
+// ---------------------------------------------------------------------------
+#define TFFT_SQRT1_2 0.70710678118654752440084436210484903928483593768847
+#define TFFT_COS_PI8 0.92387953251128675612818318939678828682241662586364
+#define TFFT_SIN_PI8 0.38268343236508977172845998403039886676134456248563
+#define TFFT_SQRT3_2 0.86602540378443864676372317075293618347140262690519
+
+template <class V> __device__ __forceinline__ void dft2(V& a, V& b) {
+    V t = a;
+    a = cadd(t, b);
+    b = csub(t, b);
+}
+
+// y = [a+s, a - s/2 - i(sqrt3/2)d, a - s/2 + i(sqrt3/2)d], s = b+c, d = b-c
+template <class V> __device__ __forceinline__ void dft3(V& a, V& b, V& c) {
+    using R = typename RealOf<V>::type;
+    V s = cadd(b, c);
+    V d = csub(b, c);
+    V t = V{a.x - (R)0.5 * s.x, a.y - (R)0.5 * s.y};
+    a = cadd(a, s);
+    V r = cscale(mul_mi(d), (R)TFFT_SQRT3_2);   // -i (sqrt3/2) d
+    b = cadd(t, r);
+    c = csub(t, r);
+}
+
+template <class V> __device__ __forceinline__ void dft4(V& a0, V& a1, V& a2, V& a3) {
+    V t0 = cadd(a0, a2), t1 = csub(a0, a2);
+    V t2 = cadd(a1, a3), t3 = mul_mi(csub(a1, a3));
+    a0 = cadd(t0, t2);
+    a2 = csub(t0, t2);
+    a1 = cadd(t1, t3);
+    a3 = csub(t1, t3);
+}
+
+// multiply by w16^m = exp(-2 pi i m / 16), m known at compile time
+template <int m, class V> __device__ __forceinline__ V w16(V a) {
+    using R = typename RealOf<V>::type;
+    constexpr int mm = m & 15;
+    if constexpr (mm == 0) return a;
+    else if constexpr (mm == 4) return mul_mi(a);
+    else if constexpr (mm == 8) return V{-a.x, -a.y};
+    else if constexpr (mm == 12) return mul_pi(a);
+    else if constexpr (mm == 2) return V{(R)TFFT_SQRT1_2 * (a.x + a.y), (R)TFFT_SQRT1_2 * (a.y - a.x)};
+    else if constexpr (mm == 6) return V{(R)TFFT_SQRT1_2 * (a.y - a.x), (R)(-TFFT_SQRT1_2) * (a.x + a.y)};
+    else if constexpr (mm == 1) return mul_cis(a, (R)TFFT_COS_PI8, (R)TFFT_SIN_PI8);
+    else if constexpr (mm == 3) return mul_cis(a, (R)TFFT_SIN_PI8, (R)TFFT_COS_PI8);
+    else if constexpr (mm == 9) return mul_cis(a, (R)(-TFFT_COS_PI8), (R)(-TFFT_SIN_PI8));
+    else {
+        static_assert(mm == 0 || mm == 1 || mm == 2 || mm == 3 || mm == 4 || mm == 6 || mm == 8 ||
+                          mm == 9 || mm == 12,
+                      "unused w16 power");
+        return a;
+    }
+}
+
+template <class V> __device__ __forceinline__ void dft8(V (&v)[8]) {
+    dft4(v[0], v[2], v[4], v[6]);
+    dft4(v[1], v[3], v[5], v[7]);
+    // y_k = E_k + w8^k O_k, y_{k+4} = E_k - w8^k O_k  (E_k in v[2k], O_k in v[2k+1])
+    V o1 = w16<2>(v[3]), o2 = w16<4>(v[5]), o3 = w16<6>(v[7]);
+    V e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6], o0 = v[1];
+    v[0] = cadd(e0, o0); v[4] = csub(e0, o0);
+    v[1] = cadd(e1, o1); v[5] = csub(e1, o1);
+    v[2] = cadd(e2, o2); v[6] = csub(e2, o2);
+    v[3] = cadd(e3, o3); v[7] = csub(e3, o3);
+}
+
+// 16 = 4 x 4: n = 4 n1 + n2, k = k1 + 4 k2
+template <class V> __device__ __forceinline__ void dft16(V (&v)[16]) {
+    dft4(v[0], v[4], v[8], v[12]);
+    dft4(v[1], v[5], v[9], v[13]);
+    dft4(v[2], v[6], v[10], v[14]);
+    dft4(v[3], v[7], v[11], v[15]);
+    // v[n2 + 4 k1] *= w16^{n2 k1}
+    v[5] = w16<1>(v[5]);  v[6] = w16<2>(v[6]);  v[7] = w16<3>(v[7]);
+    v[9] = w16<2>(v[9]);  v[10] = w16<4>(v[10]); v[11] = w16<6>(v[11]);
+    v[13] = w16<3>(v[13]); v[14] = w16<6>(v[14]); v[15] = w16<9>(v[15]);
+    dft4(v[0], v[1], v[2], v[3]);
+    dft4(v[4], v[5], v[6], v[7]);
+    dft4(v[8], v[9], v[10], v[11]);
+    dft4(v[12], v[13], v[14], v[15]);
+    // group k1 holds y[k1 + 4 k2] in v[4 k1 + k2]: transpose the 4x4 index
+    V t[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) t[i] = v[i];
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = t[4 * k1 + k2];
+}
+
+template <int R, class V> __device__ __forceinline__ void dft(V (&v)[R]) {
+    if constexpr (R == 1) {
+    } else if constexpr (R == 2) dft2(v[0], v[1]);
+    else if constexpr (R == 3) dft3(v[0], v[1], v[2]);
+    else if constexpr (R == 4) dft4(v[0], v[1], v[2], v[3]);
+    else if constexpr (R == 8) dft8(v);
+    else if constexpr (R == 16) dft16(v);
+    else static_assert(R == 2, "unsupported radix");
+}
+
+// ---------------------------------------------------------------------------
+// Synchronisation of LDS exchanges.
+// ---------------------------------------------------------------------------
+// Within one wavefront LDS operations execute in order, so a wavefront-scope
+// fence plus a code-motion barrier is enough between a store and a load.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <bool BLOCK> __device__ __forceinline__ void lds_sync() {
+    if constexpr (BLOCK) __syncthreads();
+    else wave_lds_sync();
+}
+
+// XOR swizzle on the element index: rows of 2^B elements, the column is XORed
+// with the row number so strided accesses of one wavefront spread over all
+// banks without padding.  Stays inside the row, so any region whose size is a
+// multiple of 2^B maps onto itself.
+template <int B> __device__ __forceinline__ int swz(int g) {
+    return g ^ ((g >> B) & ((1 << B) - 1));
+}
+
+// ---------------------------------------------------------------------------
+// Reductions over aligned groups of W lanes (W a power of two <= 64).
+// ---------------------------------------------------------------------------
+template <int W, class T> __device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+    for (int off = W / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+template <int W> __device__ __forceinline__ unsigned group_or(unsigned v) {
+#pragma unroll
+    for (int off = W / 2; off >= 1; off >>= 1) v |= (unsigned)__shfl_xor((int)v, off, kWave);
+    return v;
+}
+template <int W, class T> __device__ __forceinline__ T group_max(T v) {
+#pragma unroll
+    for (int off = W / 2; off >= 1; off >>= 1) {
+        T o = __shfl_xor(v, off, kWave);
+        v = (o > v || o != o) ? o : v;   // NaN propagates
+    }
+    return v;
+}
+
+template <class T> __device__ __forceinline__ bool finite_le(T v, T cap) {
+    return __builtin_fabs(v) <= cap;   // false for NaN and +-Inf
+}
+
+}  // namespace tfft

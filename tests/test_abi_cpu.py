@@ -1,0 +1,71 @@
+"""C-ABI library checks that need no GPU: it loads, exports every function
+declared in include/tfft.h, and rejects invalid arguments before any device
+work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2412_05824_amd import _lib
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "tfft.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tfft_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported_and_bound():
+    lib = _lib.load()
+    names = declared_functions()
+    assert "tfft_c2c" in names and "tfft_c2c_ragged" in names
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in _lib.SIGNATURES, n
+
+
+def test_strerror_and_status_codes():
+    for st in (_lib.TFFT_OK, _lib.TFFT_EINVAL, _lib.TFFT_EUNSUPPORTED, _lib.TFFT_EALIGN,
+               _lib.TFFT_EHIP, _lib.TFFT_ENOMEM, _lib.TFFT_ECAPTURE):
+        assert _lib.strerror(st) and _lib.strerror(st) != "unknown status"
+    assert _lib.strerror(-99) == "unknown status"
+
+
+def test_invalid_arguments_rejected_on_host():
+    lib = _lib.load()
+    c2c = lib.tfft_c2c
+    dummy = 4096  # never dereferenced: validation fails first
+    assert c2c(dummy, dummy, 0, 4, -1, 0, 0, 0.0, None, None) == _lib.TFFT_EINVAL        # N < 1
+    assert c2c(dummy, dummy, 64, -1, -1, 0, 0, 0.0, None, None) == _lib.TFFT_EINVAL      # batch < 0
+    assert c2c(dummy, dummy, 64, 4, 0, 0, 0, 0.0, None, None) == _lib.TFFT_EINVAL        # dir
+    assert c2c(dummy, dummy, 64, 4, -1, 2, 0, 0.0, None, None) == _lib.TFFT_EINVAL       # precision
+    assert c2c(dummy, dummy, 64, 4, -1, 0, 3, 0.0, None, None) == _lib.TFFT_EINVAL       # ft mode
+    assert c2c(dummy, dummy, 100, 4, -1, 0, 0, 0.0, None, None) == _lib.TFFT_EUNSUPPORTED  # 100 = 4*25
+    assert c2c(dummy, dummy, 64, 0, -1, 0, 0, 0.0, None, None) == _lib.TFFT_OK           # empty batch
+    assert c2c(None, dummy, 64, 4, -1, 0, 0, 0.0, None, None) == _lib.TFFT_EINVAL        # null x
+    assert c2c(dummy, dummy, 64, 4, -1, 0, 2, 0.0, None, None) == _lib.TFFT_EINVAL       # FT without counts
+    assert c2c(dummy + 4, dummy + 4, 64, 4, -1, 0, 0, 0.0, None, None) == _lib.TFFT_EALIGN
+    assert c2c(dummy, dummy + 8, 64, 4, -1, 0, 0, 0.0, None, None) == _lib.TFFT_EINVAL   # partial overlap
+    assert lib.tfft_inject_arm(0, 0, 0, 32, 0) == _lib.TFFT_EINVAL
+    assert lib.tfft_inject_arm(0, 0, 2, 3, 0) == _lib.TFFT_EINVAL
+    assert lib.tfft_inject_arm(0, 0, 0, 63, 1) == _lib.TFFT_OK
+    assert lib.tfft_inject_disarm() == _lib.TFFT_OK
+    assert lib.tfft_set_tuning(64, 0, 33, 0.0) == _lib.TFFT_EINVAL
+    assert lib.tfft_prepare(0, 0, 0) == _lib.TFFT_EINVAL
+    assert lib.tfft_prepare(100, 0, 0) == _lib.TFFT_EUNSUPPORTED
+
+
+def test_supported_sizes_and_tuning_roundtrip():
+    lib = _lib.load()
+    for N in (64, 256, 1024, 4096):
+        assert lib.tfft_supported(N, 0) == 1
+        assert lib.tfft_supported(N, 1) == 1
+    assert lib.tfft_supported(100, 0) == 0
+    T = ctypes.c_int()
+    k = ctypes.c_double()
+    assert lib.tfft_set_tuning(512, 0, 2, 3.5) == 0
+    assert lib.tfft_get_tuning(512, 0, ctypes.byref(T), ctypes.byref(k)) == 0
+    assert (T.value, k.value) == (2, 3.5)

@@ -1,0 +1,185 @@
+"""GPU parity: the HIP path through the C ABI against the CPU fp64 oracle.
+
+Transform (Sec. 2.2): relative L2 <= 2e-6 (fp32), <= 1e-13 (fp64) per batch
+and per signal.  Fault tolerance (Sec. 4): with no fault the ABFT kernels
+produce bit-identical outputs to the plain kernels and count nothing; an
+injected bit flip (Sec. 5.3 protocol) that exceeds the threshold is detected,
+located and corrected back within the same tolerance.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import abft_model as am
+from paper_2412_05824_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+tf = pytest.importorskip("paper_2412_05824_amd")
+
+TOL = {torch.complex64: 2e-6, torch.complex128: 1e-13}
+NPDT = {torch.complex64: np.complex64, torch.complex128: np.complex128}
+PREC = {torch.complex64: "fp32", torch.complex128: "fp64"}
+SIZES = [64, 128, 256, 512, 1024, 2048, 4096]
+DTYPES = [torch.complex64, torch.complex128]
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _batch_for(N):
+    # several workgroups plus a ragged tail that fills no whole group
+    return max(3, (1 << 17) // N) + 3
+
+
+def _per_signal_rel(got, ref):
+    num = np.linalg.norm(got - ref, axis=1)
+    den = np.linalg.norm(ref, axis=1)
+    return num / np.maximum(den, 1e-300)
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["fp32", "fp64"])
+@pytest.mark.parametrize("N", SIZES)
+def test_forward_parity_and_ft_bit_identity(dev, N, dtype):
+    batch = _batch_for(N)
+    x = synth.signals(batch, N, seed=2000 + N, dtype=NPDT[dtype])
+    xd = torch.from_numpy(x).to(dev)
+    ref = oracle.fft(x, threads=8)
+    y0, _ = tf.fft_c2c(xd, dir=tf.FORWARD, ft_mode=tf.FT_OFF)
+    y0h = y0.cpu().numpy()
+    assert oracle.rel_l2(y0h, ref) <= TOL[dtype]
+    assert _per_signal_rel(y0h, ref).max() <= 2 * TOL[dtype]
+    for ft in (tf.FT_DETECT, tf.FT_CORRECT):
+        y, counts = tf.fft_c2c(xd, dir=tf.FORWARD, ft_mode=ft)
+        c = tf.counts_dict(counts)
+        assert c["detected"] == 0, (ft, c)
+        # ABFT must not touch the data path
+        assert torch.equal(y, y0), ft
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["fp32", "fp64"])
+@pytest.mark.parametrize("N", [64, 512, 2048, 4096])
+def test_inverse_parity_and_round_trip(dev, N, dtype):
+    batch = _batch_for(N) // 2 + 1
+    x = synth.signals(batch, N, seed=3000 + N, dist="normal", dtype=NPDT[dtype])
+    xd = torch.from_numpy(x).to(dev)
+    ref = oracle.fft(x, dir=+1, threads=8)
+    for ft in (tf.FT_OFF, tf.FT_CORRECT):
+        y, counts = tf.fft_c2c(xd, dir=tf.INVERSE, ft_mode=ft)
+        assert oracle.rel_l2(y.cpu().numpy(), ref) <= TOL[dtype]
+        if counts is not None:
+            assert tf.counts_dict(counts)["detected"] == 0
+    yf, _ = tf.fft_c2c(xd, dir=tf.FORWARD, ft_mode=tf.FT_CORRECT)
+    xr, _ = tf.fft_c2c(yf, dir=tf.INVERSE, ft_mode=tf.FT_CORRECT)
+    assert oracle.rel_l2(xr.cpu().numpy(), x) <= 2 * TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["fp32", "fp64"])
+def test_in_place_and_explicit_scale(dev, dtype):
+    N, batch = 1024, 37
+    x = synth.signals(batch, N, seed=77, dtype=NPDT[dtype])
+    xd = torch.from_numpy(x).to(dev)
+    tf.fft_c2c(xd, dir=tf.FORWARD, ft_mode=tf.FT_CORRECT, out=xd)
+    assert oracle.rel_l2(xd.cpu().numpy(), oracle.fft(x)) <= TOL[dtype]
+    xd2 = torch.from_numpy(x).to(dev)
+    y, _ = tf.fft_c2c(xd2, dir=tf.FORWARD, ft_mode=tf.FT_OFF, scale=0.5)
+    assert oracle.rel_l2(y.cpu().numpy(), 0.5 * oracle.fft(x)) <= TOL[dtype]
+
+
+def test_empty_batch_and_single_signal(dev):
+    x = torch.zeros(0, 256, dtype=torch.complex64, device=dev)
+    y, _ = tf.fft_c2c(x, ft_mode=tf.FT_OFF)
+    assert y.shape == (0, 256)
+    x1 = synth.signals(1, 256, seed=5, dtype=np.complex64)
+    y1, c = tf.fft_c2c(torch.from_numpy(x1).to(dev), ft_mode=tf.FT_CORRECT)
+    assert oracle.rel_l2(y1.cpu().numpy(), oracle.fft(x1)) <= 2e-6
+    assert tf.counts_dict(c)["detected"] == 0
+
+
+def _inject_case(dev, dtype, N, batch, sig, elem, part, bit, T=None):
+    x = synth.signals(batch, N, seed=4000 + N, dtype=NPDT[dtype])
+    xd = torch.from_numpy(x).to(dev)
+    ref = oracle.fft(x, threads=8)
+    y_clean, _ = tf.fft_c2c(xd, ft_mode=tf.FT_OFF)
+    yc = y_clean.cpu().numpy()
+    tf.inject_arm(sig, elem, part, bit, dtype=dtype)
+    y, counts = tf.fft_c2c(xd, ft_mode=tf.FT_CORRECT)
+    c = tf.counts_dict(counts)
+    yh = y.cpu().numpy()
+    # the flip the kernel applied, as the model sees it
+    flipped = am.flip_bit(complex(yc[sig, elem]), part, bit, PREC[dtype])
+    delta = abs(flipped - yc[sig, elem])
+    return x, ref, yc, yh, c, delta
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["fp32", "fp64"])
+@pytest.mark.parametrize("N", [64, 256, 1024, 4096])
+def test_injected_flip_detected_located_corrected(dev, N, dtype):
+    batch = _batch_for(N)
+    nbits = 31 if dtype == torch.complex64 else 63
+    tol = TOL[dtype]
+    rng = np.random.default_rng(N)
+    for bit in sorted(set([nbits - 1, nbits - 3, nbits - 8, nbits - 12, nbits // 2, 5, 0] +
+                          rng.integers(0, nbits, size=3).tolist())):
+        sig = int(rng.integers(0, batch))
+        elem = int(rng.integers(0, N))
+        part = int(rng.integers(0, 2))
+        x, ref, yc, yh, c, delta = _inject_case(dev, dtype, N, batch, sig, elem, part, bit)
+        per = _per_signal_rel(yh, ref)
+        msg = f"N={N} bit={bit} sig={sig} elem={elem} part={part} delta={delta:.3e} counts={c}"
+        # every output, corrupted or not, ends within tolerance of the oracle
+        assert per.max() <= 2 * tol, msg + f" worst={per.max():.3e} at {per.argmax()}"
+        if c["detected"]:
+            assert c["detected"] == 1 and c["uncorrectable"] == 0, msg
+            assert c["corrected"] + c["rebuilt"] == 1, msg
+            assert c["last_signal"] == sig, msg
+        else:
+            # only flips far below the signal's norm may pass unnoticed
+            assert delta <= 2 * tol * np.linalg.norm(ref[sig]), msg
+        # the uncorrupted signals are bit-identical to the clean run
+        others = np.ones(batch, bool)
+        others[sig] = False
+        assert np.array_equal(yh[others], yc[others]), msg
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["fp32", "fp64"])
+def test_exponent_flips_always_detected(dev, dtype):
+    # the top exponent bits change a value by orders of magnitude (or make it
+    # Inf/NaN); they must all be detected and repaired
+    N = 512
+    batch = _batch_for(N)
+    top = [30, 29, 28, 27, 26, 25, 24, 23] if dtype == torch.complex64 else [62, 61, 60, 59, 56, 53, 52]
+    for i, bit in enumerate(top):
+        sig, elem, part = (7 * i + 3) % batch, (37 * i + 1) % N, i % 2
+        x, ref, yc, yh, c, delta = _inject_case(dev, dtype, N, batch, sig, elem, part, bit)
+        msg = f"bit={bit} sig={sig} elem={elem} counts={c} delta={delta}"
+        assert c["detected"] == 1 and c["corrected"] + c["rebuilt"] == 1, msg
+        assert c["last_signal"] == sig, msg
+        assert oracle.rel_l2(yh[sig], ref[sig]) <= 2 * TOL[dtype], msg
+
+
+@pytest.mark.parametrize("T", [1, 2, 8])
+def test_transactions_per_slot(dev, T):
+    # T changes only the grouping of the checksums, never the transform
+    N, dtype = 1024, torch.complex64
+    old = tf.get_tuning(N, dtype)
+    try:
+        tf.set_tuning(N, dtype, T=T)
+        batch = 3 * T * 4 + 1
+        x = synth.signals(batch, N, seed=55, dtype=np.complex64)
+        xd = torch.from_numpy(x).to(dev)
+        y, c = tf.fft_c2c(xd, ft_mode=tf.FT_CORRECT)
+        assert oracle.rel_l2(y.cpu().numpy(), oracle.fft(x)) <= 2e-6
+        assert tf.counts_dict(c)["detected"] == 0
+        tf.inject_arm(batch - 1, 3, 1, 27, dtype=dtype)
+        y2, c2 = tf.fft_c2c(xd, ft_mode=tf.FT_CORRECT)
+        cd = tf.counts_dict(c2)
+        assert cd["detected"] == 1 and cd["last_signal"] == batch - 1, cd
+        assert torch.equal(y2, y) or oracle.rel_l2(y2.cpu().numpy(), oracle.fft(x)) <= 2e-6
+    finally:
+        tf.set_tuning(N, dtype, T=old[0], kappa=old[1])
