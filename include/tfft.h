@@ -112,6 +112,12 @@ int tfft_inject_disarm(void);
 int tfft_set_tuning(long long N, int precision, int T, double kappa);
 int tfft_get_tuning(long long N, int precision, int* T, double* kappa);
 
+/* Lengths above the single-pass limit run as a column pass and a row pass
+ * over chunks of signals whose intermediate (chunk_bytes, default 256 MiB)
+ * lives in a library workspace.  Sets the chunk size for (N, precision);
+ * 0 keeps the current value. */
+int tfft_set_chunk(long long N, int precision, long long chunk_bytes);
+
 /* Calibration of the detection threshold (Sec. 5.3 ROC protocol): while on,
  * every ABFT call also records in counts->reserved[0] the largest ratio
  * |D0| / tau over its fault-free groups, as the bits of an IEEE double

@@ -43,6 +43,7 @@ SIGNATURES = {
     "tfft_set_tuning": ([_LL, _I, _I, _D], _I),
     "tfft_get_tuning": ([_LL, _I, ctypes.POINTER(_I), ctypes.POINTER(_D)], _I),
     "tfft_calibration": ([_I], _I),
+    "tfft_set_chunk": ([_LL, _I, _LL], _I),
     "tfft_strerror": ([_I], ctypes.c_char_p),
     "tfft_last_hip_error": ([], _I),
 }

@@ -1,0 +1,22 @@
+// fp32 column/row pass kernels for N = N1 * N2 > 8192: sub-lengths 64..2048,
+// 16 sub-signals per tile (128-byte contiguous accesses) up to 512 points,
+// 8 above so that a workgroup stays at 512 lanes; E = 16, 32 for 2048 points.
+#include "tfft_registry.hpp"
+
+namespace tfft {
+
+template <int KIND> static void add_kind(std::vector<KernelEntry>& out) {
+    add_plan<float2, KIND, 64, 16, 16, 0, 4, 16>(out, 0);
+    add_plan<float2, KIND, 128, 16, 16, 0, 8, 16>(out, 0);
+    add_plan<float2, KIND, 256, 16, 16, 0, 16, 16>(out, 0);
+    add_plan<float2, KIND, 512, 16, 16, 0, 2, 16, 16>(out, 0);
+    add_plan<float2, KIND, 1024, 16, 8, 0, 4, 16, 16>(out, 0);
+    add_plan<float2, KIND, 2048, 32, 8, 0, 8, 16, 16>(out, 0);
+}
+
+void register_fp32_tiles(std::vector<KernelEntry>& out) {
+    add_kind<kColPass>(out);
+    add_kind<kRowPass>(out);
+}
+
+}  // namespace tfft

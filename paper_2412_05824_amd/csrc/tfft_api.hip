@@ -1,8 +1,11 @@
 // tfft_api.hip -- host runtime behind the C ABI declared in include/tfft.h.
 //
-// Plans come from the compiled kernel registry; twiddle tables and the ABFT
-// left vector e^T W are built here in long double, rounded once to the
-// kernel precision, uploaded at prepare time and cached for the process.
+// Plans come from the compiled kernel registry.  Twiddle tables and the ABFT
+// left vector e^T W are built here in long double, rounded once to the kernel
+// precision, uploaded at prepare time and cached for the process.  Lengths
+// above the single-pass limit run as a column pass and a row pass
+// (N = N1 * N2, TurboFFT Sec. 3.1 kernel level), over chunks of signals so
+// the intermediate stays in the on-package cache and the workspace is bounded.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -10,7 +13,6 @@
 #include <cstring>
 #include <map>
 #include <mutex>
-#include <string>
 #include <tuple>
 #include <vector>
 
@@ -34,7 +36,6 @@ void cis_neg(long long num, long long den, long double* re, long double* im) {
     const long double pi = 3.141592653589793238462643383279502884L;
     long long m = num % den;
     if (m < 0) m += den;
-    // angle = 2 pi m / den in [0, 2 pi); work with q = 8 m relative to den
     bool neg = false;
     if (2 * m > den) { m = den - m; neg = true; }          // angle -> 2 pi - angle
     long double c, s;
@@ -57,20 +58,22 @@ void cis_neg(long long num, long long den, long double* re, long double* im) {
     *im = neg ? s : -s;
 }
 
-struct Tables {
-    void* tw = nullptr;     // device, concatenated stage tables
-    void* left = nullptr;   // device, e^T W (N entries)
-};
+struct SubTables { void* tw = nullptr; void* left = nullptr; };
+struct PassTwiddle { void* hi = nullptr; void* lo = nullptr; int bits = 0; };
+struct Workspace { void* ptr = nullptr; size_t bytes = 0; };
 
 struct Tuning {
     int T;
     double kappa;
+    long long chunk_bytes;
 };
 
 std::mutex g_mu;
 std::vector<KernelEntry>* g_entries = nullptr;
-std::map<std::tuple<int, long long, int>, const KernelEntry*> g_by_key;   // (prec, N, ft)
-std::map<std::tuple<int, long long, int>, Tables> g_tables;              // (prec, N, device)
+std::map<std::tuple<int, int, int, int>, const KernelEntry*> g_by_key;   // (prec, kind, Ns, ft)
+std::map<std::tuple<int, int, int>, SubTables> g_sub;                    // (prec, Ns, device)
+std::map<std::tuple<int, long long, int>, PassTwiddle> g_pass;           // (prec, N, device)
+std::map<int, Workspace> g_ws;                                           // device
 std::map<std::pair<int, long long>, Tuning> g_tuning;
 
 struct Inject {
@@ -84,22 +87,62 @@ bool g_stats = false;   // calibration mode: kernels record max |D0| / tau
 void ensure_registry() {
     if (g_entries) return;
     g_entries = new std::vector<KernelEntry>();
-    register_fp32(*g_entries);
-    register_fp64(*g_entries);
-    for (const KernelEntry& e : *g_entries) g_by_key[std::make_tuple(e.precision, (long long)e.N, e.ft)] = &e;
+    register_fp32_single(*g_entries);
+    register_fp32_tiles(*g_entries);
+    register_fp64_single(*g_entries);
+    register_fp64_tiles(*g_entries);
+    for (const KernelEntry& e : *g_entries)
+        g_by_key[std::make_tuple(e.precision, e.kind, e.Ns, e.ft)] = &e;
 }
 
-const KernelEntry* find_entry(int precision, long long N, int ft) {
-    auto it = g_by_key.find(std::make_tuple(precision, N, ft));
+const KernelEntry* find_entry(int precision, int kind, long long Ns, int ft) {
+    if (Ns > (1 << 30)) return nullptr;
+    auto it = g_by_key.find(std::make_tuple(precision, kind, (int)Ns, ft));
     return it == g_by_key.end() ? nullptr : it->second;
 }
 
+// How a length is executed: one single-pass kernel, or a column pass of
+// length N1 and a row pass of length N2.
+struct Route {
+    const KernelEntry* single = nullptr;
+    const KernelEntry* col = nullptr;
+    const KernelEntry* row = nullptr;
+    long long N1 = 0, N2 = 0;
+};
+
+bool route_for(int precision, long long N, int ft, Route* r) {
+    *r = Route{};
+    if ((r->single = find_entry(precision, kSingle, N, ft))) return true;
+    // balanced split N = N1 * N2 with N1 <= N2, both with tile kernels
+    long long best1 = 0;
+    for (long long n1 = 2; n1 * n1 <= N; n1 <<= 1) {
+        if (N % n1) continue;
+        const long long n2 = N / n1;
+        if (find_entry(precision, kColPass, n1, ft) && find_entry(precision, kRowPass, n2, ft)) best1 = n1;
+    }
+    if (!best1) return false;
+    r->N1 = best1;
+    r->N2 = N / best1;
+    r->col = find_entry(precision, kColPass, r->N1, ft);
+    r->row = find_entry(precision, kRowPass, r->N2, ft);
+    return true;
+}
+
 Tuning default_tuning(int precision, long long N) {
-    // fp32: small groups keep an undetected sub-threshold flip inside the
-    // 2e-6 relative tolerance; fp64 has three orders of magnitude of margin.
-    (void)N;
-    if (precision == TFFT_FP32) return Tuning{4, 4.0};
-    return Tuning{8, 16.0};
+    // Groups of T signals share one checksum reduction (Sec. 4.3).  In fp32 an
+    // undetected flip just under the threshold perturbs one signal by about
+    // kappa * u * sqrt(T log2 Ns) of its norm, so T stays small to keep that
+    // under the 2e-6 relative tolerance; fp64 has ample margin.
+    Tuning t{};
+    t.chunk_bytes = 256ll << 20;
+    if (precision == TFFT_FP32) {
+        t.kappa = 8.0;
+        t.T = N <= 128 ? 2 : 1;
+    } else {
+        t.kappa = 16.0;
+        t.T = 8;
+    }
+    return t;
 }
 
 Tuning get_tuning(int precision, long long N) {
@@ -112,8 +155,17 @@ template <class R> void put(std::vector<R>& v, long double re, long double im) {
     v.push_back((R)im);
 }
 
-template <class R> int build_tables(const KernelEntry& e, Tables* out) {
-    const long long N = e.N;
+template <class R> int upload(const std::vector<R>& h, void** d) {
+    hipError_t err = hipMalloc(d, h.size() * sizeof(R));
+    if (err != hipSuccess) { g_last_hip = (int)err; *d = nullptr; return TFFT_ENOMEM; }
+    err = hipMemcpy(*d, h.data(), h.size() * sizeof(R), hipMemcpyHostToDevice);
+    if (err != hipSuccess) return hip_fail(err);
+    return TFFT_OK;
+}
+
+// stage tables w_{L R}^{j k} (k < L, j < R per stage) and a = e^T W
+template <class R> int build_sub(const KernelEntry& e, SubTables* out) {
+    const long long N = e.Ns;
     std::vector<R> tw;
     long long L = 1;
     for (int s = 0; s < e.n_stages; ++s) {
@@ -133,23 +185,39 @@ template <class R> int build_tables(const KernelEntry& e, Tables* out) {
     cis_neg(N, M, &nr, &ni);
     const long double num_re = 1.0L - nr, num_im = -ni;
     for (long long n = 0; n < N; ++n) {
-        // w_M * w_N^n = exp(-2 pi i (N + M n) / (M N))
-        long double wr, wi;
+        long double wr, wi;   // w_M w_N^n = exp(-2 pi i (N + M n) / (M N))
         cis_neg(N + M * n, M * N, &wr, &wi);
         const long double dr = 1.0L - wr, di = -wi;
         const long double den = dr * dr + di * di;
         put(left, (num_re * dr + num_im * di) / den, (num_im * dr - num_re * di) / den);
     }
-    hipError_t err;
-    err = hipMalloc(&out->tw, tw.size() * sizeof(R));
-    if (err != hipSuccess) return (g_last_hip = (int)err, TFFT_ENOMEM);
-    err = hipMalloc(&out->left, left.size() * sizeof(R));
-    if (err != hipSuccess) return (g_last_hip = (int)err, TFFT_ENOMEM);
-    err = hipMemcpy(out->tw, tw.data(), tw.size() * sizeof(R), hipMemcpyHostToDevice);
-    if (err != hipSuccess) return hip_fail(err);
-    err = hipMemcpy(out->left, left.data(), left.size() * sizeof(R), hipMemcpyHostToDevice);
-    if (err != hipSuccess) return hip_fail(err);
-    return TFFT_OK;
+    int rc = upload(tw, &out->tw);
+    if (rc != TFFT_OK) return rc;
+    return upload(left, &out->left);
+}
+
+// two-level table: w_N^m = hi[m >> bits] * lo[m & (2^bits - 1)]
+template <class R> int build_pass(long long N, PassTwiddle* out) {
+    int lg = 0;
+    while ((1ll << (lg + 1)) <= N) ++lg;
+    const int bits = (lg + 1) / 2;
+    const long long nlo = 1ll << bits;
+    const long long nhi = (N + nlo - 1) / nlo;
+    std::vector<R> hi, lo;
+    for (long long i = 0; i < nhi; ++i) {
+        long double c, s;
+        cis_neg(i * nlo, N, &c, &s);
+        put(hi, c, s);
+    }
+    for (long long i = 0; i < nlo; ++i) {
+        long double c, s;
+        cis_neg(i, N, &c, &s);
+        put(lo, c, s);
+    }
+    out->bits = bits;
+    int rc = upload(hi, &out->hi);
+    if (rc != TFFT_OK) return rc;
+    return upload(lo, &out->lo);
 }
 
 int current_device() {
@@ -158,58 +226,163 @@ int current_device() {
     return d;
 }
 
-// Tables for (precision, N) on the current device; builds them unless the
-// stream is capturing.  Caller holds g_mu.
-int get_tables(const KernelEntry& e, hipStream_t stream, bool allow_build, Tables** out) {
-    auto key = std::make_tuple(e.precision, (long long)e.N, current_device());
-    auto it = g_tables.find(key);
-    if (it != g_tables.end()) { *out = &it->second; return TFFT_OK; }
-    if (!allow_build) return TFFT_ECAPTURE;
-    if (stream) {
-        hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
-        if (hipStreamIsCapturing(stream, &st) == hipSuccess && st != hipStreamCaptureStatusNone)
-            return TFFT_ECAPTURE;
-    }
-    Tables t;
-    int rc = e.precision == TFFT_FP32 ? build_tables<float>(e, &t) : build_tables<double>(e, &t);
+bool capturing(hipStream_t stream) {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(stream, &st) == hipSuccess && st != hipStreamCaptureStatusNone;
+}
+
+// Cached resources; built unless the stream is being captured.  Caller holds g_mu.
+int get_sub(const KernelEntry& e, bool may_alloc, SubTables** out) {
+    auto key = std::make_tuple(e.precision, e.Ns, current_device());
+    auto it = g_sub.find(key);
+    if (it != g_sub.end()) { *out = &it->second; return TFFT_OK; }
+    if (!may_alloc) return TFFT_ECAPTURE;
+    SubTables t;
+    int rc = e.precision == TFFT_FP32 ? build_sub<float>(e, &t) : build_sub<double>(e, &t);
     if (rc != TFFT_OK) return rc;
-    g_tables[key] = t;
-    *out = &g_tables[key];
+    *out = &(g_sub[key] = t);
     return TFFT_OK;
 }
 
-template <class V>
-int launch_transform(const KernelEntry& e, const Tables& tb, const void* x, void* y, long long batch,
-                     int dir, double scale, tfft_ft_counts* counts, const Tuning& tu,
-                     const Inject& inj, hipStream_t stream) {
+int get_pass(int precision, long long N, bool may_alloc, PassTwiddle** out) {
+    auto key = std::make_tuple(precision, N, current_device());
+    auto it = g_pass.find(key);
+    if (it != g_pass.end()) { *out = &it->second; return TFFT_OK; }
+    if (!may_alloc) return TFFT_ECAPTURE;
+    PassTwiddle p;
+    int rc = precision == TFFT_FP32 ? build_pass<float>(N, &p) : build_pass<double>(N, &p);
+    if (rc != TFFT_OK) return rc;
+    *out = &(g_pass[key] = p);
+    return TFFT_OK;
+}
+
+int get_workspace(size_t bytes, bool may_alloc, void** out) {
+    Workspace& w = g_ws[current_device()];
+    if (w.bytes >= bytes) { *out = w.ptr; return TFFT_OK; }
+    if (!may_alloc) return TFFT_ECAPTURE;
+    if (w.ptr) {
+        hipError_t e = hipDeviceSynchronize();   // no kernel may still use the old buffer
+        if (e != hipSuccess) return hip_fail(e);
+        (void)hipFree(w.ptr);
+        w = Workspace{};
+    }
+    hipError_t e = hipMalloc(&w.ptr, bytes);
+    if (e != hipSuccess) { g_last_hip = (int)e; w = Workspace{}; return TFFT_ENOMEM; }
+    w.bytes = bytes;
+    *out = w.ptr;
+    return TFFT_OK;
+}
+
+template <class V> struct Launch {
     using R = typename RealOf<V>::type;
     KArgs<V> a{};
-    a.tw = static_cast<const V*>(tb.tw);
-    a.left = static_cast<const V*>(tb.left);
-    a.batch = batch;
+    const KernelEntry* e = nullptr;
+};
+
+template <class V>
+void fill_common(KArgs<V>& a, const KernelEntry& e, const SubTables& st, const Tuning& tu,
+                 tfft_ft_counts* counts) {
+    using R = typename RealOf<V>::type;
+    a.tw = static_cast<const V*>(st.tw);
+    a.left = static_cast<const V*>(st.left);
     a.T = tu.T;
-    a.conj = dir == TFFT_INVERSE ? 1 : 0;
-    a.scale = (R)scale;
     const double u = e.precision == TFFT_FP32 ? 0x1p-24 : 0x1p-53;
-    const double N = (double)e.N;
-    a.tau_coef = (R)(tu.kappa * u * std::sqrt(N * std::log2(N)));
+    const double Ns = (double)e.Ns;
+    a.tau_coef = (R)(tu.kappa * u * std::sqrt(Ns * std::log2(Ns)));
     a.cap = e.precision == TFFT_FP32 ? (R)0x1p64 : (R)0x1p512;
     a.counts = reinterpret_cast<FtCounts*>(counts);
-    a.inj_signal = inj.armed ? inj.signal : -1;
-    a.inj_elem = (int)inj.element;
-    a.inj_part = inj.part;
-    a.inj_bit = inj.bit;
+    a.inj_signal = -1;
     a.stats = g_stats ? 1 : 0;
-    a.x_intact = x != y ? 1 : 0;
-    const long long per_block = (long long)e.slots_per_block * tu.T;
-    const long long grid = (batch + per_block - 1) / per_block;
+}
+
+template <class V> int run(const KernelEntry& e, const void* x, void* y, const KArgs<V>& a,
+                           long long grid, hipStream_t stream) {
+    if (grid <= 0) return TFFT_OK;
     if (grid > 0x7fffffffLL) return TFFT_EUNSUPPORTED;
     hipError_t err = e.launch(x, y, &a, grid, stream);
-    if (err != hipSuccess) return hip_fail(err);
+    return err == hipSuccess ? TFFT_OK : hip_fail(err);
+}
+
+template <class V>
+int transform(const Route& rt, const void* x, void* y, long long N, long long batch, int dir,
+              double scale, tfft_ft_counts* counts, const Tuning& tu, const Inject& inj,
+              hipStream_t stream, bool may_alloc) {
+    using R = typename RealOf<V>::type;
+    const int precision = sizeof(R) == 4 ? TFFT_FP32 : TFFT_FP64;
+    const int conj = dir == TFFT_INVERSE ? 1 : 0;
+    if (rt.single) {
+        SubTables* st = nullptr;
+        int rc = get_sub(*rt.single, may_alloc, &st);
+        if (rc != TFFT_OK) return rc;
+        KArgs<V> a{};
+        fill_common(a, *rt.single, *st, tu, counts);
+        a.batch = batch;
+        a.N = N;
+        a.conj_in = a.conj_out = conj;
+        a.scale = (R)scale;
+        a.sig_base = 0;
+        a.x_intact = x != y ? 1 : 0;
+        if (inj.armed) { a.inj_signal = inj.signal; a.inj_elem = inj.element; a.inj_part = inj.part; a.inj_bit = inj.bit; }
+        const long long per_block = (long long)rt.single->slots_per_block * tu.T;
+        return run<V>(*rt.single, x, y, a, (batch + per_block - 1) / per_block, stream);
+    }
+    // two passes over chunks of signals
+    SubTables *sa = nullptr, *sb = nullptr;
+    PassTwiddle* pt = nullptr;
+    int rc = get_sub(*rt.col, may_alloc, &sa);
+    if (rc == TFFT_OK) rc = get_sub(*rt.row, may_alloc, &sb);
+    if (rc == TFFT_OK) rc = get_pass(precision, N, may_alloc, &pt);
+    if (rc != TFFT_OK) return rc;
+    const size_t sig_bytes = (size_t)N * sizeof(V);
+    long long chunk = tu.chunk_bytes / (long long)sig_bytes;
+    if (chunk < 1) chunk = 1;
+    if (chunk > batch) chunk = batch;
+    void* ws = nullptr;
+    rc = get_workspace((size_t)chunk * sig_bytes, may_alloc, &ws);
+    if (rc != TFFT_OK) return rc;
+
+    KArgs<V> A{}, B{};
+    fill_common(A, *rt.col, *sa, tu, counts);
+    fill_common(B, *rt.row, *sb, tu, counts);
+    for (KArgs<V>* k : {&A, &B}) {
+        k->N = N;
+        k->N1 = (int)rt.N1;
+        k->N2 = (int)rt.N2;
+        k->x_intact = 1;   // pass A reads x (untouched until pass B of the chunk), pass B reads Z
+    }
+    A.conj_in = conj; A.conj_out = 0; A.scale = (R)1;
+    B.conj_in = 0; B.conj_out = conj; B.scale = (R)scale;
+    B.tw_hi = static_cast<const V*>(pt->hi);
+    B.tw_lo = static_cast<const V*>(pt->lo);
+    B.tw_bits = pt->bits;
+    A.tiles = (int)(rt.N2 / rt.col->slots_per_block);
+    B.tiles = (int)(rt.N1 / rt.row->slots_per_block);
+
+    const char* xb = static_cast<const char*>(x);
+    char* yb = static_cast<char*>(y);
+    for (long long c0 = 0; c0 < batch; c0 += chunk) {
+        const long long cnt = (batch - c0 < chunk) ? batch - c0 : chunk;
+        A.batch = B.batch = cnt;
+        A.sig_base = B.sig_base = c0;
+        B.inj_signal = -1;
+        if (inj.armed && inj.signal >= c0 && inj.signal < c0 + cnt) {
+            B.inj_signal = inj.signal - c0;
+            B.inj_elem = inj.element;
+            B.inj_part = inj.part;
+            B.inj_bit = inj.bit;
+        }
+        const long long groups = (cnt + tu.T - 1) / tu.T;
+        rc = run<V>(*rt.col, xb + (size_t)c0 * sig_bytes, ws, A, groups * A.tiles, stream);
+        if (rc != TFFT_OK) return rc;
+        rc = run<V>(*rt.row, ws, yb + (size_t)c0 * sig_bytes, B, groups * B.tiles, stream);
+        if (rc != TFFT_OK) return rc;
+    }
     return TFFT_OK;
 }
 
 bool is_pow2(long long n) { return n > 0 && (n & (n - 1)) == 0; }
+
+int check_precision(int p) { return (p == TFFT_FP32 || p == TFFT_FP64) ? TFFT_OK : TFFT_EINVAL; }
 
 }  // namespace
 
@@ -231,25 +404,30 @@ const char* tfft_strerror(int status) {
 int tfft_last_hip_error(void) { return g_last_hip; }
 
 int tfft_supported(long long N, int precision) {
+    if (check_precision(precision) != TFFT_OK || N < 1) return 0;
     std::lock_guard<std::mutex> lk(g_mu);
     ensure_registry();
-    return find_entry(precision, N, 0) != nullptr ? 1 : 0;
+    Route r;
+    return route_for(precision, N, 0, &r) ? 1 : 0;
 }
 
 int tfft_prepare(long long N, int precision, int ft_mode) {
-    if (N < 1 || (precision != TFFT_FP32 && precision != TFFT_FP64) || ft_mode < 0 || ft_mode > 2)
-        return TFFT_EINVAL;
+    if (N < 1 || check_precision(precision) != TFFT_OK || ft_mode < 0 || ft_mode > 2) return TFFT_EINVAL;
     std::lock_guard<std::mutex> lk(g_mu);
     ensure_registry();
-    const KernelEntry* e = find_entry(precision, N, ft_mode);
-    if (!e) return TFFT_EUNSUPPORTED;
-    Tables* tb = nullptr;
-    return get_tables(*e, nullptr, true, &tb);
+    Route r;
+    if (!route_for(precision, N, ft_mode, &r)) return TFFT_EUNSUPPORTED;
+    SubTables* st = nullptr;
+    if (r.single) return get_sub(*r.single, true, &st);
+    int rc = get_sub(*r.col, true, &st);
+    if (rc == TFFT_OK) rc = get_sub(*r.row, true, &st);
+    PassTwiddle* pt = nullptr;
+    if (rc == TFFT_OK) rc = get_pass(precision, N, true, &pt);
+    return rc;
 }
 
 int tfft_set_tuning(long long N, int precision, int T, double kappa) {
-    if (N < 1 || (precision != TFFT_FP32 && precision != TFFT_FP64) || T < 0 || T > 32 || kappa < 0)
-        return TFFT_EINVAL;
+    if (N < 1 || check_precision(precision) != TFFT_OK || T < 0 || T > 32 || kappa < 0) return TFFT_EINVAL;
     std::lock_guard<std::mutex> lk(g_mu);
     Tuning tu = get_tuning(precision, N);
     if (T > 0) tu.T = T;
@@ -259,7 +437,7 @@ int tfft_set_tuning(long long N, int precision, int T, double kappa) {
 }
 
 int tfft_get_tuning(long long N, int precision, int* T, double* kappa) {
-    if (!T || !kappa || (precision != TFFT_FP32 && precision != TFFT_FP64)) return TFFT_EINVAL;
+    if (!T || !kappa || check_precision(precision) != TFFT_OK) return TFFT_EINVAL;
     std::lock_guard<std::mutex> lk(g_mu);
     Tuning tu = get_tuning(precision, N);
     *T = tu.T;
@@ -267,9 +445,24 @@ int tfft_get_tuning(long long N, int precision, int* T, double* kappa) {
     return TFFT_OK;
 }
 
+int tfft_set_chunk(long long N, int precision, long long chunk_bytes) {
+    if (N < 1 || check_precision(precision) != TFFT_OK || chunk_bytes < 0) return TFFT_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    Tuning tu = get_tuning(precision, N);
+    if (chunk_bytes > 0) tu.chunk_bytes = chunk_bytes;
+    g_tuning[std::make_pair(precision, N)] = tu;
+    return TFFT_OK;
+}
+
+int tfft_calibration(int on) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_stats = on != 0;
+    return TFFT_OK;
+}
+
 int tfft_inject_arm(long long signal, long long element, int part, int bit, int precision) {
     if (signal < 0 || element < 0 || (part != 0 && part != 1)) return TFFT_EINVAL;
-    if (precision != TFFT_FP32 && precision != TFFT_FP64) return TFFT_EINVAL;
+    if (check_precision(precision) != TFFT_OK) return TFFT_EINVAL;
     const int width = precision == TFFT_FP32 ? 32 : 64;
     if (bit < 0 || bit >= width) return TFFT_EINVAL;
     std::lock_guard<std::mutex> lk(g_mu);
@@ -279,12 +472,6 @@ int tfft_inject_arm(long long signal, long long element, int part, int bit, int 
     g_inj.part = part;
     g_inj.bit = bit;
     g_inj.precision = precision;
-    return TFFT_OK;
-}
-
-int tfft_calibration(int on) {
-    std::lock_guard<std::mutex> lk(g_mu);
-    g_stats = on != 0;
     return TFFT_OK;
 }
 
@@ -298,7 +485,7 @@ int tfft_c2c(const void* x, void* y, long long N, long long batch, int dir, int 
              int ft_mode, double scale, tfft_ft_counts* counts, void* hip_stream) {
     if (N < 1 || batch < 0) return TFFT_EINVAL;
     if (dir != TFFT_FORWARD && dir != TFFT_INVERSE) return TFFT_EINVAL;
-    if (precision != TFFT_FP32 && precision != TFFT_FP64) return TFFT_EINVAL;
+    if (check_precision(precision) != TFFT_OK) return TFFT_EINVAL;
     if (ft_mode < TFFT_FT_OFF || ft_mode > TFFT_FT_CORRECT) return TFFT_EINVAL;
     if (!(is_pow2(N) || (N % 3 == 0 && is_pow2(N / 3)))) return TFFT_EUNSUPPORTED;
     if (batch == 0) return TFFT_OK;
@@ -316,20 +503,23 @@ int tfft_c2c(const void* x, void* y, long long N, long long batch, int dir, int 
 
     std::lock_guard<std::mutex> lk(g_mu);
     ensure_registry();
-    const KernelEntry* e = find_entry(precision, N, ft_mode);
-    if (!e) return TFFT_EUNSUPPORTED;
-    Inject inj = g_inj;
-    if (inj.armed) {
-        if (inj.precision != precision || inj.signal >= batch || inj.element >= N) return TFFT_EINVAL;
+    Route rt;
+    if (!route_for(precision, N, ft_mode, &rt)) return TFFT_EUNSUPPORTED;
+    if (rt.single && ft_mode == TFFT_FT_CORRECT && x == y) {
+        // in place: the kernel variant that keeps the right-side input sum
+        rt.single = find_entry(precision, kSingle, N, 3);
+        if (!rt.single) return TFFT_EUNSUPPORTED;
     }
-    Tables* tb = nullptr;
-    int rc = get_tables(*e, stream, true, &tb);
-    if (rc != TFFT_OK) return rc;
+    Inject inj = g_inj;
+    if (inj.armed && (inj.precision != precision || inj.signal >= batch || inj.element >= N))
+        return TFFT_EINVAL;
+    const bool may_alloc = !capturing(stream);
     const Tuning tu = get_tuning(precision, N);
+    int rc;
     if (precision == TFFT_FP32)
-        rc = launch_transform<float2>(*e, *tb, x, y, batch, dir, scale, counts, tu, inj, stream);
+        rc = transform<float2>(rt, x, y, N, batch, dir, scale, counts, tu, inj, stream, may_alloc);
     else
-        rc = launch_transform<double2>(*e, *tb, x, y, batch, dir, scale, counts, tu, inj, stream);
+        rc = transform<double2>(rt, x, y, N, batch, dir, scale, counts, tu, inj, stream, may_alloc);
     if (rc == TFFT_OK) g_inj = Inject{};   // one-shot
     return rc;
 }

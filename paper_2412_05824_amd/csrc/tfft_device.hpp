@@ -159,35 +159,55 @@ template <bool BLOCK> __device__ __forceinline__ void lds_sync() {
     else wave_lds_sync();
 }
 
-// XOR swizzle on the element index: rows of 2^B elements, the column is XORed
-// with the row number so strided accesses of one wavefront spread over all
-// banks without padding.  Stays inside the row, so any region whose size is a
-// multiple of 2^B maps onto itself.
-template <int B> __device__ __forceinline__ int swz(int g) {
-    return g ^ ((g >> B) & ((1 << B) - 1));
-}
+// Padded LDS index: one spare element after every 2^B elements (a 128-byte
+// row), so that lanes writing with a stride of 2^B elements hit distinct
+// banks.  Strides that are multiples of 2^B stay compile-time offsets.
+template <int B> __device__ __forceinline__ int pad_idx(int g) { return g + (g >> B); }
+template <int B> constexpr int padded_size(int n) { return n + (n >> B) + 1; }
 
 // ---------------------------------------------------------------------------
-// Reductions over aligned groups of W lanes (W a power of two <= 64).
+// Cross-lane exchange v[lane ^ X] inside a wave, on the VALU where possible:
+// DPP quad permutes for X = 1, 2; ds_swizzle (bit-mask mode, no LDS memory
+// access) for X = 4, 8, 16; ds_bpermute only for X = 32.
 // ---------------------------------------------------------------------------
-template <int W, class T> __device__ __forceinline__ T group_sum(T v) {
-#pragma unroll
-    for (int off = W / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
-    return v;
+template <int X> __device__ __forceinline__ int xor_lane_i32(int v) {
+    static_assert(X == 1 || X == 2 || X == 4 || X == 8 || X == 16 || X == 32, "xor offset");
+    if constexpr (X == 1) return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+    else if constexpr (X == 2) return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false); // quad_perm [2,3,0,1]
+    else if constexpr (X < 32) return __builtin_amdgcn_ds_swizzle(v, (X << 10) | 0x1F);  // lane ^ X within 32
+    else return __builtin_amdgcn_ds_bpermute((int)((__lane_id() ^ 32u) << 2), v);
 }
-template <int W> __device__ __forceinline__ unsigned group_or(unsigned v) {
-#pragma unroll
-    for (int off = W / 2; off >= 1; off >>= 1) v |= (unsigned)__shfl_xor((int)v, off, kWave);
-    return v;
+template <int X> __device__ __forceinline__ float xor_lane(float v) {
+    return __int_as_float(xor_lane_i32<X>(__float_as_int(v)));
 }
-template <int W, class T> __device__ __forceinline__ T group_max(T v) {
-#pragma unroll
-    for (int off = W / 2; off >= 1; off >>= 1) {
-        T o = __shfl_xor(v, off, kWave);
-        v = (o > v || o != o) ? o : v;   // NaN propagates
+template <int X> __device__ __forceinline__ double xor_lane(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = xor_lane_i32<X>((int)(b & 0xffffffffll));
+    const int hi = xor_lane_i32<X>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+template <int X> __device__ __forceinline__ unsigned xor_lane(unsigned v) {
+    return (unsigned)xor_lane_i32<X>((int)v);
+}
+
+// v op v[lane ^ X] for X = FROM, 2 FROM, ..., < TO (powers of two).  Every
+// step pairs two lanes that combine the same two values, so all lanes of a
+// group end with bit-identical results.
+template <int FROM, int TO, class Op, class T> __device__ __forceinline__ T xor_reduce(T v) {
+    if constexpr (FROM < TO) {
+        v = Op::f(v, xor_lane<FROM>(v));
+        return xor_reduce<FROM * 2, TO, Op>(v);
+    } else {
+        return v;
     }
-    return v;
 }
+
+struct OpAdd {
+    template <class T> __device__ __forceinline__ static T f(T a, T b) { return a + b; }
+};
+struct OpOr {
+    __device__ __forceinline__ static unsigned f(unsigned a, unsigned b) { return a | b; }
+};
 
 template <class T> __device__ __forceinline__ bool finite_le(T v, T cap) {
     return __builtin_fabs(v) <= cap;   // false for NaN and +-Inf

@@ -1,29 +1,46 @@
 // tfft_kernels.hpp -- batched C2C FFT kernels with fused two-side ABFT (gfx950).
 //
 // Structure (TurboFFT Sec. 3.1, Fig. 3, re-designed for CDNA4):
-//   * a "slot" is the set of P = N/E lanes that transform one signal per
-//     transaction, E elements per lane held in registers;
+//   * a "slot" is the set of P = Ns/E lanes that transform one (sub-)signal of
+//     length Ns per transaction, E elements per lane held in registers;
 //   * lane t of a slot holds elements t + P*r (r < E) before and after every
-//     stage, so HBM loads/stores and LDS reads are unit-stride across lanes;
+//     stage, so global loads/stores and LDS reads are unit-stride across lanes;
 //   * stage s (radix R, L = product of the earlier radices) is a Stockham
-//     autosort step: butterfly beta = t + i*P reads elements beta + j*N/R,
+//     autosort step: butterfly beta = t + i*P reads elements beta + j*Ns/R,
 //     multiplies by w_{LR}^{j k} (k = beta mod L, from a precomputed table,
-//     Sec. 3.1 "avoid FP64 trigonometric functions"), applies the radix-R DFT
-//     in registers and writes output j to g*L*R + k + j*L (g = beta div L);
-//   * stages exchange data through LDS with an XOR swizzle instead of padding
-//     (Sec. 3.2); slots of at most one wavefront synchronise with wavefront
-//     fences only, larger slots use workgroup barriers;
-//   * a slot runs T transactions back to back (Sec. 4.3 multi-transaction).
+//     Sec. 3.1: no trigonometric functions in the kernel), applies the radix-R
+//     DFT in registers and writes output j to g*L*R + k + j*L (g = beta div L);
+//   * stages exchange data through LDS (Sec. 3.2); a slot runs T transactions
+//     back to back (Sec. 4.3 multi-transaction).
+// Three geometries share that machinery:
+//   * Single : one whole signal per slot; slots of at most a wavefront sit
+//     side by side in a wave (lane = slot*P + t) and synchronise with
+//     wavefront fences; LDS rows of 128 bytes carry one pad element, which
+//     keeps strided stores conflict-free and every address a base register
+//     plus a compile-time offset;
+//   * ColPass: pass A of N = N1*N2, column FFTs of length N1 (stride N2),
+//     C adjacent columns per workgroup (lane = t*C + c), so every global
+//     access moves C*S contiguous bytes and the LDS tile [m][c] is
+//     conflict-free without padding (Sec. 3.2: lanes of a wave own different
+//     sub-signals);
+//   * RowPass: pass B, row FFTs of length N2 of the pass-A result multiplied
+//     by w_N^{n2 k1}, C adjacent rows per workgroup, outputs written at
+//     k1 + N1*k2 (the reorganised last-stage store of Sec. 5.1.2, coalesced
+//     over the C rows).
 //
-// Two-side ABFT (Sec. 4.1-4.3), per slot and group of T transactions:
-//   right side  x_s = sum_b x_b,  y_s = sum_b y_b          (X e_c, Y e_c)
-//   location    xw_s = sum_b (b+1) x_b,  q_b = e^T y_b      (e_3 weights)
-//   left side   s_in = (e^T W) x_s, l_in = (e^T W) xw_s,
-//               s_out = e^T y_s,   l_out = sum_b (b+1) q_b
-//   D0 = s_out - s_in detects, D1/D0 - 1 locates, c = W x_s - y_s corrects.
-// Linearity lets the left encoding of the inputs run once per group on the
-// right-side sums instead of once per element; e_k = w_M^k takes only M
-// values, so e^T y needs M bucket sums per lane and no table.
+// Two-side ABFT (Sec. 4.1-4.3), per slot and group of T transactions, e_k =
+// w_M^k (M = 3, or 5 when 3 | Ns) and a = e^T W of the sub-length:
+//   per transaction b: p_b = a^T x_b (input, a from LDS), q_b = e^T y_b
+//   (output, M bucket sums), x_s += x_b (right-side checksum X e, kept in
+//   registers: the inputs "compressed" into registers);
+//   group close: D0 = sum q_b - sum p_b detects, D1 = sum (b+1)(q_b - p_b)
+//   locates (location encoding), c = W x_s - Y e corrects the located
+//   signal (delayed batched correction).  Y e is summed from the group's
+//   stored outputs on the error path only.
+// In the row pass the left vector becomes a_n * w_N^{n k1} applied to the raw
+// loaded values and x_s sums the raw values, so the inter-pass twiddle
+// multiply is covered as well; all transactions of a row-pass group share
+// the row k1 (they run over consecutive signals).
 #pragma once
 
 #include "tfft_device.hpp"
@@ -34,44 +51,62 @@ struct FtCounts {   // mirrors tfft_ft_counts in the public header
     unsigned long long detected, corrected, rebuilt, uncorrectable, last_signal, reserved[3];
 };
 
+enum Kind { kSingle = 0, kColPass = 1, kRowPass = 2 };
+
 // Kernel arguments shared by all transform kernels.
 template <class V> struct KArgs {
     using R = typename RealOf<V>::type;
-    const V* tw;          // stage twiddle tables, concatenated
-    const V* left;        // e^T W for the transform length (ABFT only)
+    const V* tw;          // stage twiddle tables of the sub-length, concatenated
+    const V* left;        // e^T W of the sub-length (ABFT only)
+    const V* tw_hi;       // row pass: w_N^m = tw_hi[m >> tw_bits] * tw_lo[m & mask]
+    const V* tw_lo;
+    int tw_bits;
     long long batch;      // number of signals
+    long long N;          // full transform length (signal stride in elements)
+    int N1, N2;           // two-pass split, N = N1 * N2
     int T;                // transactions (signals) per slot
-    int conj;             // 1: conjugate on load and store (inverse direction)
+    int conj_in;          // 1: conjugate loaded values (inverse direction, first pass)
+    int conj_out;         // 1: conjugate stored values (inverse direction, last pass)
     R scale;              // applied to every stored value
-    R tau_coef;           // kappa * u * sqrt(N log2 N); tau = tau_coef * sqrt(nu)
+    long long sig_base;   // global index of local signal 0 (counters only)
+    R tau_coef;           // kappa * u * sqrt(Ns log2 Ns); tau = tau_coef * sqrt(nu)
     R cap;                // magnitude cap: larger outputs mark their signal corrupted
     FtCounts* counts;     // device counters (ABFT only)
     long long inj_signal; // signal to corrupt (-1: none)
-    int inj_elem;         // output element index
+    long long inj_elem;   // element index in this kernel's output numbering
     int inj_part;         // 0 real, 1 imaginary
     int inj_bit;          // bit to flip
     int stats;            // 1: record max |D0| / tau over groups (calibration)
-    int x_intact;         // 1: out of place, inputs can be re-read on the error path
+    int x_intact;         // 1: inputs can be re-read on the error path
+    int tiles;            // workgroups per signal group (tile geometries)
 };
 
-// Compile-time plan: length N, E elements per lane, WPB waves per workgroup,
-// swizzle row 2^B, stage radices Rs...
-template <int N_, int E_, int WPB_, int B_, int... Rs> struct Plan {
-    static constexpr int N = N_;
+// Compile-time plan: kind, sub-length Ns, E elements per lane, WC = waves per
+// workgroup (single geometry) or sub-signals per workgroup (tile
+// geometries), padded LDS row of 2^B elements (single geometry), stage
+// radices Rs...
+template <int KIND_, int Ns_, int E_, int WC_, int B_, int... Rs> struct Plan {
+    static constexpr int KIND = KIND_;
+    static constexpr int Ns = Ns_;
     static constexpr int E = E_;
-    static constexpr int P = N / E;                       // lanes per slot
-    static constexpr bool MULTI_WAVE = P > kWave;         // slot spans waves
-    static constexpr int WPB = MULTI_WAVE ? P / kWave : WPB_;
-    static constexpr int THREADS = WPB * kWave;
-    static constexpr int SPW = MULTI_WAVE ? 1 : kWave / P;  // slots per wave
-    static constexpr int SLOTS = MULTI_WAVE ? 1 : WPB * SPW; // slots per workgroup
+    static constexpr int P = Ns / E;                           // lanes per slot
+    static constexpr bool TILE = KIND != kSingle;
+    static constexpr int C = TILE ? WC_ : 1;                    // sub-signals per tile
+    static constexpr int THREADS = TILE ? P * C : (P > kWave ? P : WC_ * kWave);
+    static constexpr bool MULTI_WAVE = THREADS > kWave && (TILE || P > kWave);
+    static constexpr int WAVES = THREADS >= kWave ? THREADS / kWave : 1;
+    static constexpr int SPW = (!TILE && P <= kWave) ? kWave / P : 1;   // slots per wave
+    static constexpr int SLOTS = TILE ? C : (P > kWave ? 1 : WAVES * SPW);
     static constexpr int B = B_;
-    static constexpr int LDS_ELEMS = MULTI_WAVE ? N : WPB * SPW * N;
-    static constexpr int M = (N % 3 == 0) ? 5 : 3;         // encoding period
-    static_assert(N % E == 0, "E must divide N");
-    static_assert(MULTI_WAVE ? (P % kWave == 0) : (kWave % P == 0), "slot must tile waves");
-    static_assert(((Rs * ...) == N), "radices must multiply to N");
+    static constexpr int LDS_DATA = TILE ? Ns * C : padded_size<B_>(P > kWave ? Ns : WAVES * SPW * Ns);
+    static constexpr int M = (Ns % 3 == 0) ? 5 : 3;            // encoding period
+    static_assert(Ns % E == 0, "E must divide Ns");
+    static_assert(((Rs * ...) == Ns), "radices must multiply to Ns");
     static_assert(((E % Rs == 0) && ...), "every radix must divide E");
+    static_assert(THREADS <= 1024, "workgroup too large");
+    static_assert(!TILE || THREADS % kWave == 0, "tile workgroups are whole waves");
+    static_assert(!TILE || (kWave % C == 0), "tile width divides a wave");
+    static_assert(TILE || (P > kWave ? P % kWave == 0 : kWave % P == 0), "slot must tile waves");
 };
 
 // Bit flip of one component (fault injection, Sec. 5.3 protocol).
@@ -83,12 +118,24 @@ __device__ __forceinline__ double flip_bit(double v, int bit) {
 }
 
 // ---------------------------------------------------------------------------
+// LDS index maps.
+// ---------------------------------------------------------------------------
+template <int B> struct LdsPad {   // one signal per region, one pad element per 2^B
+    int off;
+    __device__ __forceinline__ int operator()(int m) const { return pad_idx<B>(off + m); }
+};
+template <int C> struct LdsCol {    // tile [m][c]: C sub-signals interleaved
+    int c;
+    __device__ __forceinline__ int operator()(int m) const { return m * C + c; }
+};
+
+// ---------------------------------------------------------------------------
 // One Stockham stage.  LAST: results stay in registers (output layout),
 // otherwise they go to LDS at their autosorted positions.
 // ---------------------------------------------------------------------------
-template <class V, int E, int P, int N, int R, int L, bool LAST, int B>
+template <class V, int E, int P, int R, int L, bool LAST, class LI>
 __device__ __forceinline__ void stockham_stage(V (&reg)[E], const V* __restrict__ tw_s, int t,
-                                               V* __restrict__ lds, int lds_off) {
+                                               V* __restrict__ lds, const LI& li) {
     constexpr int NB = E / R;
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
@@ -107,37 +154,29 @@ __device__ __forceinline__ void stockham_stage(V (&reg)[E], const V* __restrict_
 #pragma unroll
             for (int j = 0; j < R; ++j) reg[i + j * NB] = v[j];
         } else {
-            const int base = lds_off + (beta / L) * (L * R) + k;
+            const int base = (beta / L) * (L * R) + k;
 #pragma unroll
-            for (int j = 0; j < R; ++j) lds[swz<B>(base + j * L)] = v[j];
+            for (int j = 0; j < R; ++j) lds[li(base + j * L)] = v[j];
         }
     }
 }
 
 // All stages of one in-slot FFT.  reg holds elements t + P*r on entry and the
-// transform's outputs t + P*r on exit.
-template <class V, int E, int P, int N, int B, bool BLOCK, int L, int R, int... Rest>
+// transform's outputs t + P*r on exit.  Stage s's table holds L_s * R_s
+// entries and the tables follow each other.
+template <class V, int E, int P, bool BLOCK, class LI, int L, int R, int... Rest>
 __device__ __forceinline__ void slot_fft(V (&reg)[E], const V* __restrict__ tw, int t,
-                                         V* __restrict__ lds, int lds_off) {
+                                         V* __restrict__ lds, const LI& li) {
     constexpr bool LAST = sizeof...(Rest) == 0;
-    stockham_stage<V, E, P, N, R, L, LAST, B>(reg, tw, t, lds, lds_off);
+    stockham_stage<V, E, P, R, L, LAST>(reg, tw, t, lds, li);
     if constexpr (!LAST) {
         lds_sync<BLOCK>();
 #pragma unroll
-        for (int r = 0; r < E; ++r) reg[r] = lds[swz<B>(lds_off + t + P * r)];
+        for (int r = 0; r < E; ++r) reg[r] = lds[li(t + P * r)];
         lds_sync<BLOCK>();
-        // the next stage's table follows this one: L*R entries
-        slot_fft<V, E, P, N, B, BLOCK, L * R, Rest...>(reg, tw + L * R, t, lds, lds_off);
+        slot_fft<V, E, P, BLOCK, LI, L * R, Rest...>(reg, tw + L * R, t, lds, li);
     }
 }
-
-template <class V, class PL, int... Rs> struct SlotFFT {
-    __device__ __forceinline__ static void run(V (&reg)[PL::E], const V* tw, int t, V* lds,
-                                               int lds_off) {
-        // stage 0 has L = 1 and reads no twiddles; its table slot holds R0 entries
-        slot_fft<V, PL::E, PL::P, PL::N, PL::B, PL::MULTI_WAVE, 1, Rs...>(reg, tw, t, lds, lds_off);
-    }
-};
 
 // w_M^j for the encoding vector e_k = w_M^k, w_M = exp(-2 pi i / M)
 template <class V, int M> __device__ __forceinline__ V wM(int j) {
@@ -177,155 +216,240 @@ template <class V, int E, int P, int M> __device__ __forceinline__ V encode_out(
     return acc;
 }
 
-// Reduce K values (sum) over one slot.  Single-wave slots use lane shuffles
-// (an XOR butterfly leaves bit-identical results on every lane); multi-wave
-// slots add one pass through LDS, which the caller must not be using.
-template <class PL, class R, int K>
-__device__ __forceinline__ void slot_sum(R (&v)[K], R* scratch /* K * WPB */) {
-    if constexpr (!PL::MULTI_WAVE) {
-#pragma unroll
-        for (int i = 0; i < K; ++i) v[i] = group_sum<PL::P>(v[i]);
-    } else {
-#pragma unroll
-        for (int i = 0; i < K; ++i) v[i] = group_sum<kWave>(v[i]);
-        const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-        __syncthreads();
-        if (lane == 0) {
-#pragma unroll
-            for (int i = 0; i < K; ++i) scratch[i * PL::WPB + wave] = v[i];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < K; ++i) {
-            R s = 0;
-#pragma unroll
-            for (int w = 0; w < PL::WPB; ++w) s += scratch[i * PL::WPB + w];
-            v[i] = s;
-        }
-        __syncthreads();
-    }
-}
-
-template <class PL> __device__ __forceinline__ unsigned slot_or(unsigned v, unsigned* scratch) {
-    if constexpr (!PL::MULTI_WAVE) {
-        return group_or<PL::P>(v);
-    } else {
-        v = group_or<kWave>(v);
-        const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-        __syncthreads();
-        if (lane == 0) scratch[wave] = v;
-        __syncthreads();
-        unsigned o = 0;
-#pragma unroll
-        for (int w = 0; w < PL::WPB; ++w) o |= scratch[w];
-        __syncthreads();
-        return o;
-    }
-}
-
-template <class PL, class R> __device__ __forceinline__ R slot_max(R v, R* scratch) {
-    if constexpr (!PL::MULTI_WAVE) {
-        return group_max<PL::P>(v);
-    } else {
-        v = group_max<kWave>(v);
-        const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-        __syncthreads();
-        if (lane == 0) scratch[wave] = v;
-        __syncthreads();
-        R m = scratch[0];
-#pragma unroll
-        for (int w = 1; w < PL::WPB; ++w) m = (scratch[w] > m || scratch[w] != scratch[w]) ? scratch[w] : m;
-        __syncthreads();
-        return m;
-    }
-}
-
-// Is any lane of the synchronisation domain flagging?  Multi-wave slots take
-// their decisions from workgroup-wide reductions, so the flag is uniform.
-template <class PL> __device__ __forceinline__ bool domain_any(bool f) {
-    if constexpr (!PL::MULTI_WAVE) return __any(f) != 0;
-    else return f;
-}
-
 template <class R> __device__ __forceinline__ bool cfin(R x, R y, R cap) {
     return finite_le(x, cap) && finite_le(y, cap);
 }
 
 // ---------------------------------------------------------------------------
-// Single-pass batched kernel.  FT: 0 off, 1 detect (one-side check plus
-// location), 2 correct (two-side, delayed batched correction at group close).
+// Geometry: lane -> (slot, t), addressing, reductions over a slot.
 // ---------------------------------------------------------------------------
-template <class V, class PL, int FT, int... Rs>
-__global__ __launch_bounds__(PL::THREADS) void k_single(const V* __restrict__ x, V* __restrict__ y,
-                                                        KArgs<V> a) {
+template <class V, class PL> struct Geo {
     using R = typename RealOf<V>::type;
-    constexpr int N = PL::N, E = PL::E, P = PL::P, M = PL::M;
-    __shared__ V lds[PL::LDS_ELEMS];
-
-    const int lane = threadIdx.x % kWave;
-    const int wave = threadIdx.x / kWave;
-    int t, lds_off;
+    static constexpr int E = PL::E, P = PL::P, Ns = PL::Ns, C = PL::C;
+    static constexpr bool BLOCK = PL::MULTI_WAVE;
+    int t;               // position in the slot
+    int slot;            // slot within the workgroup (column / row of a tile)
     long long sig0;      // signal of transaction 0
     long long sig_step;  // signal stride between transactions
-    if constexpr (PL::MULTI_WAVE) {
-        t = threadIdx.x;
-        lds_off = 0;
-        sig0 = (long long)blockIdx.x * a.T;
-        sig_step = 1;
-    } else {
-        const int sigma = lane / P;
-        t = lane % P;
-        lds_off = (wave * PL::SPW + sigma) * N;
-        sig0 = ((long long)blockIdx.x * PL::WPB + wave) * a.T * PL::SPW + sigma;
-        sig_step = PL::SPW;
+    int line;            // tiles: column n2 (pass A) or row k1 (pass B)
+    int lds_off;         // single: start of the slot's LDS region
+    int par = 0;         // which half of the reduction scratch the next reduce uses
+
+    __device__ __forceinline__ Geo(const KArgs<V>& a) {
+        const int tid = threadIdx.x;
+        if constexpr (PL::KIND == kSingle) {
+            const int lane = tid % kWave, wave = tid / kWave;
+            if constexpr (P > kWave) {
+                t = tid;
+                slot = 0;
+                lds_off = 0;
+                sig0 = (long long)blockIdx.x * a.T;
+                sig_step = 1;
+            } else {
+                const int sigma = lane / P;
+                t = lane % P;
+                slot = wave * PL::SPW + sigma;
+                lds_off = slot * Ns;
+                sig0 = ((long long)blockIdx.x * PL::WAVES + wave) * a.T * PL::SPW + sigma;
+                sig_step = PL::SPW;
+            }
+            line = 0;
+        } else {
+            t = tid / C;
+            slot = tid % C;
+            lds_off = 0;
+            const long long bid = blockIdx.x;
+            const long long tile = bid % a.tiles;   // tiles of one signal group are consecutive
+            const long long grp = bid / a.tiles;
+            line = (int)(tile * C + slot);
+            sig0 = grp * a.T;
+            sig_step = 1;
+        }
+    }
+    __device__ __forceinline__ long long sig(int b) const { return sig0 + (long long)b * sig_step; }
+    // element offsets of input element m / output element k of signal s
+    __device__ __forceinline__ long long in_off(const KArgs<V>& a, long long s, int m) const {
+        if constexpr (PL::KIND == kSingle) return s * Ns + m;
+        else if constexpr (PL::KIND == kColPass) return s * a.N + (long long)m * a.N2 + line;
+        else return s * a.N + (long long)line * a.N2 + m;
+    }
+    __device__ __forceinline__ long long out_off(const KArgs<V>& a, long long s, int k) const {
+        if constexpr (PL::KIND == kSingle) return s * Ns + k;
+        else if constexpr (PL::KIND == kColPass) return s * a.N + (long long)k * a.N2 + line;
+        else return s * a.N + line + (long long)a.N1 * k;
+    }
+    // is output element k of this slot the injected one (this kernel's numbering)?
+    __device__ __forceinline__ bool inj_hit(const KArgs<V>& a, int k) const {
+        if constexpr (PL::KIND == kSingle) return k == a.inj_elem;
+        else if constexpr (PL::KIND == kColPass) return (long long)k * a.N2 + line == a.inj_elem;
+        else return line + (long long)a.N1 * k == a.inj_elem;
+    }
+    __device__ __forceinline__ auto lidx() const {
+        if constexpr (PL::KIND == kSingle) return LdsPad<PL::B>{lds_off};
+        else return LdsCol<C>{slot};
+    }
+    // row pass: w_N^{n k1} for sub-signal element n (two table values, one product)
+    __device__ __forceinline__ V twiddle(const KArgs<V>& a, int n) const {
+        if constexpr (PL::KIND == kRowPass) {
+            const unsigned m = (unsigned)n * (unsigned)line;   // n < N2, k1 < N1: m < N
+            const V hi = a.tw_hi[m >> a.tw_bits];
+            const V lo = a.tw_lo[m & ((1u << a.tw_bits) - 1u)];
+            return cmul(hi, lo);
+        } else {
+            return V{(R)1, (R)0};
+        }
+    }
+
+    // reduce K values over the slot with Op; the result is bit-identical on
+    // every lane of the slot (XOR butterflies, then one ordered pass over the
+    // per-wave partials in LDS).  scratch holds 2 * K * WAVES * C values of T.
+    template <class Op, int K, class T> __device__ __forceinline__ void reduce(T (&v)[K], T* scratch) {
+        if constexpr (PL::KIND == kSingle) {
+            constexpr int W = P < kWave ? P : kWave;
+#pragma unroll
+            for (int i = 0; i < K; ++i) v[i] = xor_reduce<1, W, Op>(v[i]);
+            if constexpr (P > kWave) {
+                // two alternating halves: a half is rewritten only after the
+                // barrier of the next reduction, when all its readers are done
+                const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+                T* sc = scratch + par * (K * PL::WAVES);
+                par ^= 1;
+                if (lane == 0) {
+#pragma unroll
+                    for (int i = 0; i < K; ++i) sc[i * PL::WAVES + wave] = v[i];
+                }
+                __syncthreads();
+#pragma unroll
+                for (int i = 0; i < K; ++i) {
+                    T s = sc[i * PL::WAVES];
+#pragma unroll
+                    for (int w = 1; w < PL::WAVES; ++w) s = Op::f(s, sc[i * PL::WAVES + w]);
+                    v[i] = s;
+                }
+            }
+        } else {
+            // lanes t*C + c: XOR over the t bits inside a wave, then across waves
+            constexpr int TW = (kWave / C) < P ? (kWave / C) : P;   // t values per wave
+#pragma unroll
+            for (int i = 0; i < K; ++i) v[i] = xor_reduce<C, C * TW, Op>(v[i]);
+            if constexpr (PL::MULTI_WAVE) {
+                const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+                T* sc = scratch + par * (K * PL::WAVES * C);
+                par ^= 1;
+                if (lane < C) {
+#pragma unroll
+                    for (int i = 0; i < K; ++i) sc[(i * PL::WAVES + wave) * C + lane] = v[i];
+                }
+                __syncthreads();
+#pragma unroll
+                for (int i = 0; i < K; ++i) {
+                    T s = sc[(i * PL::WAVES) * C + slot];
+#pragma unroll
+                    for (int w = 1; w < PL::WAVES; ++w) s = Op::f(s, sc[(i * PL::WAVES + w) * C + slot]);
+                    v[i] = s;
+                }
+            }
+        }
+    }
+    // any lane of the synchronisation domain (wave or workgroup)
+    __device__ __forceinline__ bool domain_any(bool f) const {
+        if constexpr (BLOCK) return __syncthreads_or(f ? 1 : 0) != 0;
+        else return __any(f ? 1 : 0) != 0;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// The transform kernel.  FT: 0 off, 1 detect (one-side check with location),
+// 2 correct (two-side check, location and delayed batched correction; the
+// right-side input sum is formed again from the intact inputs on the error
+// path), 3 correct in place (the right-side input sum X e stays in registers
+// through the group, because the outputs overwrite the inputs).
+// ---------------------------------------------------------------------------
+template <class V, class PL, int FT, int... Rs>
+__global__ __launch_bounds__(PL::THREADS) void k_fft(const V* __restrict__ x, V* __restrict__ y,
+                                                     KArgs<V> a) {
+    using R = typename RealOf<V>::type;
+    constexpr int E = PL::E, P = PL::P, M = PL::M, Ns = PL::Ns;
+    constexpr bool BLOCK = PL::MULTI_WAVE;
+    constexpr int NRED = 6;
+    constexpr int RED = 2 * (PL::TILE ? PL::C : 1) * PL::WAVES * NRED;
+    __shared__ V lds[PL::LDS_DATA];
+    __shared__ V a_lds[FT ? Ns : 1];
+    __shared__ R red[FT ? RED : 1];
+
+    Geo<V, PL> g(a);
+    const auto li = g.lidx();
+    constexpr bool KEEP_XS = FT == 3;   // in place: inputs are gone after the store
+    const int t = g.t;
+
+    if constexpr (FT != 0) {
+        for (int n = threadIdx.x; n < Ns; n += PL::THREADS) a_lds[n] = a.left[n];
+        __syncthreads();
     }
 
     V reg[E];
-    V xs[FT ? E : 1], xw[FT ? E : 1], ys[FT == 2 ? E : 1];
-    V lq = V{0, 0};        // sum_b (b+1) q_b
-    V sq = V{0, 0};        // sum_b q_b
-    R nu = 0;              // input energy
-    unsigned nfmask = 0;   // transactions with a non-finite / oversized output
-    if constexpr (FT != 0) {
+    V xs[KEEP_XS ? E : 1];
+    V ps = V{0, 0}, pw = V{0, 0};   // sum_b p_b, sum_b (b+1) p_b
+    V qs = V{0, 0}, qw = V{0, 0};   // sum_b q_b, sum_b (b+1) q_b
+    R nu = 0;                        // input energy of the group
+    unsigned nfmask = 0;             // transactions with a non-finite / oversized output
+    if constexpr (KEEP_XS) {
 #pragma unroll
-        for (int r = 0; r < E; ++r) xs[r] = xw[r] = V{0, 0};
-    }
-    if constexpr (FT == 2) {
-#pragma unroll
-        for (int r = 0; r < E; ++r) ys[r] = V{0, 0};
+        for (int r = 0; r < E; ++r) xs[r] = V{0, 0};
     }
 
     for (int b = 0; b < a.T; ++b) {
-        const long long sig = sig0 + (long long)b * sig_step;
-        const bool valid = sig < a.batch;
-        const V* xin = x + sig * N;
+        const long long s = g.sig(b);
+        const bool valid = s < a.batch;
+        // Opaque copies of the lane's coordinates: address arithmetic is
+        // recomputed inside each transaction instead of being hoisted into
+        // dozens of loop-invariant registers.
+        int t = g.t;
+        asm volatile("" : "+v"(t));
+        auto li = g.lidx();
+        asm volatile("" : "+v"(li));
         if (valid) {
 #pragma unroll
-            for (int r = 0; r < E; ++r) reg[r] = xin[t + P * r];
+            for (int r = 0; r < E; ++r) reg[r] = x[g.in_off(a, s, t + P * r)];
         } else {
 #pragma unroll
             for (int r = 0; r < E; ++r) reg[r] = V{0, 0};
         }
-        if (a.conj) {
+        if (a.conj_in) {
 #pragma unroll
             for (int r = 0; r < E; ++r) reg[r].y = -reg[r].y;
         }
-        if constexpr (FT != 0) {
+        {
             const R wb = (R)(b + 1);
+            V p = V{0, 0};
 #pragma unroll
             for (int r = 0; r < E; ++r) {
-                xs[r] = cadd(xs[r], reg[r]);
-                xw[r] = V{xw[r].x + wb * reg[r].x, xw[r].y + wb * reg[r].y};
-                nu += reg[r].x * reg[r].x + reg[r].y * reg[r].y;
+                const V z = reg[r];   // raw loaded value
+                V tw = V{(R)1, (R)0};
+                if constexpr (PL::KIND == kRowPass) {
+                    tw = g.twiddle(a, t + P * r);
+                    reg[r] = cmul(z, tw);
+                }
+                if constexpr (FT != 0) {
+                    V av = a_lds[t + P * r];
+                    if constexpr (PL::KIND == kRowPass) av = cmul(av, tw);
+                    p = cadd(p, cmul(av, z));
+                    nu += z.x * z.x + z.y * z.y;
+                    if constexpr (KEEP_XS) xs[r] = cadd(xs[r], z);
+                }
+            }
+            if constexpr (FT != 0) {
+                ps = cadd(ps, p);
+                pw = V{pw.x + wb * p.x, pw.y + wb * p.y};
             }
         }
 
-        SlotFFT<V, PL, Rs...>::run(reg, a.tw, t, lds, lds_off);
+        slot_fft<V, E, P, BLOCK, decltype(li), 1, Rs...>(reg, a.tw, t, lds, li);
 
-        if (sig == a.inj_signal) {   // test hook: one bit flip in one output value
+        if (s == a.inj_signal) {   // test hook: one bit flip in one output value
 #pragma unroll
             for (int r = 0; r < E; ++r) {
-                if (t + P * r == a.inj_elem) {
+                if (g.inj_hit(a, t + P * r)) {
                     if (a.inj_part == 0) reg[r].x = flip_bit(reg[r].x, a.inj_bit);
                     else reg[r].y = flip_bit(reg[r].y, a.inj_bit);
                 }
@@ -335,181 +459,222 @@ __global__ __launch_bounds__(PL::THREADS) void k_single(const V* __restrict__ x,
         if constexpr (FT != 0) {
             const V q = encode_out<V, E, P, M>(reg);
             const R wb = (R)(b + 1);
-            sq = cadd(sq, q);
-            lq = V{lq.x + wb * q.x, lq.y + wb * q.y};
+            qs = cadd(qs, q);
+            qw = V{qw.x + wb * q.x, qw.y + wb * q.y};
             if (!cfin(q.x, q.y, a.cap)) nfmask |= 1u << b;
-        }
-        if constexpr (FT == 2) {
-#pragma unroll
-            for (int r = 0; r < E; ++r) ys[r] = cadd(ys[r], reg[r]);
         }
 
         if (valid) {
-            V* yout = y + sig * N;
 #pragma unroll
             for (int r = 0; r < E; ++r) {
                 V v = reg[r];
-                if (a.conj) v.y = -v.y;
-                yout[t + P * r] = V{v.x * a.scale, v.y * a.scale};
+                if (a.conj_out) v.y = -v.y;
+                y[g.out_off(a, s, t + P * r)] = V{v.x * a.scale, v.y * a.scale};
             }
         }
     }
 
     if constexpr (FT != 0) {
-        // ---- group close: left-side checksums from the right-side sums ----
-        __shared__ R red[9 * PL::WPB];
-        V sin_ = V{0, 0}, lin = V{0, 0};
-#pragma unroll
-        for (int r = 0; r < E; ++r) {
-            const V av = a.left[t + P * r];
-            sin_ = cadd(sin_, cmul(av, xs[r]));
-            lin = cadd(lin, cmul(av, xw[r]));
-        }
+        // ---- group close: reduce the checksum differences over the slot ----
         const V lanef = wM<V, M>(t % M);   // e_{t + P r} = w_M^t w_M^{P r}
-        const V sout = cmul(lanef, sq);
-        const V lout = cmul(lanef, lq);
-        R v[9] = {sin_.x, sin_.y, lin.x, lin.y, sout.x, sout.y, lout.x, lout.y, nu};
-        slot_sum<PL>(v, red);
-        const unsigned nf = slot_or<PL>(nfmask, reinterpret_cast<unsigned*>(red));
+        const V dd0 = csub(cmul(lanef, qs), ps);   // this lane's share of D0
+        const V dd1 = csub(cmul(lanef, qw), pw);   // and of D1
+        const R nfc = (R)__builtin_popcount(nfmask);
+        V D0, D1;
+        R nu_s, nf_count;
+        if (a.T == 1) {   // one transaction: D1 = D0, no location needed
+            R v[4] = {dd0.x, dd0.y, nu, nfc};
+            g.template reduce<OpAdd>(v, red);
+            D0 = V{v[0], v[1]};
+            D1 = D0;
+            nu_s = v[2];
+            nf_count = v[3];
+        } else {
+            R v[6] = {dd0.x, dd0.y, dd1.x, dd1.y, nu, nfc};
+            g.template reduce<OpAdd>(v, red);
+            D0 = V{v[0], v[1]};
+            D1 = V{v[2], v[3]};
+            nu_s = v[4];
+            nf_count = v[5];
+        }
+        unsigned nf = 0;
+        if (nf_count > (R)0) {   // rare: which transactions held a non-finite output
+            unsigned nfv[1] = {nfmask};
+            g.template reduce<OpOr>(nfv, reinterpret_cast<unsigned*>(red));
+            nf = nfv[0];
+        }
 
         // decision, identical on every lane of the slot:
         // 0 clean or unchecked, 1 add the correction, 2 rebuild, 3 uncorrectable
         int action = 0, bstar = -1;
-        const V D0 = V{v[4] - v[0], v[5] - v[1]};
-        const V D1 = V{v[6] - v[2], v[7] - v[3]};
-        const R nu_s = v[8];
         const R tau = a.tau_coef * __builtin_sqrt(nu_s);
         const bool checked = (nu_s == nu_s) && nu_s < (R)INFINITY;
+        const R d0 = __builtin_sqrt(D0.x * D0.x + D0.y * D0.y);
         if (checked) {
             if (nf != 0) {
                 if ((nf & (nf - 1)) != 0) action = 3;
                 else { bstar = __builtin_ctz(nf); action = 2; }
-            } else if (!(__builtin_sqrt(D0.x * D0.x + D0.y * D0.y) <= tau)) {
+            } else if (!(d0 <= tau)) {
                 const R den = D0.x * D0.x + D0.y * D0.y;
                 const R rr = (D1.x * D0.x + D1.y * D0.y) / den;
                 const R ri = (D1.y * D0.x - D1.x * D0.y) / den;
                 const R rnd = __builtin_rint(rr);
                 const R dx = rr - rnd;
                 const bool ok = rnd >= (R)1 && rnd <= (R)a.T && (dx * dx + ri * ri) <= (R)0.0625 &&
-                                (sig0 + (long long)((int)rnd - 1) * sig_step) < a.batch;
+                                g.sig((int)rnd - 1) < a.batch;
                 if (ok) { bstar = (int)rnd - 1; action = 1; }
                 else action = 3;
             }
         }
         if (a.stats && checked && nf == 0 && t == 0 && tau > (R)0) {
             // calibration: largest |D0| / tau seen (non-negative doubles order as integers)
-            const double q = (double)__builtin_sqrt(D0.x * D0.x + D0.y * D0.y) / (double)tau;
+            const double q = (double)d0 / (double)tau;
             atomicMax(&a.counts->reserved[0], (unsigned long long)__double_as_longlong(q));
         }
+
         // Location fallback on the error path: when D1/D0 is not an index (an
         // error just above the threshold, where location noise dominates) and
         // the inputs are intact, re-encode every signal of the group and take
         // the one whose own checksums disagree most.
-        if (domain_any<PL>(action == 3 && nf == 0 && a.x_intact)) {
+        if (g.domain_any(action == 3 && nf == 0 && a.x_intact)) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             R best = (R)-1;
             int bbest = -1;
             for (int b = 0; b < a.T; ++b) {
-                const long long sb = sig0 + (long long)b * sig_step;
+                const long long sb = g.sig(b);
                 const bool vb = sb < a.batch;
-                V p = V{0, 0}, qv[E];
+                V p = V{0, 0};
+                V bucket[M];
 #pragma unroll
-                for (int r = 0; r < E; ++r) {
-                    V xv = vb ? x[sb * N + t + P * r] : V{0, 0};
-                    if (a.conj) xv.y = -xv.y;
-                    p = cadd(p, cmul(a.left[t + P * r], xv));
-                    V yv = vb ? y[sb * N + t + P * r] : V{0, 0};
-                    if (a.conj) yv.y = -yv.y;
-                    qv[r] = V{yv.x / a.scale, yv.y / a.scale};
+                for (int m = 0; m < M; ++m) bucket[m] = V{0, 0};
+                if (vb) {
+#pragma unroll
+                    for (int r = 0; r < E; ++r) {
+                        V xv = x[g.in_off(a, sb, t + P * r)];
+                        if (a.conj_in) xv.y = -xv.y;
+                        V av = a_lds[t + P * r];
+                        if constexpr (PL::KIND == kRowPass) av = cmul(av, g.twiddle(a, t + P * r));
+                        p = cadd(p, cmul(av, xv));
+                        V yv = y[g.out_off(a, sb, t + P * r)];
+                        if (a.conj_out) yv.y = -yv.y;
+                        bucket[(P * r) % M] = cadd(bucket[(P * r) % M], V{yv.x / a.scale, yv.y / a.scale});
+                    }
                 }
-                const V q = cmul(lanef, encode_out<V, E, P, M>(qv));
+                V q = bucket[0];
+#pragma unroll
+                for (int m = 1; m < M; ++m) q = cadd(q, cmul(bucket[m], wM<V, M>(m)));
+                q = cmul(lanef, q);
                 R d[2] = {q.x - p.x, q.y - p.y};
-                slot_sum<PL>(d, red);
-                const R m = d[0] * d[0] + d[1] * d[1];
-                if (vb && m > best) { best = m; bbest = b; }
+                g.template reduce<OpAdd>(d, red);
+                const R m2 = d[0] * d[0] + d[1] * d[1];
+                if (vb && m2 > best) { best = m2; bbest = b; }
             }
             if (action == 3 && nf == 0 && bbest >= 0) { bstar = bbest; action = 1; }
         }
-        const long long sstar = sig0 + (long long)(bstar < 0 ? 0 : bstar) * sig_step;
+        const long long sstar = g.sig(bstar < 0 ? 0 : bstar);
 
         if constexpr (FT == 1) {
             if (action != 0 && t == 0) {
                 atomicAdd(&a.counts->detected, 1ull);
                 if (action == 3) atomicAdd(&a.counts->uncorrectable, 1ull);
-                else atomicExch(&a.counts->last_signal, (unsigned long long)sstar);
+                else atomicExch(&a.counts->last_signal, (unsigned long long)(a.sig_base + sstar));
             }
         } else {
-            if (domain_any<PL>(action == 1 || action == 2)) {
+            if (g.domain_any(action == 1 || action == 2)) {
                 // ---- delayed batched correction: W x_s on the slot's lanes ----
-                SlotFFT<V, PL, Rs...>::run(xs, a.tw, t, lds, lds_off);   // xs := W x_s
-                R cm = 0;
-                bool cf = true;
-                V cvec[E];
-#pragma unroll
-                for (int r = 0; r < E; ++r) {
-                    cvec[r] = csub(xs[r], ys[r]);   // c = W x_s - y_s
-                    cf = cf && cfin(cvec[r].x, cvec[r].y, a.cap);
-                    const R m2 = cvec[r].x * cvec[r].x + cvec[r].y * cvec[r].y;
-                    cm = m2 > cm ? m2 : cm;
-                }
-                const V ec = cmul(lanef, encode_out<V, E, P, M>(cvec));
-                R w3[3] = {ec.x, ec.y, cf ? (R)0 : (R)1};
-                slot_sum<PL>(w3, red);
-                const R cmx = slot_max<PL>(cm, red);
-                // additive only when c is finite and no larger than one signal's
-                // rms output norm; otherwise rebuild from the other outputs
-                const R yrms2 = (R)N * nu_s / (R)a.T;
-                if (action == 1 && !(w3[2] == (R)0 && cmx <= yrms2)) action = 2;
-                bool ok = true;
-                if (action == 1) {
-                    const R vx = w3[0] + D0.x, vy = w3[1] + D0.y;
-                    ok = __builtin_sqrt(vx * vx + vy * vy) <= tau;
-                }
-                // make this lane's earlier stores visible to its own reloads
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                // x_s = X e: kept in registers when in place, else summed
+                // again from the group's intact inputs
+#pragma unroll
+                for (int r = 0; r < E; ++r) {
+                    V acc = V{0, 0};
+                    if constexpr (KEEP_XS) {
+                        acc = xs[r];
+                    } else {
+                        for (int b = 0; b < a.T; ++b) {
+                            const long long sb = g.sig(b);
+                            if (sb >= a.batch) continue;
+                            V xv = x[g.in_off(a, sb, t + P * r)];
+                            if (a.conj_in) xv.y = -xv.y;
+                            acc = cadd(acc, xv);
+                        }
+                    }
+                    if constexpr (PL::KIND == kRowPass) acc = cmul(acc, g.twiddle(a, t + P * r));
+                    reg[r] = acc;
+                }
+                slot_fft<V, E, P, BLOCK, decltype(li), 1, Rs...>(reg, a.tw, t, lds, li);   // W x_s
+                // c = W x_s - Y e, element by element, Y e summed from the
+                // group's stored outputs (internal domain); skip: leave out b*
+                auto corr_elem = [&](int r, int skip) -> V {
+                    V acc = reg[r];
+                    for (int b = 0; b < a.T; ++b) {
+                        const long long sb = g.sig(b);
+                        if (sb >= a.batch || b == skip) continue;
+                        V yv = y[g.out_off(a, sb, t + P * r)];
+                        if (a.conj_out) yv.y = -yv.y;
+                        acc = V{acc.x - yv.x / a.scale, acc.y - yv.y / a.scale};
+                    }
+                    return acc;
+                };
+                const R yrms2 = (R)Ns * nu_s / (R)a.T;
+                bool cf = true, small = true;
+                V bucket[M];
+#pragma unroll
+                for (int m = 0; m < M; ++m) bucket[m] = V{0, 0};
+#pragma unroll
+                for (int r = 0; r < E; ++r) {
+                    const V c = corr_elem(r, -1);
+                    cf = cf && cfin(c.x, c.y, a.cap);
+                    small = small && (c.x * c.x + c.y * c.y) <= yrms2;
+                    bucket[(P * r) % M] = cadd(bucket[(P * r) % M], c);
+                }
+                V ec = bucket[0];
+#pragma unroll
+                for (int m = 1; m < M; ++m) ec = cadd(ec, cmul(bucket[m], wM<V, M>(m)));
+                ec = cmul(lanef, ec);
+                R w4[4] = {ec.x, ec.y, cf ? (R)0 : (R)1, small ? (R)0 : (R)1};
+                g.template reduce<OpAdd>(w4, red);
+                // additive only when c is finite and no larger than one signal's
+                // rms output norm; otherwise rebuild from the other outputs
+                if (action == 1 && !(w4[2] == (R)0 && w4[3] == (R)0)) action = 2;
+                bool ok = true;
+                if (action == 1) {
+                    const R vx = w4[0] + D0.x, vy = w4[1] + D0.y;
+                    ok = __builtin_sqrt(vx * vx + vy * vy) <= tau;
+                }
                 bool rebuilt_ok = true;
                 if (action == 1 && ok) {
-                    V* yo = y + sstar * N;
+                    // y_b* += scale * cj(c)
 #pragma unroll
                     for (int r = 0; r < E; ++r) {
-                        V cc = cvec[r];
-                        if (a.conj) cc.y = -cc.y;
-                        const V old = yo[t + P * r];
-                        yo[t + P * r] = V{old.x + a.scale * cc.x, old.y + a.scale * cc.y};
+                        V cc = corr_elem(r, -1);
+                        if (a.conj_out) cc.y = -cc.y;
+                        const long long o = g.out_off(a, sstar, t + P * r);
+                        const V old = y[o];
+                        y[o] = V{old.x + a.scale * cc.x, old.y + a.scale * cc.y};
                     }
                 } else if (action == 2) {
-                    // stored domain: y_b* = scale * cj(W x_s) - sum_{b != b*} y_b
+                    // y_b* = scale * cj(W x_s - sum_{b != b*} y_b)
 #pragma unroll
                     for (int r = 0; r < E; ++r) {
-                        V vv = xs[r];
-                        if (a.conj) vv.y = -vv.y;
-                        cvec[r] = V{a.scale * vv.x, a.scale * vv.y};
-                    }
-                    for (int b = 0; b < a.T; ++b) {
-                        const long long sb = sig0 + (long long)b * sig_step;
-                        if (b == bstar || sb >= a.batch) continue;
-                        const V* yb = y + sb * N;
-#pragma unroll
-                        for (int r = 0; r < E; ++r) cvec[r] = csub(cvec[r], yb[t + P * r]);
-                    }
-                    V* yo = y + sstar * N;
-#pragma unroll
-                    for (int r = 0; r < E; ++r) {
-                        rebuilt_ok = rebuilt_ok && cfin(cvec[r].x, cvec[r].y, a.cap);
-                        yo[t + P * r] = cvec[r];
+                        V vv = corr_elem(r, bstar);
+                        if (a.conj_out) vv.y = -vv.y;
+                        vv = V{a.scale * vv.x, a.scale * vv.y};
+                        rebuilt_ok = rebuilt_ok && cfin(vv.x, vv.y, a.cap);
+                        y[g.out_off(a, sstar, t + P * r)] = vv;
                     }
                 }
-                const unsigned bad =
-                    slot_or<PL>((action == 2 && !rebuilt_ok) ? 1u : 0u, reinterpret_cast<unsigned*>(red));
-                if (action == 2 && bad) ok = false;
+                unsigned badv[1] = {(action == 2 && !rebuilt_ok) ? 1u : 0u};
+                g.template reduce<OpOr>(badv, reinterpret_cast<unsigned*>(red));
+                if (action == 2 && badv[0] != 0u) ok = false;
                 if ((action == 1 || action == 2) && t == 0) {
                     atomicAdd(&a.counts->detected, 1ull);
                     if (!ok) atomicAdd(&a.counts->uncorrectable, 1ull);
                     else if (action == 1) atomicAdd(&a.counts->corrected, 1ull);
                     else atomicAdd(&a.counts->rebuilt, 1ull);
-                    atomicExch(&a.counts->last_signal, (unsigned long long)sstar);
+                    atomicExch(&a.counts->last_signal, (unsigned long long)(a.sig_base + sstar));
                 }
             }
             if (action == 3 && t == 0) {

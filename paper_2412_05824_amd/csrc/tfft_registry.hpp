@@ -14,27 +14,29 @@ using LaunchFn = hipError_t (*)(const void* x, void* y, const void* kargs, long 
 
 struct KernelEntry {
     int precision;          // 0 fp32, 1 fp64
-    int N;                  // transform length
-    int ft;                 // 0 off, 1 detect, 2 correct
+    int kind;               // kSingle, kColPass, kRowPass
+    int Ns;                 // (sub-)transform length
+    int ft;                 // 0 off, 1 detect, 2 correct, 3 correct in place
     int E, P, threads;      // elements per lane, lanes per slot, lanes per workgroup
-    int slots_per_block;    // signals per workgroup per transaction
+    int slots_per_block;    // sub-signals per workgroup per transaction
     int n_stages;
     int radices[8];
     LaunchFn launch;
 };
 
 template <class V, class PL, int FT, int... Rs>
-hipError_t launch_single(const void* x, void* y, const void* ka, long long grid, hipStream_t s) {
+hipError_t launch_fft(const void* x, void* y, const void* ka, long long grid, hipStream_t s) {
     const KArgs<V>& a = *static_cast<const KArgs<V>*>(ka);
-    hipLaunchKernelGGL((k_single<V, PL, FT, Rs...>), dim3((unsigned)grid), dim3(PL::THREADS), 0, s,
+    hipLaunchKernelGGL((k_fft<V, PL, FT, Rs...>), dim3((unsigned)grid), dim3(PL::THREADS), 0, s,
                        static_cast<const V*>(x), static_cast<V*>(y), a);
     return hipGetLastError();
 }
 
-template <class V, class PL, int FT, int... Rs> KernelEntry make_single_entry(int precision) {
+template <class V, class PL, int FT, int... Rs> KernelEntry make_entry(int precision) {
     KernelEntry e{};
     e.precision = precision;
-    e.N = PL::N;
+    e.kind = PL::KIND;
+    e.Ns = PL::Ns;
     e.ft = FT;
     e.E = PL::E;
     e.P = PL::P;
@@ -43,19 +45,24 @@ template <class V, class PL, int FT, int... Rs> KernelEntry make_single_entry(in
     const int rs[] = {Rs...};
     e.n_stages = (int)sizeof...(Rs);
     for (int i = 0; i < e.n_stages; ++i) e.radices[i] = rs[i];
-    e.launch = &launch_single<V, PL, FT, Rs...>;
+    e.launch = &launch_fft<V, PL, FT, Rs...>;
     return e;
 }
 
-template <class V, int N, int E, int WPB, int B, int... Rs>
-void add_single(std::vector<KernelEntry>& out, int precision) {
-    using PL = Plan<N, E, WPB, B, Rs...>;
-    out.push_back(make_single_entry<V, PL, 0, Rs...>(precision));
-    out.push_back(make_single_entry<V, PL, 1, Rs...>(precision));
-    out.push_back(make_single_entry<V, PL, 2, Rs...>(precision));
+// register the ABFT modes of one plan (in-place correction: single pass only;
+// the passes of a two-pass transform never overwrite their own inputs)
+template <class V, int KIND, int Ns, int E, int WC, int B, int... Rs>
+void add_plan(std::vector<KernelEntry>& out, int precision) {
+    using PL = Plan<KIND, Ns, E, WC, B, Rs...>;
+    out.push_back(make_entry<V, PL, 0, Rs...>(precision));
+    out.push_back(make_entry<V, PL, 1, Rs...>(precision));
+    out.push_back(make_entry<V, PL, 2, Rs...>(precision));
+    if constexpr (KIND == kSingle) out.push_back(make_entry<V, PL, 3, Rs...>(precision));
 }
 
-void register_fp32(std::vector<KernelEntry>& out);
-void register_fp64(std::vector<KernelEntry>& out);
+void register_fp32_single(std::vector<KernelEntry>& out);
+void register_fp32_tiles(std::vector<KernelEntry>& out);
+void register_fp64_single(std::vector<KernelEntry>& out);
+void register_fp64_tiles(std::vector<KernelEntry>& out);
 
 }  // namespace tfft

@@ -22,6 +22,9 @@ TOL = {torch.complex64: 2e-6, torch.complex128: 1e-13}
 NPDT = {torch.complex64: np.complex64, torch.complex128: np.complex128}
 PREC = {torch.complex64: "fp32", torch.complex128: "fp64"}
 SIZES = [64, 128, 256, 512, 1024, 2048, 4096]
+# lengths served by a column pass and a row pass (N = N1 * N2)
+TWO_PASS = {torch.complex64: [1 << 14, 1 << 15, 1 << 17, 1 << 20],
+            torch.complex128: [1 << 13, 1 << 14, 1 << 16]}
 DTYPES = [torch.complex64, torch.complex128]
 
 
@@ -183,3 +186,71 @@ def test_transactions_per_slot(dev, T):
         assert torch.equal(y2, y) or oracle.rel_l2(y2.cpu().numpy(), oracle.fft(x)) <= 2e-6
     finally:
         tf.set_tuning(N, dtype, T=old[0], kappa=old[1])
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["fp32", "fp64"])
+def test_two_pass_parity(dev, dtype):
+    for N in TWO_PASS[dtype]:
+        batch = max(3, (1 << 19) // N) + 1
+        x = synth.signals(batch, N, seed=5000 + N, dtype=NPDT[dtype])
+        xd = torch.from_numpy(x).to(dev)
+        ref = oracle.fft(x, threads=8)
+        y0, _ = tf.fft_c2c(xd, dir=tf.FORWARD, ft_mode=tf.FT_OFF)
+        y0h = y0.cpu().numpy()
+        assert oracle.rel_l2(y0h, ref) <= TOL[dtype], N
+        assert _per_signal_rel(y0h, ref).max() <= 2 * TOL[dtype], N
+        for ft in (tf.FT_DETECT, tf.FT_CORRECT):
+            y, counts = tf.fft_c2c(xd, dir=tf.FORWARD, ft_mode=ft)
+            c = tf.counts_dict(counts)
+            assert c["detected"] == 0, (N, ft, c)
+            assert torch.equal(y, y0), (N, ft)
+        # inverse and in place
+        yi, _ = tf.fft_c2c(xd, dir=tf.INVERSE, ft_mode=tf.FT_CORRECT)
+        assert oracle.rel_l2(yi.cpu().numpy(), oracle.fft(x, dir=+1, threads=8)) <= TOL[dtype], N
+        xin = xd.clone()
+        tf.fft_c2c(xin, dir=tf.FORWARD, ft_mode=tf.FT_CORRECT, out=xin)
+        assert torch.equal(xin, y0), N
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["fp32", "fp64"])
+def test_two_pass_small_chunks(dev, dtype):
+    # chunking of the batch must not change any output bit
+    from paper_2412_05824_amd import _lib
+    N = TWO_PASS[dtype][1]
+    batch = 13
+    x = synth.signals(batch, N, seed=6000, dtype=NPDT[dtype])
+    xd = torch.from_numpy(x).to(dev)
+    y_full, _ = tf.fft_c2c(xd, ft_mode=tf.FT_CORRECT)
+    prec = 0 if dtype == torch.complex64 else 1
+    sig_bytes = N * (8 if prec == 0 else 16)
+    try:
+        assert _lib.load().tfft_set_chunk(N, prec, 3 * sig_bytes) == 0
+        y_chunk, c = tf.fft_c2c(xd, ft_mode=tf.FT_CORRECT)
+        assert torch.equal(y_full, y_chunk)
+        assert tf.counts_dict(c)["detected"] == 0
+        # an injection in the last chunk is located with its global index
+        tf.inject_arm(batch - 2, 7, 1, 29 if prec == 0 else 61, dtype=dtype)
+        y_inj, c2 = tf.fft_c2c(xd, ft_mode=tf.FT_CORRECT)
+        cd = tf.counts_dict(c2)
+        assert cd["detected"] == 1 and cd["last_signal"] == batch - 2, cd
+        assert oracle.rel_l2(y_inj.cpu().numpy()[batch - 2], oracle.fft(x[batch - 2])) <= 2 * TOL[dtype]
+    finally:
+        _lib.load().tfft_set_chunk(N, prec, 256 << 20)
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["fp32", "fp64"])
+def test_two_pass_injection(dev, dtype):
+    N = TWO_PASS[dtype][0]
+    batch = 9
+    nbits = 31 if dtype == torch.complex64 else 63
+    rng = np.random.default_rng(99)
+    for bit in [nbits - 1, nbits - 4, nbits - 9, nbits // 2, 3]:
+        sig, elem, part = int(rng.integers(0, batch)), int(rng.integers(0, N)), int(rng.integers(0, 2))
+        x, ref, yc, yh, c, delta = _inject_case(dev, dtype, N, batch, sig, elem, part, bit)
+        per = _per_signal_rel(yh, ref)
+        msg = f"N={N} bit={bit} sig={sig} elem={elem} counts={c} delta={delta:.3e}"
+        assert per.max() <= 2 * TOL[dtype], msg + f" worst={per.max():.3e}"
+        if c["detected"]:
+            assert c["corrected"] + c["rebuilt"] == 1 and c["last_signal"] == sig, msg
+        else:
+            assert delta <= 2 * TOL[dtype] * np.linalg.norm(ref[sig]), msg
