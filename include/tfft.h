@@ -113,7 +113,7 @@ int tfft_set_tuning(long long N, int precision, int T, double kappa);
 int tfft_get_tuning(long long N, int precision, int* T, double* kappa);
 
 /* Lengths above the single-pass limit run as a column pass and a row pass
- * over chunks of signals whose intermediate (chunk_bytes, default 256 MiB)
+ * over chunks of signals whose intermediate (chunk_bytes, default 128 MiB)
  * lives in a library workspace.  Sets the chunk size for (N, precision);
  * 0 keeps the current value. */
 int tfft_set_chunk(long long N, int precision, long long chunk_bytes);

@@ -7,3 +7,4 @@ from ._lib import (FORWARD, INVERSE, FP32, FP64, FT_OFF, FT_DETECT, FT_CORRECT, 
                    TfftError)
 from .fft import (fft_c2c, prepare, supported, inject_arm, inject_disarm,  # noqa: F401
                   set_tuning, get_tuning, new_counts, counts_dict)
+from .autograd import FFT, fft  # noqa: F401,E402

@@ -1,6 +1,7 @@
 // fp32 column/row pass kernels for N = N1 * N2 > 8192: sub-lengths 64..2048,
-// 16 sub-signals per tile (128-byte contiguous accesses) up to 512 points,
-// 8 above so that a workgroup stays at 512 lanes; E = 16, 32 for 2048 points.
+// E = 16, 16 sub-signals per tile (128-byte contiguous accesses) up to 512
+// points, then 8 and 4 so that a workgroup stays at 512 lanes; neighbouring
+// tiles complete each other's cache lines in the same L2.
 #include "tfft_registry.hpp"
 
 namespace tfft {
@@ -11,7 +12,7 @@ template <int KIND> static void add_kind(std::vector<KernelEntry>& out) {
     add_plan<float2, KIND, 256, 16, 16, 0, 16, 16>(out, 0);
     add_plan<float2, KIND, 512, 16, 16, 0, 2, 16, 16>(out, 0);
     add_plan<float2, KIND, 1024, 16, 8, 0, 4, 16, 16>(out, 0);
-    add_plan<float2, KIND, 2048, 32, 8, 0, 8, 16, 16>(out, 0);
+    add_plan<float2, KIND, 2048, 16, 4, 0, 8, 16, 16>(out, 0);
 }
 
 void register_fp32_tiles(std::vector<KernelEntry>& out) {

@@ -1,5 +1,5 @@
 // fp64 column/row pass kernels for N = N1 * N2 > 4096: sub-lengths 64..1024,
-// 8 sub-signals per tile (128-byte contiguous accesses); E = 8, 16 for the
+// E = 8, 8 sub-signals per tile (128-byte contiguous accesses), 4 for the
 // 1024-point sub-length so that a workgroup stays at 512 lanes.
 #include "tfft_registry.hpp"
 
@@ -10,7 +10,7 @@ template <int KIND> static void add_kind(std::vector<KernelEntry>& out) {
     add_plan<double2, KIND, 128, 8, 8, 0, 2, 8, 8>(out, 1);
     add_plan<double2, KIND, 256, 8, 8, 0, 4, 8, 8>(out, 1);
     add_plan<double2, KIND, 512, 8, 8, 0, 8, 8, 8>(out, 1);
-    add_plan<double2, KIND, 1024, 16, 8, 0, 4, 16, 16>(out, 1);
+    add_plan<double2, KIND, 1024, 8, 4, 0, 2, 8, 8, 8>(out, 1);
 }
 
 void register_fp64_tiles(std::vector<KernelEntry>& out) {

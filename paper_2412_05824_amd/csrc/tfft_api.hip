@@ -134,7 +134,7 @@ Tuning default_tuning(int precision, long long N) {
     // kappa * u * sqrt(T log2 Ns) of its norm, so T stays small to keep that
     // under the 2e-6 relative tolerance; fp64 has ample margin.
     Tuning t{};
-    t.chunk_bytes = 256ll << 20;
+    t.chunk_bytes = 128ll << 20;
     if (precision == TFFT_FP32) {
         t.kappa = 8.0;
         t.T = N <= 128 ? 2 : 1;

@@ -30,7 +30,8 @@
 //
 // Two-side ABFT (Sec. 4.1-4.3), per slot and group of T transactions, e_k =
 // w_M^k (M = 3, or 5 when 3 | Ns) and a = e^T W of the sub-length:
-//   per transaction b: p_b = a^T x_b (input, a from LDS), q_b = e^T y_b
+//   per transaction b: p_b = a^T x_b (input; each lane keeps its E entries of
+//   a in registers, since it encodes the same positions every time), q_b = e^T y_b
 //   (output, M bucket sums), x_s += x_b (right-side checksum X e, kept in
 //   registers: the inputs "compressed" into registers);
 //   group close: D0 = sum q_b - sum p_b detects, D1 = sum (b+1)(q_b - p_b)
@@ -258,7 +259,12 @@ template <class V, class PL> struct Geo {
             t = tid / C;
             slot = tid % C;
             lds_off = 0;
-            const long long bid = blockIdx.x;
+            // workgroups are dealt round-robin to the 8 XCDs; renumber them so
+            // each XCD (and its L2) walks a contiguous range of tiles, where
+            // neighbouring tiles share cache lines
+            long long bid = blockIdx.x;
+            const long long G = gridDim.x;
+            if ((G & 7) == 0) bid = (bid & 7) * (G >> 3) + (bid >> 3);
             const long long tile = bid % a.tiles;   // tiles of one signal group are consecutive
             const long long grp = bid / a.tiles;
             line = (int)(tile * C + slot);
@@ -374,7 +380,6 @@ __global__ __launch_bounds__(PL::THREADS) void k_fft(const V* __restrict__ x, V*
     constexpr int NRED = 6;
     constexpr int RED = 2 * (PL::TILE ? PL::C : 1) * PL::WAVES * NRED;
     __shared__ V lds[PL::LDS_DATA];
-    __shared__ V a_lds[FT ? Ns : 1];
     __shared__ R red[FT ? RED : 1];
 
     Geo<V, PL> g(a);
@@ -382,9 +387,11 @@ __global__ __launch_bounds__(PL::THREADS) void k_fft(const V* __restrict__ x, V*
     constexpr bool KEEP_XS = FT == 3;   // in place: inputs are gone after the store
     const int t = g.t;
 
+    // this lane's share of the left vector e^T W: always the same positions
+    V aw[FT ? E : 1];
     if constexpr (FT != 0) {
-        for (int n = threadIdx.x; n < Ns; n += PL::THREADS) a_lds[n] = a.left[n];
-        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < E; ++r) aw[r] = a.left[t + P * r];
     }
 
     V reg[E];
@@ -431,7 +438,7 @@ __global__ __launch_bounds__(PL::THREADS) void k_fft(const V* __restrict__ x, V*
                     reg[r] = cmul(z, tw);
                 }
                 if constexpr (FT != 0) {
-                    V av = a_lds[t + P * r];
+                    V av = aw[r];
                     if constexpr (PL::KIND == kRowPass) av = cmul(av, tw);
                     p = cadd(p, cmul(av, z));
                     nu += z.x * z.x + z.y * z.y;
@@ -553,7 +560,7 @@ __global__ __launch_bounds__(PL::THREADS) void k_fft(const V* __restrict__ x, V*
                     for (int r = 0; r < E; ++r) {
                         V xv = x[g.in_off(a, sb, t + P * r)];
                         if (a.conj_in) xv.y = -xv.y;
-                        V av = a_lds[t + P * r];
+                        V av = aw[r];
                         if constexpr (PL::KIND == kRowPass) av = cmul(av, g.twiddle(a, t + P * r));
                         p = cadd(p, cmul(av, xv));
                         V yv = y[g.out_off(a, sb, t + P * r)];

@@ -235,7 +235,7 @@ def test_two_pass_small_chunks(dev, dtype):
         assert cd["detected"] == 1 and cd["last_signal"] == batch - 2, cd
         assert oracle.rel_l2(y_inj.cpu().numpy()[batch - 2], oracle.fft(x[batch - 2])) <= 2 * TOL[dtype]
     finally:
-        _lib.load().tfft_set_chunk(N, prec, 256 << 20)
+        _lib.load().tfft_set_chunk(N, prec, 128 << 20)
 
 
 @pytest.mark.parametrize("dtype", DTYPES, ids=["fp32", "fp64"])
