@@ -30,6 +30,16 @@ HBM_PEAK_GBS = 8000.0
 TOTAL_ELEMS = 1 << 27          # 1 GiB of complex64 per buffer
 
 
+def kernel_fingerprint() -> str:
+    """Hash of the kernel sources, to match stored counter readings to this build."""
+    import hashlib
+    m = hashlib.sha256()
+    for f in ("tfft_device.hpp", "tfft_kernels.hpp", "inst_fp32_single.hip", "inst_fp32_tiles.hip"):
+        with open(os.path.join(ROOT, "paper_2412_05824_amd", "csrc", f), "rb") as fh:
+            m.update(fh.read())
+    return m.hexdigest()[:16]
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -39,6 +49,8 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-extra", action="store_true", help="skip the off/injection sweep")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--copy-ref", action="store_true",
+                   help="only run a plain 1 GiB device copy (reference for counter scaling)")
     return p.parse_args()
 
 
@@ -58,6 +70,14 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
+    if args.copy_ref:
+        src = torch.zeros(TOTAL_ELEMS, dtype=torch.complex64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(args.warmup + args.steps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_ref_bytes_per_launch": 2 * TOTAL_ELEMS * 8}), flush=True)
+        return
     logs = [int(s) for s in args.sizes.split(",") if s] if args.sizes else list(range(6, 23))
     sizes = [1 << k for k in logs if tf.supported(1 << k, torch.complex64)]
     skipped = [1 << k for k in logs if (1 << k) not in sizes]
@@ -108,9 +128,19 @@ def main():
         return total_ms
 
     # ---- timed region: K steps of the ABFT sweep ----
+    from paper_2412_05824_amd import _lib
+    lib = _lib.load()
     torch.cuda.synchronize()
     per_kernel_ms = {}
-    total_ms = time_sweep(tf.FT_CORRECT, args.steps, args.warmup, per_kernel=per_kernel_ms)
+    for _ in range(args.warmup):
+        for N in sizes:
+            launch(N, tf.FT_CORRECT)
+    torch.cuda.synchronize()
+    lib.tfft_profile(1)          # HIP events around every kernel launch, on its stream
+    _lib.profile_read()          # drop anything recorded before the timed region
+    total_ms = time_sweep(tf.FT_CORRECT, args.steps, 0, per_kernel=per_kernel_ms)
+    kernels = [k for k in _lib.profile_read() if k["ft"] >= 2]
+    lib.tfft_profile(0)
     ms_per_step = total_ms / args.steps
     bytes_per_step = sum(2 * TOTAL_ELEMS * 8 for _ in sizes)
     value = bytes_per_step / (ms_per_step * 1e-3) / 1e9
@@ -159,16 +189,20 @@ def main():
                 "inj_counts": {k: cd[k] for k in ("detected", "corrected", "rebuilt", "uncorrectable")},
             })
 
-    # ---- roofline of the kernel that dominates the step ----
-    dom = max(sizes, key=lambda n: per_kernel_ms[n])
-    achieved = 2 * TOTAL_ELEMS * 8 / (per_kernel_ms[dom] * 1e-3) / 1e9
+    # ---- roofline of the kernel that takes most of the step ----
+    dom = max(kernels, key=lambda k: k["total_ms"])
+    dom_name = f"{dom['precision']} {dom['kind']} Ns={dom['Ns']} ft={dom['ft']}"
+    dom_avg_ms = dom["total_ms"] / dom["launches"]
+    dom_bytes = dom["bytes"] / dom["launches"]
+    achieved = dom_bytes / (dom_avg_ms * 1e-3) / 1e9
     traffic = None
     tpath = os.path.join(ROOT, "profiles", "traffic.json")
     if os.path.exists(tpath):
-        try:
-            traffic = json.load(open(tpath)).get(f"fp32_ft_N{dom}")
-        except Exception:
-            traffic = None
+        # counters taken on other kernel sources do not describe this build
+        tj = json.load(open(tpath))
+        if tj.get("kernel_source_sha256_16") == kernel_fingerprint():
+            rec = tj.get("kernels", {}).get(dom_name)
+            traffic = rec["traffic_bytes"] if rec else None
 
     # ---- CPU oracle baseline on a bounded sample (rank 0, N=1) ----
     cpu = None
@@ -215,7 +249,13 @@ def main():
                    "pct_hbm_peak": round(100 * value / HBM_PEAK_GBS, 2)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": f"k_single fp32 N={dom} ft=correct"},
+                     "traffic": traffic, "kernel": f"k_fft {dom_name}",
+                     "avg_launch_us": round(dom_avg_ms * 1e3, 2),
+                     "bytes_per_launch": dom_bytes,
+                     "share_of_step": round(dom["total_ms"] / total_ms, 3)},
+        "kernels": [{**k, "avg_us": round(1e3 * k["total_ms"] / k["launches"], 2),
+                     "gbs": round(k["bytes"] / (k["total_ms"] * 1e-3) / 1e9, 1)} for k in
+                    sorted(kernels, key=lambda k: -k["total_ms"])],
         "cpu_baseline": cpu,
         "clean_counts": c_clean,
         "sweep": {str(k): v for k, v in sweep.items()},

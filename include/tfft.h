@@ -126,6 +126,17 @@ int tfft_set_chunk(long long N, int precision, long long chunk_bytes);
  * group. */
 int tfft_calibration(int on);
 
+/* Per-launch timing for benchmarks: while on, every kernel launch made by
+ * tfft_c2c outside stream capture is bracketed by a pair of HIP events on its
+ * stream.  tfft_profile_read synchronises on them, writes one text line per
+ * kernel "precision kind Ns ft launches total_ms algorithmic_bytes" into buf
+ * (host memory of buflen bytes), clears the log and returns the text length;
+ * with buf == NULL it returns the size needed instead.  kind is single,
+ * colpass or rowpass; algorithmic bytes count each launch's input read and
+ * output write once. */
+int tfft_profile(int on);
+int tfft_profile_read(char* buf, long long buflen);
+
 const char* tfft_strerror(int status);
 int tfft_last_hip_error(void);
 

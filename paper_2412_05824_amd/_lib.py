@@ -43,6 +43,8 @@ SIGNATURES = {
     "tfft_set_tuning": ([_LL, _I, _I, _D], _I),
     "tfft_get_tuning": ([_LL, _I, ctypes.POINTER(_I), ctypes.POINTER(_D)], _I),
     "tfft_calibration": ([_I], _I),
+    "tfft_profile": ([_I], _I),
+    "tfft_profile_read": ([ctypes.c_char_p, _LL], _I),
     "tfft_set_chunk": ([_LL, _I, _LL], _I),
     "tfft_strerror": ([_I], ctypes.c_char_p),
     "tfft_last_hip_error": ([], _I),
@@ -84,3 +86,19 @@ def last_hip_error() -> int:
 def check(status: int, what: str) -> None:
     if status != TFFT_OK:
         raise TfftError(status, what)
+
+
+def profile_read() -> list:
+    """Per-kernel launch statistics recorded since tfft_profile(1) (see tfft.h)."""
+    lib = load()
+    n = lib.tfft_profile_read(None, 0)
+    buf = ctypes.create_string_buffer(max(1, n))
+    rc = lib.tfft_profile_read(buf, len(buf))
+    if rc < 0:
+        raise TfftError(rc, "tfft_profile_read")
+    rows = []
+    for line in buf.value.decode().splitlines():
+        prec, kind, ns, ft, n_l, ms, nbytes = line.split()
+        rows.append({"precision": prec, "kind": kind, "Ns": int(ns), "ft": int(ft),
+                     "launches": int(n_l), "total_ms": float(ms), "bytes": float(nbytes)})
+    return rows

@@ -13,6 +13,8 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <string>
+#include <cstdio>
 #include <tuple>
 #include <vector>
 
@@ -83,6 +85,17 @@ struct Inject {
 } g_inj;
 
 bool g_stats = false;   // calibration mode: kernels record max |D0| / tau
+
+// Optional per-launch timing: a HIP event pair around every kernel launch, on
+// the launch stream, with the launch's algorithmic bytes (input + output).
+struct LaunchRec {
+    const KernelEntry* e;
+    hipEvent_t start, stop;
+    double bytes;
+};
+bool g_prof = false;
+std::vector<LaunchRec> g_prof_log;
+std::string g_prof_text;   // aggregated, not yet read
 
 void ensure_registry() {
     if (g_entries) return;
@@ -293,13 +306,27 @@ void fill_common(KArgs<V>& a, const KernelEntry& e, const SubTables& st, const T
     a.counts = reinterpret_cast<FtCounts*>(counts);
     a.inj_signal = -1;
     a.stats = g_stats ? 1 : 0;
+    a.xcd_order = 1;
 }
 
 template <class V> int run(const KernelEntry& e, const void* x, void* y, const KArgs<V>& a,
                            long long grid, hipStream_t stream) {
     if (grid <= 0) return TFFT_OK;
     if (grid > 0x7fffffffLL) return TFFT_EUNSUPPORTED;
+    LaunchRec rec{};
+    const bool prof = g_prof && !capturing(stream);
+    if (prof) {
+        rec.e = &e;
+        rec.bytes = 2.0 * (double)a.batch * (double)a.N * (double)sizeof(V);
+        if (hipEventCreate(&rec.start) != hipSuccess || hipEventCreate(&rec.stop) != hipSuccess)
+            return hip_fail(hipGetLastError());
+        (void)hipEventRecord(rec.start, stream);
+    }
     hipError_t err = e.launch(x, y, &a, grid, stream);
+    if (prof) {
+        (void)hipEventRecord(rec.stop, stream);
+        g_prof_log.push_back(rec);
+    }
     return err == hipSuccess ? TFFT_OK : hip_fail(err);
 }
 
@@ -366,7 +393,7 @@ int transform(const Route& rt, const void* x, void* y, long long N, long long ba
         A.sig_base = B.sig_base = c0;
         B.inj_signal = -1;
         if (inj.armed && inj.signal >= c0 && inj.signal < c0 + cnt) {
-            B.inj_signal = inj.signal - c0;
+            B.inj_signal = inj.signal;   // global index: the kernel compares sig_base + s
             B.inj_elem = inj.element;
             B.inj_part = inj.part;
             B.inj_bit = inj.bit;
@@ -452,6 +479,45 @@ int tfft_set_chunk(long long N, int precision, long long chunk_bytes) {
     if (chunk_bytes > 0) tu.chunk_bytes = chunk_bytes;
     g_tuning[std::make_pair(precision, N)] = tu;
     return TFFT_OK;
+}
+
+int tfft_profile(int on) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_prof = on != 0;
+    return TFFT_OK;
+}
+
+int tfft_profile_read(char* buf, long long buflen) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    // aggregate the pending launches per kernel: launches, total ms, bytes
+    struct Agg { long long n = 0; double ms = 0, bytes = 0; };
+    std::map<std::tuple<int, int, int, int>, Agg> agg;
+    for (LaunchRec& r : g_prof_log) {
+        float ms = 0.f;
+        if (hipEventSynchronize(r.stop) == hipSuccess && hipEventElapsedTime(&ms, r.start, r.stop) == hipSuccess) {
+            Agg& g = agg[std::make_tuple(r.e->precision, r.e->kind, r.e->Ns, r.e->ft)];
+            g.n += 1;
+            g.ms += ms;
+            g.bytes += r.bytes;
+        }
+        (void)hipEventDestroy(r.start);
+        (void)hipEventDestroy(r.stop);
+    }
+    g_prof_log.clear();
+    static const char* kinds[] = {"single", "colpass", "rowpass"};
+    for (auto& kv : agg) {
+        char line[256];
+        snprintf(line, sizeof(line), "%s %s %d %d %lld %.6f %.1f\n",
+                 std::get<0>(kv.first) == TFFT_FP32 ? "fp32" : "fp64", kinds[std::get<1>(kv.first)],
+                 std::get<2>(kv.first), std::get<3>(kv.first), kv.second.n, kv.second.ms, kv.second.bytes);
+        g_prof_text += line;
+    }
+    if (!buf) return (int)g_prof_text.size() + 1;   // size query keeps the text
+    if ((long long)g_prof_text.size() + 1 > buflen) return TFFT_EINVAL;
+    memcpy(buf, g_prof_text.c_str(), g_prof_text.size() + 1);
+    const int n = (int)g_prof_text.size();
+    g_prof_text.clear();
+    return n;
 }
 
 int tfft_calibration(int on) {

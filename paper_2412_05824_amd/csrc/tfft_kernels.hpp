@@ -80,6 +80,13 @@ template <class V> struct KArgs {
     int stats;            // 1: record max |D0| / tau over groups (calibration)
     int x_intact;         // 1: inputs can be re-read on the error path
     int tiles;            // workgroups per signal group (tile geometries)
+    // Optional indirection (ragged batches): element offset of local signal s
+    // in x and in y, and its global index for counters and injection.  When
+    // null, signal s starts at s * N and its global index is sig_base + s.
+    const long long* in_tab;
+    const long long* out_tab;
+    const long long* id_tab;
+    int xcd_order;        // 1: renumber tile workgroups XCD-major (regular launches)
 };
 
 // Compile-time plan: kind, sub-length Ns, E elements per lane, WC = waves per
@@ -236,7 +243,7 @@ template <class V, class PL> struct Geo {
     int lds_off;         // single: start of the slot's LDS region
     int par = 0;         // which half of the reduction scratch the next reduce uses
 
-    __device__ __forceinline__ Geo(const KArgs<V>& a) {
+    __device__ __forceinline__ Geo(const KArgs<V>& a, long long block, long long nblocks) {
         const int tid = threadIdx.x;
         if constexpr (PL::KIND == kSingle) {
             const int lane = tid % kWave, wave = tid / kWave;
@@ -244,14 +251,14 @@ template <class V, class PL> struct Geo {
                 t = tid;
                 slot = 0;
                 lds_off = 0;
-                sig0 = (long long)blockIdx.x * a.T;
+                sig0 = block * a.T;
                 sig_step = 1;
             } else {
                 const int sigma = lane / P;
                 t = lane % P;
                 slot = wave * PL::SPW + sigma;
                 lds_off = slot * Ns;
-                sig0 = ((long long)blockIdx.x * PL::WAVES + wave) * a.T * PL::SPW + sigma;
+                sig0 = (block * PL::WAVES + wave) * a.T * PL::SPW + sigma;
                 sig_step = PL::SPW;
             }
             line = 0;
@@ -262,9 +269,9 @@ template <class V, class PL> struct Geo {
             // workgroups are dealt round-robin to the 8 XCDs; renumber them so
             // each XCD (and its L2) walks a contiguous range of tiles, where
             // neighbouring tiles share cache lines
-            long long bid = blockIdx.x;
-            const long long G = gridDim.x;
-            if ((G & 7) == 0) bid = (bid & 7) * (G >> 3) + (bid >> 3);
+            long long bid = block;
+            const long long G = nblocks;
+            if (a.xcd_order && (G & 7) == 0) bid = (bid & 7) * (G >> 3) + (bid >> 3);
             const long long tile = bid % a.tiles;   // tiles of one signal group are consecutive
             const long long grp = bid / a.tiles;
             line = (int)(tile * C + slot);
@@ -274,15 +281,24 @@ template <class V, class PL> struct Geo {
     }
     __device__ __forceinline__ long long sig(int b) const { return sig0 + (long long)b * sig_step; }
     // element offsets of input element m / output element k of signal s
+    __device__ __forceinline__ long long in_base(const KArgs<V>& a, long long s) const {
+        return a.in_tab ? a.in_tab[s] : s * a.N;
+    }
+    __device__ __forceinline__ long long out_base(const KArgs<V>& a, long long s) const {
+        return a.out_tab ? a.out_tab[s] : s * a.N;
+    }
+    __device__ __forceinline__ long long gid(const KArgs<V>& a, long long s) const {
+        return a.id_tab ? a.id_tab[s] : a.sig_base + s;
+    }
     __device__ __forceinline__ long long in_off(const KArgs<V>& a, long long s, int m) const {
-        if constexpr (PL::KIND == kSingle) return s * Ns + m;
-        else if constexpr (PL::KIND == kColPass) return s * a.N + (long long)m * a.N2 + line;
-        else return s * a.N + (long long)line * a.N2 + m;
+        if constexpr (PL::KIND == kSingle) return in_base(a, s) + m;
+        else if constexpr (PL::KIND == kColPass) return in_base(a, s) + (long long)m * a.N2 + line;
+        else return in_base(a, s) + (long long)line * a.N2 + m;
     }
     __device__ __forceinline__ long long out_off(const KArgs<V>& a, long long s, int k) const {
-        if constexpr (PL::KIND == kSingle) return s * Ns + k;
-        else if constexpr (PL::KIND == kColPass) return s * a.N + (long long)k * a.N2 + line;
-        else return s * a.N + line + (long long)a.N1 * k;
+        if constexpr (PL::KIND == kSingle) return out_base(a, s) + k;
+        else if constexpr (PL::KIND == kColPass) return out_base(a, s) + (long long)k * a.N2 + line;
+        else return out_base(a, s) + line + (long long)a.N1 * k;
     }
     // is output element k of this slot the injected one (this kernel's numbering)?
     __device__ __forceinline__ bool inj_hit(const KArgs<V>& a, int k) const {
@@ -371,18 +387,25 @@ template <class V, class PL> struct Geo {
 // path), 3 correct in place (the right-side input sum X e stays in registers
 // through the group, because the outputs overwrite the inputs).
 // ---------------------------------------------------------------------------
+// LDS of one workgroup of a plan: exchange buffer, then reduction scratch
+template <class V, class PL, int FT> struct Smem {
+    using R = typename RealOf<V>::type;
+    static constexpr int NRED = 6;
+    static constexpr int RED = FT ? 2 * (PL::TILE ? PL::C : 1) * PL::WAVES * NRED : 1;
+    static constexpr int BYTES = PL::LDS_DATA * (int)sizeof(V) + RED * (int)sizeof(R);
+};
+
+// One workgroup's share of a transform: block `block` of `nblocks`.
 template <class V, class PL, int FT, int... Rs>
-__global__ __launch_bounds__(PL::THREADS) void k_fft(const V* __restrict__ x, V* __restrict__ y,
-                                                     KArgs<V> a) {
+__device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict__ y, const KArgs<V>& a,
+                                         long long block, long long nblocks, char* smem) {
     using R = typename RealOf<V>::type;
     constexpr int E = PL::E, P = PL::P, M = PL::M, Ns = PL::Ns;
     constexpr bool BLOCK = PL::MULTI_WAVE;
-    constexpr int NRED = 6;
-    constexpr int RED = 2 * (PL::TILE ? PL::C : 1) * PL::WAVES * NRED;
-    __shared__ V lds[PL::LDS_DATA];
-    __shared__ R red[FT ? RED : 1];
+    V* lds = reinterpret_cast<V*>(smem);
+    R* red = reinterpret_cast<R*>(smem + PL::LDS_DATA * sizeof(V));
 
-    Geo<V, PL> g(a);
+    Geo<V, PL> g(a, block, nblocks);
     const auto li = g.lidx();
     constexpr bool KEEP_XS = FT == 3;   // in place: inputs are gone after the store
     const int t = g.t;
@@ -453,7 +476,7 @@ __global__ __launch_bounds__(PL::THREADS) void k_fft(const V* __restrict__ x, V*
 
         slot_fft<V, E, P, BLOCK, decltype(li), 1, Rs...>(reg, a.tw, t, lds, li);
 
-        if (s == a.inj_signal) {   // test hook: one bit flip in one output value
+        if (a.inj_signal >= 0 && valid && g.gid(a, s) == a.inj_signal) {   // test hook: one bit flip
 #pragma unroll
             for (int r = 0; r < E; ++r) {
                 if (g.inj_hit(a, t + P * r)) {
@@ -585,7 +608,7 @@ __global__ __launch_bounds__(PL::THREADS) void k_fft(const V* __restrict__ x, V*
             if (action != 0 && t == 0) {
                 atomicAdd(&a.counts->detected, 1ull);
                 if (action == 3) atomicAdd(&a.counts->uncorrectable, 1ull);
-                else atomicExch(&a.counts->last_signal, (unsigned long long)(a.sig_base + sstar));
+                else atomicExch(&a.counts->last_signal, (unsigned long long)g.gid(a, sstar));
             }
         } else {
             if (g.domain_any(action == 1 || action == 2)) {
@@ -681,7 +704,7 @@ __global__ __launch_bounds__(PL::THREADS) void k_fft(const V* __restrict__ x, V*
                     if (!ok) atomicAdd(&a.counts->uncorrectable, 1ull);
                     else if (action == 1) atomicAdd(&a.counts->corrected, 1ull);
                     else atomicAdd(&a.counts->rebuilt, 1ull);
-                    atomicExch(&a.counts->last_signal, (unsigned long long)(a.sig_base + sstar));
+                    atomicExch(&a.counts->last_signal, (unsigned long long)g.gid(a, sstar));
                 }
             }
             if (action == 3 && t == 0) {
@@ -690,6 +713,13 @@ __global__ __launch_bounds__(PL::THREADS) void k_fft(const V* __restrict__ x, V*
             }
         }
     }
+}
+
+template <class V, class PL, int FT, int... Rs>
+__global__ __launch_bounds__(PL::THREADS) void k_fft(const V* __restrict__ x, V* __restrict__ y,
+                                                     KArgs<V> a) {
+    __shared__ __align__(16) char smem[Smem<V, PL, FT>::BYTES];
+    fft_body<V, PL, FT, Rs...>(x, y, a, blockIdx.x, gridDim.x, smem);
 }
 
 }  // namespace tfft

@@ -22,6 +22,7 @@ struct KernelEntry {
     int n_stages;
     int radices[8];
     LaunchFn launch;
+    int ragged_id;          // index in the ragged plan list (-1: regular plan)
 };
 
 template <class V, class PL, int FT, int... Rs>
@@ -46,6 +47,7 @@ template <class V, class PL, int FT, int... Rs> KernelEntry make_entry(int preci
     e.n_stages = (int)sizeof...(Rs);
     for (int i = 0; i < e.n_stages; ++i) e.radices[i] = rs[i];
     e.launch = &launch_fft<V, PL, FT, Rs...>;
+    e.ragged_id = -1;
     return e;
 }
 
