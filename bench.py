@@ -11,7 +11,11 @@ Printed as ONE JSON line, with:
     (one seeded single-bit flip per 100 launches), ABFT overhead and counts;
   * roofline: the kernel that takes most of the step, HBM-bound, achieved
     GB/s from HIP events on the launch stream against 8 TB/s;
-  * cpu_baseline: the fp64 CPU oracle on a bounded sample of the same sweep.
+  * cpu_baseline: the fp64 CPU oracle on a bounded sample of the same sweep;
+  * ragged: 10,000 signals with lengths drawn uniformly from {2^k, 3*2^k :
+    6 <= k <= 16} (seeded), ABFT on, as one persistent launch replayed from a
+    captured graph against one launch per length and pass (eager and
+    captured), same kernel bodies.
 """
 from __future__ import annotations
 
@@ -49,6 +53,8 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-extra", action="store_true", help="skip the off/injection sweep")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--no-ragged", action="store_true", help="skip the ragged-batch comparison")
+    p.add_argument("--ragged-signals", type=int, default=10000)
     p.add_argument("--copy-ref", action="store_true",
                    help="only run a plain 1 GiB device copy (reference for counter scaling)")
     return p.parse_args()
@@ -189,6 +195,11 @@ def main():
                 "inj_counts": {k: cd[k] for k in ("detected", "corrected", "rebuilt", "uncorrectable")},
             })
 
+    # ---- ragged batch: one persistent launch vs one launch per length ----
+    ragged = None
+    if not args.no_ragged:
+        ragged = ragged_compare(tf, synth, np, torch, dev, args)
+
     # ---- roofline of the kernel that takes most of the step ----
     dom = max(kernels, key=lambda k: k["total_ms"])
     dom_name = f"{dom['precision']} {dom['kind']} Ns={dom['Ns']} ft={dom['ft']}"
@@ -259,8 +270,77 @@ def main():
         "cpu_baseline": cpu,
         "clean_counts": c_clean,
         "sweep": {str(k): v for k, v in sweep.items()},
+        "ragged": ragged,
     }
     print(json.dumps(out), flush=True)
+
+
+def ragged_compare(tf, synth, np, torch, dev, args):
+    """Time the ragged workload in its three forms; returns a dict for the JSON line."""
+    sizes = [int(n) for n in synth.ragged_sizes(args.ragged_signals, seed=5)]
+    total = int(sum(sizes))
+    x = torch.from_numpy(synth.signals(1, total, seed=2005).reshape(-1)).to(dev)
+    y = torch.empty_like(x)
+    plan = tf.RaggedPlan(sizes, device=dev)
+    counts = tf.new_counts(dev)
+    reps = max(3, args.steps)
+
+    def timed(fn):
+        for _ in range(max(1, args.warmup)):
+            fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    def captured(mode):
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            plan(x, out=y, ft_mode=tf.FT_CORRECT, counts=counts, mode=mode)
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            plan(x, out=y, ft_mode=tf.FT_CORRECT, counts=counts, mode=mode)
+        return g
+
+    res = {}
+    for mode in ("persistent", "per_size"):
+        res[f"{mode}_eager_ms"] = timed(lambda: plan(x, out=y, ft_mode=tf.FT_CORRECT, counts=counts,
+                                                     mode=mode))
+        g = captured(mode)
+        res[f"{mode}_graph_ms"] = timed(g.replay)
+        del g
+    off_ms = timed(lambda: plan(x, out=y, ft_mode=tf.FT_OFF, mode="persistent"))
+    info = plan.info(device_state=True)
+    c = tf.counts_dict(counts)
+    bytes_alg = 2.0 * total * 8
+    best_per_size = min(res["per_size_eager_ms"], res["per_size_graph_ms"])
+    out = {
+        "workload": f"{len(sizes)} fp32 signals, lengths uniform over 2^k and 3*2^k, 6<=k<=16 "
+                    f"(seed 5), {total} elements, forward, ABFT correct",
+        "elements": total,
+        "work_items": info["items"],
+        "persistent_grid": info["grid"],
+        **{k: round(v, 4) for k, v in res.items()},
+        "persistent_ft_off_ms": round(off_ms, 4),
+        "gbs_persistent_graph": round(bytes_alg / (res["persistent_graph_ms"] * 1e-3) / 1e9, 1),
+        "gbs_per_size_eager": round(bytes_alg / (res["per_size_eager_ms"] * 1e-3) / 1e9, 1),
+        "speedup_vs_per_size_eager": round(res["per_size_eager_ms"] / res["persistent_graph_ms"], 3),
+        "speedup_vs_best_per_size": round(best_per_size / res["persistent_graph_ms"], 3),
+        "detected": c["detected"],
+        "queue_err": info["queue_err"],
+    }
+    plan.close()
+    del x, y
+    torch.cuda.empty_cache()
+    return out
 
 
 if __name__ == "__main__":

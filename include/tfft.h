@@ -75,31 +75,70 @@ typedef struct {
 int tfft_c2c(const void* x, void* y, long long N, long long batch, int dir, int precision,
              int ft_mode, double scale, tfft_ft_counts* counts, void* hip_stream);
 
-/* Ragged batch: `count` signals of different lengths packed back to back in
- * one persistent launch.  offsets[i] is the first element of signal i
- * (offsets has count+1 entries, offsets[count] = total elements) and sizes[i]
- * its length; both are device arrays of int64.  The plan for this exact list
- * must have been built by tfft_prepare_ragged (outside stream capture); the
- * call itself allocates nothing and may be captured into a hipGraph.
- * Semantics per signal are those of tfft_c2c. */
-int tfft_c2c_ragged(const void* x, void* y, const long long* offsets, const long long* sizes,
-                    long long count, int dir, int precision, int ft_mode,
-                    tfft_ft_counts* counts, void* hip_stream);
-
 /* Build (and cache) tables and plans for length N.  Host call, allocates.
  * Call before capturing tfft_c2c into a graph. */
 int tfft_prepare(long long N, int precision, int ft_mode);
 
-/* Build the schedule for a ragged list (host array sizes_host[count]).
- * Allocates device work-queue state; call outside capture. */
-int tfft_prepare_ragged(const long long* sizes_host, long long count, int precision, int ft_mode);
+/* ---- Ragged batches: signals of mixed lengths in one call ----
+ * The transform of each signal is that of tfft_c2c (Sec. 2.2), with the same
+ * ABFT protection (Sec. 4), and per-signal results are bit-identical between
+ * the two execution modes.  Signals are packed back to back in list order:
+ * signal i occupies elements [sum_{j<i} sizes[j], sum_{j<=i} sizes[j]).
+ *   TFFT_RAGGED_PERSISTENT  one persistent launch: workgroups take work items
+ *                           (a group of signals of one length, or one tile of
+ *                           a column / row pass) from a device queue; a row
+ *                           pass waits on per-group counters for its column
+ *                           pass.  Queue and counters reset themselves, so the
+ *                           launch can be captured once and replayed.
+ *   TFFT_RAGGED_PER_SIZE    one launch per length and pass, same kernel
+ *                           bodies (the comparison baseline). */
+typedef struct tfft_ragged_plan_s* tfft_ragged_plan;
+enum { TFFT_RAGGED_PERSISTENT = 0, TFFT_RAGGED_PER_SIZE = 1 };
+
+/* 1 if a signal of length N can be part of a ragged batch: TFFT_FP32 only,
+ * N = 2^k for 6 <= k <= 17 or N = 3*2^k for 6 <= k <= 16. */
+int tfft_ragged_supported(long long N, int precision);
+
+/* Build a plan for `count` signals of lengths sizes_host[0..count) (HOST
+ * array).  Allocates device memory owned by the plan: per-signal offset
+ * tables, the work queue, the pass counters and a workspace of
+ * sum(two-pass lengths) elements for column-pass results.  Call outside
+ * stream capture.  TFFT_EUNSUPPORTED if a length has no ragged route or the
+ * precision is not TFFT_FP32; *plan is NULL on error. */
+int tfft_ragged_plan_create(tfft_ragged_plan* plan, const long long* sizes_host, long long count,
+                            int precision);
+
+/* Release a plan (after its launches have completed). */
+int tfft_ragged_plan_destroy(tfft_ragged_plan plan);
+
+/* Up to n values: [0] signals, [1] total elements, [2] work items,
+ * [3] classes (lengths x passes), [4] workspace elements, [5] persistent
+ * grid; [6] the queue's error bits and [7] its next-item counter (both read
+ * from the device with a synchronising copy; 0 and 0 between launches). */
+int tfft_ragged_plan_info(tfft_ragged_plan plan, long long* info, int n);
+
+/* Execute a plan.
+ *   x, y        device buffers of total elements (complex64); x == y only
+ *               with ft_mode below TFFT_FT_CORRECT (correction re-reads the
+ *               inputs); partial overlap is not allowed.
+ *   dir         TFFT_FORWARD or TFFT_INVERSE.
+ *   unit_scale  0: outputs scaled by 1 (forward) or 1/N (inverse, per
+ *               signal); 1: no scaling (the adjoint).
+ *   mode        TFFT_RAGGED_PERSISTENT or TFFT_RAGGED_PER_SIZE.
+ *   ft_mode     as in tfft_c2c; counts required unless TFFT_FT_OFF.
+ * Allocates nothing and never synchronises, so it may be captured into a
+ * hipGraph.  Launches of one plan share its queue and workspace and must not
+ * overlap in time (same stream, or ordered). */
+int tfft_c2c_ragged(tfft_ragged_plan plan, const void* x, void* y, int dir, int unit_scale,
+                    int mode, int ft_mode, tfft_ft_counts* counts, void* hip_stream);
 
 /* 1 if N (and precision) has a kernel in this build, else 0. */
 int tfft_supported(long long N, int precision);
 
 /* Test hook (Sec. 5.3 injection protocol): arm a single-bit flip for the NEXT
- * tfft_c2c call only.  The flip hits output element `element` of signal
- * `signal` (real part if part == 0, imaginary if 1), bit `bit` of its IEEE
+ * tfft_c2c or tfft_c2c_ragged call only.  The flip hits output element
+ * `element` of signal `signal` (for a ragged batch: the signal's index in the
+ * list) (real part if part == 0, imaginary if 1), bit `bit` of its IEEE
  * representation, inside the kernel after the last butterfly and before the
  * output checksum, i.e. as a compute-unit fault.  Returns TFFT_EINVAL for a
  * bit outside the element's width. */

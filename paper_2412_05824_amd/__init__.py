@@ -6,5 +6,6 @@ C ABI of include/tfft.h; this package is a thin binding over it.
 from ._lib import (FORWARD, INVERSE, FP32, FP64, FT_OFF, FT_DETECT, FT_CORRECT,  # noqa: F401
                    TfftError)
 from .fft import (fft_c2c, prepare, supported, inject_arm, inject_disarm,  # noqa: F401
-                  set_tuning, get_tuning, new_counts, counts_dict)
+                  set_tuning, get_tuning, new_counts, counts_dict, RaggedPlan, fft_c2c_ragged,
+                  ragged_supported, RAGGED_PERSISTENT, RAGGED_PER_SIZE)
 from .autograd import FFT, fft  # noqa: F401,E402

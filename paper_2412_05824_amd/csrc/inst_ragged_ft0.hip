@@ -1,0 +1,8 @@
+// The persistent ragged kernel with ABFT mode 0.
+#include "tfft_ragged_kernel.hpp"
+
+namespace tfft {
+
+RaggedKernel ragged_kernel_ft0() { return make_ragged_kernel<0>(); }
+
+}  // namespace tfft

@@ -1,0 +1,8 @@
+// The persistent ragged kernel with ABFT mode 2.
+#include "tfft_ragged_kernel.hpp"
+
+namespace tfft {
+
+RaggedKernel ragged_kernel_ft2() { return make_ragged_kernel<2>(); }
+
+}  // namespace tfft

@@ -8,9 +8,11 @@
 // the intermediate stays in the on-package cache and the workspace is bounded.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <string>
@@ -19,7 +21,7 @@
 #include <vector>
 
 #include "tfft.h"
-#include "tfft_registry.hpp"
+#include "tfft_ragged.hpp"
 
 using namespace tfft;
 
@@ -73,7 +75,8 @@ struct Tuning {
 std::mutex g_mu;
 std::vector<KernelEntry>* g_entries = nullptr;
 std::map<std::tuple<int, int, int, int>, const KernelEntry*> g_by_key;   // (prec, kind, Ns, ft)
-std::map<std::tuple<int, int, int>, SubTables> g_sub;                    // (prec, Ns, device)
+std::map<std::pair<int, int>, const KernelEntry*> g_ragged_by_key;      // (ragged plan id, ft)
+std::map<std::tuple<int, int, int, long long>, SubTables> g_sub;         // (prec, Ns, device, radices)
 std::map<std::tuple<int, long long, int>, PassTwiddle> g_pass;           // (prec, N, device)
 std::map<int, Workspace> g_ws;                                           // device
 std::map<std::pair<int, long long>, Tuning> g_tuning;
@@ -104,8 +107,12 @@ void ensure_registry() {
     register_fp32_tiles(*g_entries);
     register_fp64_single(*g_entries);
     register_fp64_tiles(*g_entries);
-    for (const KernelEntry& e : *g_entries)
-        g_by_key[std::make_tuple(e.precision, e.kind, e.Ns, e.ft)] = &e;
+    register_fp32_ragged_single(*g_entries);
+    register_fp32_ragged_tiles(*g_entries);
+    for (const KernelEntry& e : *g_entries) {
+        if (e.ragged_id >= 0) g_ragged_by_key[std::make_pair(e.ragged_id, e.ft)] = &e;
+        else g_by_key[std::make_tuple(e.precision, e.kind, e.Ns, e.ft)] = &e;
+    }
 }
 
 const KernelEntry* find_entry(int precision, int kind, long long Ns, int ft) {
@@ -245,8 +252,14 @@ bool capturing(hipStream_t stream) {
 }
 
 // Cached resources; built unless the stream is being captured.  Caller holds g_mu.
+long long radix_signature(const KernelEntry& e) {
+    long long sig = 0;
+    for (int s = 0; s < e.n_stages; ++s) sig = sig * 32 + e.radices[s];
+    return sig;
+}
+
 int get_sub(const KernelEntry& e, bool may_alloc, SubTables** out) {
-    auto key = std::make_tuple(e.precision, e.Ns, current_device());
+    auto key = std::make_tuple(e.precision, e.Ns, current_device(), radix_signature(e));
     auto it = g_sub.find(key);
     if (it != g_sub.end()) { *out = &it->second; return TFFT_OK; }
     if (!may_alloc) return TFFT_ECAPTURE;
@@ -306,7 +319,6 @@ void fill_common(KArgs<V>& a, const KernelEntry& e, const SubTables& st, const T
     a.counts = reinterpret_cast<FtCounts*>(counts);
     a.inj_signal = -1;
     a.stats = g_stats ? 1 : 0;
-    a.xcd_order = 1;
 }
 
 template <class V> int run(const KernelEntry& e, const void* x, void* y, const KArgs<V>& a,
@@ -402,6 +414,302 @@ int transform(const Route& rt, const void* x, void* y, long long N, long long ba
         rc = run<V>(*rt.col, xb + (size_t)c0 * sig_bytes, ws, A, groups * A.tiles, stream);
         if (rc != TFFT_OK) return rc;
         rc = run<V>(*rt.row, ws, yb + (size_t)c0 * sig_bytes, B, groups * B.tiles, stream);
+        if (rc != TFFT_OK) return rc;
+    }
+    return TFFT_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// Ragged batches: signals of mixed lengths packed back to back.
+// ---------------------------------------------------------------------------
+
+// route of one length through the ragged plan list
+struct RRoute {
+    const KernelEntry* single = nullptr;   // FT-0 entries; other modes share ids
+    const KernelEntry* col = nullptr;
+    const KernelEntry* row = nullptr;
+    long long N1 = 0, N2 = 0;
+};
+
+const KernelEntry* ragged_entry(int id, int ft) {
+    auto it = g_ragged_by_key.find(std::make_pair(id, ft));
+    return it == g_ragged_by_key.end() ? nullptr : it->second;
+}
+
+const KernelEntry* ragged_find(int kind, long long Ns) {
+    for (auto& kv : g_ragged_by_key)
+        if (kv.first.second == 0 && kv.second->kind == kind && kv.second->Ns == Ns) return kv.second;
+    return nullptr;
+}
+
+bool ragged_route(long long N, RRoute* r) {
+    *r = RRoute{};
+    if (N < 1 || N > (1 << 30)) return false;
+    if ((r->single = ragged_find(kSingle, N))) return true;
+    long long best = 0;
+    for (long long n1 = 2; n1 * n1 <= N; ++n1) {
+        if (N % n1) continue;
+        const KernelEntry* c = ragged_find(kColPass, n1);
+        const KernelEntry* w = ragged_find(kRowPass, N / n1);
+        // whole tiles only: a column tile spans slots_per_block of the N / n1
+        // columns, a row tile slots_per_block of the n1 rows
+        if (c && w && (N / n1) % c->slots_per_block == 0 && n1 % w->slots_per_block == 0) best = n1;
+    }
+    if (!best) return false;
+    r->N1 = best;
+    r->N2 = N / best;
+    r->col = ragged_find(kColPass, r->N1);
+    r->row = ragged_find(kRowPass, r->N2);
+    return true;
+}
+
+KernelEntry g_ragged_prof_entry[3];   // labels of the persistent launches in the profile
+
+RaggedKernel ragged_kernel(int ft) {
+    static RaggedKernel k[3];
+    static bool done[3] = {false, false, false};
+    if (!done[ft]) {
+        k[ft] = ft == 0 ? ragged_kernel_ft0() : ft == 1 ? ragged_kernel_ft1() : ragged_kernel_ft2();
+        done[ft] = true;
+    }
+    return k[ft];
+}
+
+}  // namespace
+
+struct tfft_ragged_plan_s {
+    int device = 0;
+    int precision = TFFT_FP32;
+    long long count = 0, total = 0, ws_elems = 0;
+    std::vector<long long> sizes;          // host copy, for argument checks
+    std::vector<RClass> classes;           // host copy (per-size launches)
+    std::vector<int> order;                // launch order of the classes (per-size mode)
+    long long n_items = 0;
+    int cus = 0;
+    void* buf = nullptr;                   // classes, items, desc, queue, counters, tables
+    void* ws = nullptr;                    // column-pass results of the two-pass signals
+    RaggedDesc* d_desc = nullptr;
+    RQueue* d_queue = nullptr;
+};
+
+namespace {
+
+int ragged_build(tfft_ragged_plan_s* P, const long long* sizes, long long count) {
+    P->count = count;
+    P->sizes.assign(sizes, sizes + count);
+    std::vector<long long> xoff(count);
+    long long tot = 0;
+    for (long long i = 0; i < count; ++i) { xoff[i] = tot; tot += sizes[i]; }
+    P->total = tot;
+
+    // classes: one per length (single) or two (column pass, row pass)
+    std::map<long long, std::vector<long long>, std::greater<long long>> by_len;
+    for (long long i = 0; i < count; ++i) by_len[sizes[i]].push_back(i);
+    struct Pending { RRoute rt; std::vector<long long> ids; };
+    std::vector<Pending> lens;
+    for (auto& kv : by_len) {
+        Pending pd;
+        if (!ragged_route(kv.first, &pd.rt)) return TFFT_EUNSUPPORTED;
+        pd.ids = kv.second;
+        lens.push_back(std::move(pd));
+    }
+    // host tables: ids, x offsets, workspace offsets, per length
+    std::vector<long long> tab;
+    long long ws_tot = 0, groups_tot = 0;
+    struct Made { RClass cl; size_t ids_at, xoff_at, wsoff_at; bool two; };
+    std::vector<Made> made;   // single classes and column passes first, row passes after
+    std::vector<Made> rows;
+    for (Pending& pd : lens) {
+        const long long N = pd.rt.single ? pd.rt.single->Ns : pd.rt.N1 * pd.rt.N2;
+        const long long n = (long long)pd.ids.size();
+        const Tuning tu = get_tuning(TFFT_FP32, N);
+        const size_t ids_at = tab.size();
+        for (long long i : pd.ids) tab.push_back(i);
+        const size_t xoff_at = tab.size();
+        for (long long i : pd.ids) tab.push_back(xoff[i]);
+        const long long groups = (n + tu.T - 1) / tu.T;
+        if (pd.rt.single) {
+            const KernelEntry& e = *pd.rt.single;
+            SubTables* st = nullptr;
+            int rc = get_sub(e, true, &st);
+            if (rc != TFFT_OK) return rc;
+            RClass c{};
+            fill_common(c.args, e, *st, tu, nullptr);
+            c.args.batch = n;
+            c.args.N = N;
+            c.args.x_intact = 1;
+            c.plan = e.ragged_id;
+            c.final_pass = 1;
+            const long long per_block = (long long)e.slots_per_block * tu.T;
+            c.nblocks = (int)((n + per_block - 1) / per_block);
+            c.cnt_base = -1;
+            made.push_back(Made{c, ids_at, xoff_at, xoff_at, false});
+            continue;
+        }
+        const size_t wsoff_at = tab.size();
+        for (long long j = 0; j < n; ++j) { tab.push_back(ws_tot); ws_tot += N; }
+        SubTables *sa = nullptr, *sb = nullptr;
+        PassTwiddle* pt = nullptr;
+        int rc = get_sub(*pd.rt.col, true, &sa);
+        if (rc == TFFT_OK) rc = get_sub(*pd.rt.row, true, &sb);
+        if (rc == TFFT_OK) rc = get_pass(TFFT_FP32, N, true, &pt);
+        if (rc != TFFT_OK) return rc;
+        RClass A{}, B{};
+        fill_common(A.args, *pd.rt.col, *sa, tu, nullptr);
+        fill_common(B.args, *pd.rt.row, *sb, tu, nullptr);
+        for (RClass* k : {&A, &B}) {
+            k->args.batch = n;
+            k->args.N = N;
+            k->args.N1 = (int)pd.rt.N1;
+            k->args.N2 = (int)pd.rt.N2;
+            k->args.x_intact = 1;
+            k->cnt_base = (int)groups_tot;
+        }
+        B.args.tw_hi = static_cast<const float2*>(pt->hi);
+        B.args.tw_lo = static_cast<const float2*>(pt->lo);
+        B.args.tw_bits = pt->bits;
+        A.args.tiles = A.tiles = (int)(pd.rt.N2 / pd.rt.col->slots_per_block);
+        B.args.tiles = B.tiles = (int)(pd.rt.N1 / pd.rt.row->slots_per_block);
+        A.plan = pd.rt.col->ragged_id;
+        B.plan = pd.rt.row->ragged_id;
+        A.dst_ws = 1;
+        A.signal_after = 1;
+        B.src_ws = 1;
+        B.final_pass = 1;
+        B.need = A.tiles;
+        A.nblocks = (int)(groups * A.tiles);
+        B.nblocks = (int)(groups * B.tiles);
+        if ((long long)A.nblocks != groups * A.tiles || (long long)B.nblocks != groups * B.tiles)
+            return TFFT_EUNSUPPORTED;
+        groups_tot += groups;
+        // column passes go first in the queue
+        made.insert(made.begin(), Made{A, ids_at, xoff_at, wsoff_at, true});
+        rows.push_back(Made{B, ids_at, wsoff_at, xoff_at, true});
+    }
+    for (Made& m : rows) made.push_back(m);
+    // the column passes were inserted at the front in reverse: largest first
+    {
+        size_t ncol = 0;
+        while (ncol < made.size() && made[ncol].cl.signal_after) ++ncol;
+        std::reverse(made.begin(), made.begin() + ncol);
+    }
+    P->ws_elems = ws_tot;
+
+    // items, in class order
+    std::vector<RItem> items;
+    for (size_t c = 0; c < made.size(); ++c)
+        for (int b = 0; b < made[c].cl.nblocks; ++b) items.push_back(RItem{(int)c, b});
+    P->n_items = (long long)items.size();
+
+    // one device buffer: classes | items | desc | queue | cnt_a | cnt_b | tables
+    auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    const size_t o_cls = 0;
+    const size_t o_items = al(o_cls + made.size() * sizeof(RClass));
+    const size_t o_desc = al(o_items + items.size() * sizeof(RItem));
+    const size_t o_q = al(o_desc + sizeof(RaggedDesc));
+    const size_t o_ca = al(o_q + sizeof(RQueue));
+    const size_t o_cb = al(o_ca + (size_t)groups_tot * sizeof(unsigned));
+    const size_t o_tab = al(o_cb + (size_t)groups_tot * sizeof(unsigned));
+    const size_t bytes = al(o_tab + tab.size() * sizeof(long long));
+    hipError_t err = hipMalloc(&P->buf, bytes);
+    if (err != hipSuccess) { g_last_hip = (int)err; P->buf = nullptr; return TFFT_ENOMEM; }
+    if (ws_tot > 0) {
+        err = hipMalloc(&P->ws, (size_t)ws_tot * sizeof(float2));
+        if (err != hipSuccess) { g_last_hip = (int)err; P->ws = nullptr; return TFFT_ENOMEM; }
+    }
+    char* base = static_cast<char*>(P->buf);
+    const long long* dtab = reinterpret_cast<const long long*>(base + o_tab);
+    for (Made& m : made) {
+        m.cl.args.id_tab = dtab + m.ids_at;
+        m.cl.args.in_tab = dtab + m.xoff_at;
+        m.cl.args.out_tab = dtab + m.wsoff_at;
+    }
+    P->classes.clear();
+    for (Made& m : made) P->classes.push_back(m.cl);
+    RaggedDesc desc{};
+    desc.classes = reinterpret_cast<const RClass*>(base + o_cls);
+    desc.items = reinterpret_cast<const RItem*>(base + o_items);
+    desc.n_items = P->n_items;
+    desc.q = reinterpret_cast<RQueue*>(base + o_q);
+    desc.cnt_a = reinterpret_cast<unsigned*>(base + o_ca);
+    desc.cnt_b = reinterpret_cast<unsigned*>(base + o_cb);
+    desc.ws = static_cast<float2*>(P->ws);
+    P->d_desc = reinterpret_cast<RaggedDesc*>(base + o_desc);
+    P->d_queue = desc.q;
+
+    std::vector<char> host(bytes, 0);
+    memcpy(host.data() + o_cls, P->classes.data(), P->classes.size() * sizeof(RClass));
+    memcpy(host.data() + o_items, items.data(), items.size() * sizeof(RItem));
+    memcpy(host.data() + o_desc, &desc, sizeof(desc));
+    memcpy(host.data() + o_tab, tab.data(), tab.size() * sizeof(long long));
+    err = hipMemcpy(P->buf, host.data(), bytes, hipMemcpyHostToDevice);
+    if (err != hipSuccess) return hip_fail(err);
+
+    hipDeviceProp_t prop{};
+    err = hipGetDeviceProperties(&prop, P->device);
+    if (err != hipSuccess) return hip_fail(err);
+    P->cus = prop.multiProcessorCount;
+    return TFFT_OK;
+}
+
+int ragged_exec(tfft_ragged_plan_s* P, const void* x, void* y, int dir, int unit_scale, int mode,
+                int ft, tfft_ft_counts* counts, const Inject& inj, hipStream_t stream) {
+    RaggedCall c{};
+    c.x = static_cast<const float2*>(x);
+    c.y = static_cast<float2*>(y);
+    c.counts = reinterpret_cast<FtCounts*>(counts);
+    c.inj_signal = inj.armed ? inj.signal : -1;
+    c.inj_elem = inj.element;
+    c.inj_part = inj.part;
+    c.inj_bit = inj.bit;
+    c.conj = dir == TFFT_INVERSE ? 1 : 0;
+    c.unit_scale = unit_scale ? 1 : 0;
+    c.stats = g_stats ? 1 : 0;
+    if (P->n_items == 0) return TFFT_OK;
+    if (mode == TFFT_RAGGED_PERSISTENT) {
+        const RaggedKernel k = ragged_kernel(ft);
+        if (!k.launch || k.blocks_per_cu <= 0) return TFFT_EUNSUPPORTED;
+        long long grid = (long long)k.blocks_per_cu * P->cus;
+        if (grid > P->n_items) grid = P->n_items;
+        LaunchRec rec{};
+        const bool prof = g_prof && !capturing(stream);
+        if (prof) {
+            KernelEntry& pe = g_ragged_prof_entry[ft];
+            pe.precision = TFFT_FP32;
+            pe.kind = 3;
+            pe.Ns = 0;
+            pe.ft = ft;
+            rec.e = &pe;
+            rec.bytes = 2.0 * (double)P->total * (double)sizeof(float2);
+            if (hipEventCreate(&rec.start) != hipSuccess || hipEventCreate(&rec.stop) != hipSuccess)
+                return hip_fail(hipGetLastError());
+            (void)hipEventRecord(rec.start, stream);
+        }
+        hipError_t err = k.launch(c, P->d_desc, (int)grid, stream);
+        if (prof) {
+            (void)hipEventRecord(rec.stop, stream);
+            g_prof_log.push_back(rec);
+        }
+        return err == hipSuccess ? TFFT_OK : hip_fail(err);
+    }
+    // one launch per class, in queue order (column passes, single, row passes)
+    for (const RClass& cl : P->classes) {
+        const KernelEntry* e = ragged_entry(cl.plan, ft);
+        if (!e) return TFFT_EUNSUPPORTED;
+        KArgs<float2> a = cl.args;
+        a.conj_in = cl.src_ws ? 0 : c.conj;
+        a.conj_out = cl.final_pass ? c.conj : 0;
+        a.scale = (cl.final_pass && c.conj && !c.unit_scale) ? 1.0f / (float)a.N : 1.0f;
+        a.counts = c.counts;
+        a.stats = c.stats;
+        a.inj_signal = cl.final_pass ? c.inj_signal : -1;
+        a.inj_elem = c.inj_elem;
+        a.inj_part = c.inj_part;
+        a.inj_bit = c.inj_bit;
+        const void* src = cl.src_ws ? P->ws : x;
+        void* dst = cl.dst_ws ? P->ws : y;
+        int rc = run<float2>(*e, src, dst, a, cl.nblocks, stream);
         if (rc != TFFT_OK) return rc;
     }
     return TFFT_OK;
@@ -504,7 +812,7 @@ int tfft_profile_read(char* buf, long long buflen) {
         (void)hipEventDestroy(r.stop);
     }
     g_prof_log.clear();
-    static const char* kinds[] = {"single", "colpass", "rowpass"};
+    static const char* kinds[] = {"single", "colpass", "rowpass", "ragged"};
     for (auto& kv : agg) {
         char line[256];
         snprintf(line, sizeof(line), "%s %s %d %d %lld %.6f %.1f\n",
@@ -590,11 +898,95 @@ int tfft_c2c(const void* x, void* y, long long N, long long batch, int dir, int 
     return rc;
 }
 
-int tfft_c2c_ragged(const void*, void*, const long long*, const long long*, long long, int, int,
-                    int, tfft_ft_counts*, void*) {
-    return TFFT_EUNSUPPORTED;
+int tfft_ragged_supported(long long N, int precision) {
+    if (precision != TFFT_FP32 || N < 1) return 0;
+    std::lock_guard<std::mutex> lk(g_mu);
+    ensure_registry();
+    RRoute r;
+    return ragged_route(N, &r) ? 1 : 0;
 }
 
-int tfft_prepare_ragged(const long long*, long long, int, int) { return TFFT_EUNSUPPORTED; }
+int tfft_ragged_plan_create(tfft_ragged_plan* plan, const long long* sizes_host, long long count,
+                            int precision) {
+    if (!plan || count < 0 || (count > 0 && !sizes_host)) return TFFT_EINVAL;
+    *plan = nullptr;
+    if (check_precision(precision) != TFFT_OK) return TFFT_EINVAL;
+    if (precision != TFFT_FP32) return TFFT_EUNSUPPORTED;
+    for (long long i = 0; i < count; ++i)
+        if (sizes_host[i] < 1) return TFFT_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    ensure_registry();
+    tfft_ragged_plan_s* P = new tfft_ragged_plan_s();
+    P->device = current_device();
+    P->precision = precision;
+    int rc = ragged_build(P, sizes_host, count);
+    if (rc != TFFT_OK) {
+        if (P->buf) (void)hipFree(P->buf);
+        if (P->ws) (void)hipFree(P->ws);
+        delete P;
+        return rc;
+    }
+    *plan = P;
+    return TFFT_OK;
+}
+
+int tfft_ragged_plan_destroy(tfft_ragged_plan plan) {
+    if (!plan) return TFFT_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (plan->buf) (void)hipFree(plan->buf);
+    if (plan->ws) (void)hipFree(plan->ws);
+    delete plan;
+    return TFFT_OK;
+}
+
+int tfft_ragged_plan_info(tfft_ragged_plan plan, long long* info, int n) {
+    if (!plan || !info || n < 1) return TFFT_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    long long v[8] = {plan->count, plan->total, plan->n_items, (long long)plan->classes.size(),
+                      plan->ws_elems, 0, 0, 0};
+    RaggedKernel k = ragged_kernel(TFFT_FT_CORRECT);
+    long long grid = (long long)k.blocks_per_cu * plan->cus;
+    v[5] = grid < plan->n_items ? grid : plan->n_items;
+    if (n > 6) {
+        RQueue q{};
+        hipError_t err = hipMemcpy(&q, plan->d_queue, sizeof(q), hipMemcpyDeviceToHost);
+        if (err != hipSuccess) return hip_fail(err);
+        v[6] = (long long)q.err;
+        v[7] = (long long)q.next;
+    }
+    for (int i = 0; i < n && i < 8; ++i) info[i] = v[i];
+    return TFFT_OK;
+}
+
+int tfft_c2c_ragged(tfft_ragged_plan plan, const void* x, void* y, int dir, int unit_scale,
+                    int mode, int ft_mode, tfft_ft_counts* counts, void* hip_stream) {
+    if (!plan) return TFFT_EINVAL;
+    if (dir != TFFT_FORWARD && dir != TFFT_INVERSE) return TFFT_EINVAL;
+    if (mode != TFFT_RAGGED_PERSISTENT && mode != TFFT_RAGGED_PER_SIZE) return TFFT_EINVAL;
+    if (ft_mode < TFFT_FT_OFF || ft_mode > TFFT_FT_CORRECT) return TFFT_EINVAL;
+    if (plan->total == 0) return TFFT_OK;
+    if (!x || !y) return TFFT_EINVAL;
+    if (ft_mode != TFFT_FT_OFF && !counts) return TFFT_EINVAL;
+    if (((uintptr_t)x % sizeof(float2)) || ((uintptr_t)y % sizeof(float2))) return TFFT_EALIGN;
+    const char* xb = static_cast<const char*>(x);
+    const char* yb = static_cast<const char*>(y);
+    const size_t bytes = (size_t)plan->total * sizeof(float2);
+    if (xb != yb && xb < yb + bytes && yb < xb + bytes) return TFFT_EINVAL;
+    // correction re-reads the inputs of single-pass and column-pass groups
+    if (x == y && ft_mode == TFFT_FT_CORRECT) return TFFT_EINVAL;
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    std::lock_guard<std::mutex> lk(g_mu);
+    ensure_registry();
+    if (current_device() != plan->device) return TFFT_EINVAL;
+    Inject inj = g_inj;
+    if (inj.armed) {
+        if (inj.precision != plan->precision || inj.signal >= plan->count ||
+            inj.element >= plan->sizes[(size_t)inj.signal])
+            return TFFT_EINVAL;
+    }
+    int rc = ragged_exec(plan, x, y, dir, unit_scale, mode, ft_mode, counts, inj, stream);
+    if (rc == TFFT_OK) g_inj = Inject{};   // one-shot
+    return rc;
+}
 
 }  // extern "C"

@@ -80,13 +80,13 @@ template <class V> struct KArgs {
     int stats;            // 1: record max |D0| / tau over groups (calibration)
     int x_intact;         // 1: inputs can be re-read on the error path
     int tiles;            // workgroups per signal group (tile geometries)
-    // Optional indirection (ragged batches): element offset of local signal s
-    // in x and in y, and its global index for counters and injection.  When
-    // null, signal s starts at s * N and its global index is sig_base + s.
+    // Indirection (ragged batches, kernels built with IND): element offset of
+    // local signal s in x and in y, and its global index for counters and
+    // injection.  Without IND, signal s starts at s * N and its global index
+    // is sig_base + s.
     const long long* in_tab;
     const long long* out_tab;
     const long long* id_tab;
-    int xcd_order;        // 1: renumber tile workgroups XCD-major (regular launches)
 };
 
 // Compile-time plan: kind, sub-length Ns, E elements per lane, WC = waves per
@@ -231,7 +231,7 @@ template <class R> __device__ __forceinline__ bool cfin(R x, R y, R cap) {
 // ---------------------------------------------------------------------------
 // Geometry: lane -> (slot, t), addressing, reductions over a slot.
 // ---------------------------------------------------------------------------
-template <class V, class PL> struct Geo {
+template <class V, class PL, bool IND> struct Geo {
     using R = typename RealOf<V>::type;
     static constexpr int E = PL::E, P = PL::P, Ns = PL::Ns, C = PL::C;
     static constexpr bool BLOCK = PL::MULTI_WAVE;
@@ -242,9 +242,10 @@ template <class V, class PL> struct Geo {
     int line;            // tiles: column n2 (pass A) or row k1 (pass B)
     int lds_off;         // single: start of the slot's LDS region
     int par = 0;         // which half of the reduction scratch the next reduce uses
+    int tid;             // lane in the workgroup
 
-    __device__ __forceinline__ Geo(const KArgs<V>& a, long long block, long long nblocks) {
-        const int tid = threadIdx.x;
+    __device__ __forceinline__ Geo(const KArgs<V>& a, long long block, long long nblocks, int tid_)
+        : tid(tid_) {
         if constexpr (PL::KIND == kSingle) {
             const int lane = tid % kWave, wave = tid / kWave;
             if constexpr (P > kWave) {
@@ -271,7 +272,7 @@ template <class V, class PL> struct Geo {
             // neighbouring tiles share cache lines
             long long bid = block;
             const long long G = nblocks;
-            if (a.xcd_order && (G & 7) == 0) bid = (bid & 7) * (G >> 3) + (bid >> 3);
+            if (!IND && (G & 7) == 0) bid = (bid & 7) * (G >> 3) + (bid >> 3);
             const long long tile = bid % a.tiles;   // tiles of one signal group are consecutive
             const long long grp = bid / a.tiles;
             line = (int)(tile * C + slot);
@@ -282,13 +283,16 @@ template <class V, class PL> struct Geo {
     __device__ __forceinline__ long long sig(int b) const { return sig0 + (long long)b * sig_step; }
     // element offsets of input element m / output element k of signal s
     __device__ __forceinline__ long long in_base(const KArgs<V>& a, long long s) const {
-        return a.in_tab ? a.in_tab[s] : s * a.N;
+        if constexpr (IND) return a.in_tab[s];
+        else return s * a.N;
     }
     __device__ __forceinline__ long long out_base(const KArgs<V>& a, long long s) const {
-        return a.out_tab ? a.out_tab[s] : s * a.N;
+        if constexpr (IND) return a.out_tab[s];
+        else return s * a.N;
     }
     __device__ __forceinline__ long long gid(const KArgs<V>& a, long long s) const {
-        return a.id_tab ? a.id_tab[s] : a.sig_base + s;
+        if constexpr (IND) return a.id_tab[s];
+        else return a.sig_base + s;
     }
     __device__ __forceinline__ long long in_off(const KArgs<V>& a, long long s, int m) const {
         if constexpr (PL::KIND == kSingle) return in_base(a, s) + m;
@@ -333,7 +337,7 @@ template <class V, class PL> struct Geo {
             if constexpr (P > kWave) {
                 // two alternating halves: a half is rewritten only after the
                 // barrier of the next reduction, when all its readers are done
-                const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+                const int wave = tid / kWave, lane = tid % kWave;
                 T* sc = scratch + par * (K * PL::WAVES);
                 par ^= 1;
                 if (lane == 0) {
@@ -355,7 +359,7 @@ template <class V, class PL> struct Geo {
 #pragma unroll
             for (int i = 0; i < K; ++i) v[i] = xor_reduce<C, C * TW, Op>(v[i]);
             if constexpr (PL::MULTI_WAVE) {
-                const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+                const int wave = tid / kWave, lane = tid % kWave;
                 T* sc = scratch + par * (K * PL::WAVES * C);
                 par ^= 1;
                 if (lane < C) {
@@ -395,8 +399,46 @@ template <class V, class PL, int FT> struct Smem {
     static constexpr int BYTES = PL::LDS_DATA * (int)sizeof(V) + RED * (int)sizeof(R);
 };
 
+// Buffers that other workgroups of the same launch read back (the persistent
+// ragged kernel's workspace) are accessed coherently at device scope: each
+// XCD has its own L2, and a plain store may sit there unseen by the others.
+// COH bit 0: stores to y (and reads of y back) are coherent; bit 1: loads
+// from x are coherent.  Relaxed device-scope atomics give exactly that per
+// access, without whole-cache write-back or invalidation.
+template <class V> __device__ __forceinline__ V ld_coh(const V* p) {
+    static_assert(sizeof(V) % 8 == 0, "complex elements are whole 8-byte words");
+    unsigned long long w[sizeof(V) / 8];
+    unsigned long long* q = reinterpret_cast<unsigned long long*>(const_cast<V*>(p));
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(V) / 8); ++i)
+        w[i] = __hip_atomic_load(q + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    V v;
+    __builtin_memcpy(&v, w, sizeof(V));
+    return v;
+}
+template <class V> __device__ __forceinline__ void st_coh(V* p, const V& v) {
+    unsigned long long w[sizeof(V) / 8];
+    __builtin_memcpy(w, &v, sizeof(V));
+    unsigned long long* q = reinterpret_cast<unsigned long long*>(p);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(V) / 8); ++i)
+        __hip_atomic_store(q + i, w[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <int COH, class V> __device__ __forceinline__ V ld_x(const V* x, long long i) {
+    if constexpr ((COH & 2) != 0) return ld_coh(x + i);
+    else return x[i];
+}
+template <int COH, class V> __device__ __forceinline__ V ld_y(const V* y, long long i) {
+    if constexpr ((COH & 1) != 0) return ld_coh(y + i);
+    else return y[i];
+}
+template <int COH, class V> __device__ __forceinline__ void st_y(V* y, long long i, const V& v) {
+    if constexpr ((COH & 1) != 0) st_coh(y + i, v);
+    else y[i] = v;
+}
+
 // One workgroup's share of a transform: block `block` of `nblocks`.
-template <class V, class PL, int FT, int... Rs>
+template <class V, class PL, int FT, bool IND, int COH, int... Rs>
 __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict__ y, const KArgs<V>& a,
                                          long long block, long long nblocks, char* smem) {
     using R = typename RealOf<V>::type;
@@ -405,7 +447,11 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
     V* lds = reinterpret_cast<V*>(smem);
     R* red = reinterpret_cast<R*>(smem + PL::LDS_DATA * sizeof(V));
 
-    Geo<V, PL> g(a, block, nblocks);
+    // An opaque copy of the lane index: a persistent caller runs this body in
+    // a loop, and nothing derived from the lane may be hoisted out of it.
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    Geo<V, PL, IND> g(a, block, nblocks, tid);
     const auto li = g.lidx();
     constexpr bool KEEP_XS = FT == 3;   // in place: inputs are gone after the store
     const int t = g.t;
@@ -440,7 +486,7 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
         asm volatile("" : "+v"(li));
         if (valid) {
 #pragma unroll
-            for (int r = 0; r < E; ++r) reg[r] = x[g.in_off(a, s, t + P * r)];
+            for (int r = 0; r < E; ++r) reg[r] = ld_x<COH>(x, g.in_off(a, s, t + P * r));
         } else {
 #pragma unroll
             for (int r = 0; r < E; ++r) reg[r] = V{0, 0};
@@ -499,7 +545,7 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
             for (int r = 0; r < E; ++r) {
                 V v = reg[r];
                 if (a.conj_out) v.y = -v.y;
-                y[g.out_off(a, s, t + P * r)] = V{v.x * a.scale, v.y * a.scale};
+                st_y<COH>(y, g.out_off(a, s, t + P * r), V{v.x * a.scale, v.y * a.scale});
             }
         }
     }
@@ -581,12 +627,12 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
                 if (vb) {
 #pragma unroll
                     for (int r = 0; r < E; ++r) {
-                        V xv = x[g.in_off(a, sb, t + P * r)];
+                        V xv = ld_x<COH>(x, g.in_off(a, sb, t + P * r));
                         if (a.conj_in) xv.y = -xv.y;
                         V av = aw[r];
                         if constexpr (PL::KIND == kRowPass) av = cmul(av, g.twiddle(a, t + P * r));
                         p = cadd(p, cmul(av, xv));
-                        V yv = y[g.out_off(a, sb, t + P * r)];
+                        V yv = ld_y<COH>(y, g.out_off(a, sb, t + P * r));
                         if (a.conj_out) yv.y = -yv.y;
                         bucket[(P * r) % M] = cadd(bucket[(P * r) % M], V{yv.x / a.scale, yv.y / a.scale});
                     }
@@ -626,7 +672,7 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
                         for (int b = 0; b < a.T; ++b) {
                             const long long sb = g.sig(b);
                             if (sb >= a.batch) continue;
-                            V xv = x[g.in_off(a, sb, t + P * r)];
+                            V xv = ld_x<COH>(x, g.in_off(a, sb, t + P * r));
                             if (a.conj_in) xv.y = -xv.y;
                             acc = cadd(acc, xv);
                         }
@@ -642,7 +688,7 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
                     for (int b = 0; b < a.T; ++b) {
                         const long long sb = g.sig(b);
                         if (sb >= a.batch || b == skip) continue;
-                        V yv = y[g.out_off(a, sb, t + P * r)];
+                        V yv = ld_y<COH>(y, g.out_off(a, sb, t + P * r));
                         if (a.conj_out) yv.y = -yv.y;
                         acc = V{acc.x - yv.x / a.scale, acc.y - yv.y / a.scale};
                     }
@@ -682,8 +728,8 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
                         V cc = corr_elem(r, -1);
                         if (a.conj_out) cc.y = -cc.y;
                         const long long o = g.out_off(a, sstar, t + P * r);
-                        const V old = y[o];
-                        y[o] = V{old.x + a.scale * cc.x, old.y + a.scale * cc.y};
+                        const V old = ld_y<COH>(y, o);
+                        st_y<COH>(y, o, V{old.x + a.scale * cc.x, old.y + a.scale * cc.y});
                     }
                 } else if (action == 2) {
                     // y_b* = scale * cj(W x_s - sum_{b != b*} y_b)
@@ -693,7 +739,7 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
                         if (a.conj_out) vv.y = -vv.y;
                         vv = V{a.scale * vv.x, a.scale * vv.y};
                         rebuilt_ok = rebuilt_ok && cfin(vv.x, vv.y, a.cap);
-                        y[g.out_off(a, sstar, t + P * r)] = vv;
+                        st_y<COH>(y, g.out_off(a, sstar, t + P * r), vv);
                     }
                 }
                 unsigned badv[1] = {(action == 2 && !rebuilt_ok) ? 1u : 0u};
@@ -715,11 +761,11 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
     }
 }
 
-template <class V, class PL, int FT, int... Rs>
+template <class V, class PL, int FT, bool IND, int... Rs>
 __global__ __launch_bounds__(PL::THREADS) void k_fft(const V* __restrict__ x, V* __restrict__ y,
                                                      KArgs<V> a) {
     __shared__ __align__(16) char smem[Smem<V, PL, FT>::BYTES];
-    fft_body<V, PL, FT, Rs...>(x, y, a, blockIdx.x, gridDim.x, smem);
+    fft_body<V, PL, FT, IND, 0, Rs...>(x, y, a, blockIdx.x, gridDim.x, smem);
 }
 
 }  // namespace tfft

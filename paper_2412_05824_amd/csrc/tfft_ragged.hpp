@@ -5,11 +5,11 @@
 // into "classes" (one per size and pass) and a list of work items, ordered
 // column passes first, then single-pass groups, then row passes.  Workgroups
 // take items from an atomic queue in that order; a row-pass item first waits
-// until every column-pass item of its signal has finished (a per-signal
-// counter), which always happens because those items were handed out earlier
-// and never wait themselves.  The queue and the counters reset themselves at
-// the end of the launch, so the launch can be replayed from a captured graph
-// without any memset node.
+// until every column-pass item of its group of signals has finished (a
+// per-group counter), which always happens because those items were handed
+// out earlier and never wait themselves.  The queue and the counters reset
+// themselves at the end of the launch, so the launch can be replayed from a
+// captured graph without any memset node.
 #pragma once
 
 #include "tfft_registry.hpp"
@@ -17,18 +17,19 @@
 namespace tfft {
 
 constexpr int kRaggedThreads = 256;
+constexpr int kRaggedSlotBytes = 16;   // LDS slot for the item index, ahead of the plan's LDS
 
 struct RClass {
-    KArgs<float2> args;      // batch = signals of the class, tables per class
+    KArgs<float2> args;      // batch = signals of the class, per-signal offset tables
     int plan;                // index into the ragged plan list
     int final_pass;          // 1: writes the transform's output (single or row pass)
     int src_ws, dst_ws;      // 1: read from / write to the workspace instead of x / y
     int nblocks;             // grid of the class
-    int tiles;               // workgroups per signal (column/row passes)
-    int cnt_base;            // first per-signal counter of this class (-1: none)
-    int need;                // row pass: column-pass workgroups per signal to wait for
-    int signal_after;        // column pass: 1 = bump the signal's counter when done
-    int pair_tiles_b;        // column pass: row-pass workgroups per signal (for resets)
+    int tiles;               // workgroups per group of signals (column / row passes)
+    int cnt_base;            // first per-group counter of this class (-1: none)
+    int need;                // row pass: column-pass workgroups per group to wait for
+    int signal_after;        // column pass: 1 = bump the group's counter when done
+    int pad;
 };
 
 struct RItem {
@@ -39,34 +40,50 @@ struct RItem {
 struct RQueue {
     unsigned long long next;   // next item to hand out
     unsigned long long done;   // workgroups that have left the loop
+    unsigned long long err;    // bit 0: a row-pass wait gave up (counters out of step)
+    unsigned long long pad;
 };
 
-struct RaggedArgs {
-    // per call
-    int conj;                  // 1: inverse direction
-    int unit_scale;            // 1: scale 1 (else 1 forward, 1/N inverse)
-    FtCounts* counts;
-    long long inj_signal;      // global signal index (-1: none)
-    long long inj_elem;
-    int inj_part, inj_bit;
-    int stats;
-    // per plan
+// Device-resident description of one ragged plan, written once by the host.
+struct RaggedDesc {
     const RClass* classes;
     const RItem* items;
     long long n_items;
     RQueue* q;
-    unsigned* cnt_a;           // per signal: finished column-pass workgroups
-    unsigned* cnt_b;           // per signal: row-pass workgroups that saw them all
-    float2* ws;                // workspace for the column-pass results
+    unsigned* cnt_a;           // per group: finished column-pass workgroups
+    unsigned* cnt_b;           // per group: finished row-pass workgroups
+    float2* ws;                // column-pass results of the two-pass signals
 };
 
-using RaggedLaunchFn = hipError_t (*)(const void* x, void* y, const RaggedArgs& ra, int grid,
+// Per-launch arguments.
+struct RaggedCall {
+    const float2* x;
+    float2* y;
+    FtCounts* counts;
+    long long inj_signal;      // global signal index (-1: none)
+    long long inj_elem;
+    int inj_part, inj_bit;
+    int conj;                  // 1: inverse direction
+    int unit_scale;            // 1: scale 1 (else 1 forward, 1/N inverse)
+    int stats;
+    int pad;
+};
+
+using RaggedLaunchFn = hipError_t (*)(const RaggedCall& c, const RaggedDesc* d, int grid,
                                       hipStream_t stream);
 
-// plan list shared by the registry and the persistent kernel (defined in
-// inst_ragged.hip)
-void register_fp32_ragged(std::vector<KernelEntry>& out);
-RaggedLaunchFn ragged_launcher(int ft);
-int ragged_max_blocks_per_cu(int ft);
+struct RaggedKernel {
+    RaggedLaunchFn launch;
+    int lds_bytes;        // dynamic LDS per workgroup
+    int blocks_per_cu;    // resident workgroups per CU (0: query failed)
+};
+
+// registry entries of the ragged plans (k_fft with offset tables: the
+// per-size launches) and the persistent kernel per ABFT mode
+void register_fp32_ragged_single(std::vector<KernelEntry>& out);
+void register_fp32_ragged_tiles(std::vector<KernelEntry>& out);
+RaggedKernel ragged_kernel_ft0();
+RaggedKernel ragged_kernel_ft1();
+RaggedKernel ragged_kernel_ft2();
 
 }  // namespace tfft

@@ -1,0 +1,189 @@
+// tfft_ragged_kernel.hpp -- the persistent kernel for ragged batches.
+//
+// Workgroups pull work items from an atomic queue until it is empty and run
+// the item's plan through a switch over the ragged plan list, every case
+// inlined.  Descriptors are read through wave-uniform constant-space
+// pointers, so the per-class arguments sit in scalar registers as kernel
+// arguments do in a plain launch.  All plans share one dynamic LDS buffer,
+// preceded by a slot for the item index.  Included once per ABFT mode
+// (inst_ragged_ft*.hip) so the three kernels compile in parallel.
+#pragma once
+
+#include "tfft_ragged.hpp"
+#include "tfft_ragged_plans.hpp"
+
+namespace tfft {
+
+extern __shared__ __align__(16) char tfft_ragged_smem[];
+
+template <int FT> constexpr int ragged_plan_smem() {
+    int m = 0;
+#define TFFT_SMEM_MAX(id, kind, Ns, E, WC, B, ...)                                                   \
+    {                                                                                                \
+        constexpr int b = Smem<float2, TFFT_PLAN_T(id, kind, Ns, E, WC, B, __VA_ARGS__), FT>::BYTES; \
+        m = m > b ? m : b;                                                                           \
+    }
+    TFFT_RAGGED_PLANS(TFFT_SMEM_MAX)
+#undef TFFT_SMEM_MAX
+    return m;
+}
+template <int FT> constexpr int ragged_smem() { return kRaggedSlotBytes + ragged_plan_smem<FT>(); }
+static_assert(ragged_smem<2>() <= 65536, "ragged plans must fit 64 KiB of LDS");
+
+#define TFFT_CHECK_WIDTH(id, kind, Ns, E, WC, B, ...)                                              \
+    static_assert(TFFT_PLAN_T(id, kind, Ns, E, WC, B, __VA_ARGS__)::THREADS == kRaggedThreads, \
+                  "every ragged plan runs 256-lane workgroups");
+TFFT_RAGGED_PLANS(TFFT_CHECK_WIDTH)
+#undef TFFT_CHECK_WIDTH
+
+// ---- wave-uniform values and constant-space views ----
+template <class T> using cptr = const __attribute__((address_space(4))) T*;
+
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ long long uni(long long v) {
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)v);
+    const unsigned hi =
+        (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)((unsigned long long)v >> 32));
+    return (long long)(((unsigned long long)hi << 32) | lo);
+}
+template <class T> __device__ __forceinline__ cptr<T> as_const(const T* p) {
+    return (cptr<T>)(unsigned long long)uni(reinterpret_cast<long long>(p));
+}
+// copy of a descriptor from constant space (scalar loads)
+template <class T> __device__ __forceinline__ T cload(cptr<T> p) {
+    static_assert(sizeof(T) % 4 == 0, "descriptors are whole dwords");
+    T v;
+    unsigned* dv = reinterpret_cast<unsigned*>(&v);
+    const cptr<unsigned> s = (cptr<unsigned>)p;
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) dv[i] = s[i];
+    return v;
+}
+
+// Publish thread 0's item index to the whole workgroup.  The leading
+// barrier also ends the previous item's use of the LDS buffer.
+__device__ __forceinline__ long long share_item(long long mine) {
+    volatile long long* slot = reinterpret_cast<volatile long long*>(tfft_ragged_smem);
+    __syncthreads();
+    if (threadIdx.x == 0) *slot = mine;
+    __syncthreads();
+    return uni(*slot);
+}
+
+// Upper bound on the polls of one row-pass wait (a poll is a device-scope
+// load plus a short sleep, about a microsecond): far beyond any column pass,
+// so it only ends a wait whose counters are out of step.  It sets the error
+// bit, and every later wait of the launch gives up at once, so even a broken
+// schedule drains the queue in bounded time instead of hanging.
+constexpr unsigned kMaxPolls = 1u << 20;
+
+// One work item.  Column passes write the workspace with coherent stores and
+// row passes read it with coherent loads, so handing results from one pass
+// to the other needs no cache-wide write-back or invalidation: the column
+// pass waits for its stores to complete before it counts itself done, and a
+// row pass starts loading only after every count of its group is in.
+template <class PL, int FT, int... Rs>
+__device__ __forceinline__ void ragged_step(const RaggedCall& c, const RaggedDesc& d,
+                                            cptr<RClass> cl, int blk) {
+    constexpr int COH = PL::KIND == kColPass ? 1 : PL::KIND == kRowPass ? 2 : 0;
+    const int tiles = cl->tiles;
+    const int need = cl->need;
+    const int grp = tiles > 0 ? blk / tiles : 0;
+    const int cnt = cl->cnt_base + grp;
+    if constexpr (PL::KIND == kRowPass) {
+        // every column-pass workgroup of this group has finished
+        if (threadIdx.x == 0) {
+            unsigned polls = 0;
+            while (__hip_atomic_load(&d.cnt_a[cnt], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+                   (unsigned)need) {
+                if (++polls > kMaxPolls ||
+                    __hip_atomic_load(&d.q->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0ull) {
+                    atomicOr(&d.q->err, 1ull);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+            // the last row-pass workgroup of the group resets both counters
+            // for the next launch; the others have all passed their wait
+            if (atomicAdd(&d.cnt_b[cnt], 1u) == (unsigned)(tiles - 1)) {
+                atomicExch(&d.cnt_a[cnt], 0u);
+                atomicExch(&d.cnt_b[cnt], 0u);
+            }
+        }
+        __syncthreads();
+    }
+    KArgs<float2> ka = cload(&cl->args);
+    const int final_pass = cl->final_pass;
+    ka.conj_in = PL::KIND == kRowPass ? 0 : c.conj;
+    ka.conj_out = final_pass ? c.conj : 0;
+    ka.scale = (final_pass && c.conj && !c.unit_scale) ? 1.0f / (float)ka.N : 1.0f;
+    ka.counts = c.counts;
+    ka.stats = c.stats;
+    ka.inj_signal = final_pass ? c.inj_signal : -1;
+    ka.inj_elem = c.inj_elem;
+    ka.inj_part = c.inj_part;
+    ka.inj_bit = c.inj_bit;
+    const float2* src = PL::KIND == kRowPass ? d.ws : c.x;
+    float2* dst = PL::KIND == kColPass ? d.ws : c.y;
+    fft_body<float2, PL, FT, true, COH, Rs...>(src, dst, ka, blk, cl->nblocks,
+                                               tfft_ragged_smem + kRaggedSlotBytes);
+    if constexpr (PL::KIND == kColPass) {
+        __builtin_amdgcn_s_waitcnt(0);   // this lane's workspace stores are complete
+        __syncthreads();
+        if (threadIdx.x == 0) atomicAdd(&d.cnt_a[cnt], 1u);
+    }
+}
+
+template <int FT>
+__global__ __launch_bounds__(kRaggedThreads) void k_ragged(RaggedCall c, const RaggedDesc* dp) {
+    const RaggedDesc d = cload(as_const(dp));
+    long long item = share_item(threadIdx.x == 0 ? (long long)atomicAdd(&d.q->next, 1ull) : 0);
+    while (item < d.n_items) {
+        // take the next item now; its index is waited for only after this one.
+        // Column-pass items all precede row-pass items in the queue, so an
+        // item taken while a row pass waits is never one it waits for.
+        unsigned long long pre = 0;
+        if (threadIdx.x == 0) pre = atomicAdd(&d.q->next, 1ull);
+        const RItem it = cload(as_const(d.items) + item);
+        cptr<RClass> cl = as_const(d.classes) + it.cls;
+        switch (cl->plan) {
+#define TFFT_CASE(id, kind, Ns, E, WC, B, ...)                                                 \
+    case id:                                                                                    \
+        ragged_step<TFFT_PLAN_T(id, kind, Ns, E, WC, B, __VA_ARGS__), FT, __VA_ARGS__>(c, d, cl, \
+                                                                                      it.blk);   \
+        break;
+            TFFT_RAGGED_PLANS(TFFT_CASE)
+#undef TFFT_CASE
+            default:   // not a plan of this list: the host never queues one
+                break;
+        }
+        item = share_item((long long)pre);
+    }
+    // the last workgroup out resets the queue for the next launch
+    if (threadIdx.x == 0) {
+        if (atomicAdd(&d.q->done, 1ull) == (unsigned long long)gridDim.x - 1ull) {
+            atomicExch(&d.q->next, 0ull);
+            atomicExch(&d.q->done, 0ull);
+        }
+    }
+}
+
+template <int FT>
+hipError_t launch_ragged(const RaggedCall& c, const RaggedDesc* d, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((k_ragged<FT>), dim3(grid), dim3(kRaggedThreads), ragged_smem<FT>(), s, c, d);
+    return hipGetLastError();
+}
+
+template <int FT> RaggedKernel make_ragged_kernel() {
+    RaggedKernel k{};
+    k.launch = &launch_ragged<FT>;
+    k.lds_bytes = ragged_smem<FT>();
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_ragged<FT>, kRaggedThreads,
+                                                     ragged_smem<FT>()) != hipSuccess)
+        n = 0;
+    k.blocks_per_cu = n;
+    return k;
+}
+
+}  // namespace tfft

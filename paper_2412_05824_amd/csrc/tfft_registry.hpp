@@ -12,6 +12,8 @@ namespace tfft {
 using LaunchFn = hipError_t (*)(const void* x, void* y, const void* kargs, long long grid,
                                 hipStream_t stream);
 
+constexpr int kMaxStages = 12;   // radix stages a registered plan may have
+
 struct KernelEntry {
     int precision;          // 0 fp32, 1 fp64
     int kind;               // kSingle, kColPass, kRowPass
@@ -20,20 +22,20 @@ struct KernelEntry {
     int E, P, threads;      // elements per lane, lanes per slot, lanes per workgroup
     int slots_per_block;    // sub-signals per workgroup per transaction
     int n_stages;
-    int radices[8];
+    int radices[kMaxStages];
     LaunchFn launch;
     int ragged_id;          // index in the ragged plan list (-1: regular plan)
 };
 
-template <class V, class PL, int FT, int... Rs>
+template <class V, class PL, int FT, bool IND, int... Rs>
 hipError_t launch_fft(const void* x, void* y, const void* ka, long long grid, hipStream_t s) {
     const KArgs<V>& a = *static_cast<const KArgs<V>*>(ka);
-    hipLaunchKernelGGL((k_fft<V, PL, FT, Rs...>), dim3((unsigned)grid), dim3(PL::THREADS), 0, s,
+    hipLaunchKernelGGL((k_fft<V, PL, FT, IND, Rs...>), dim3((unsigned)grid), dim3(PL::THREADS), 0, s,
                        static_cast<const V*>(x), static_cast<V*>(y), a);
     return hipGetLastError();
 }
 
-template <class V, class PL, int FT, int... Rs> KernelEntry make_entry(int precision) {
+template <class V, class PL, int FT, bool IND, int... Rs> KernelEntry make_entry(int precision) {
     KernelEntry e{};
     e.precision = precision;
     e.kind = PL::KIND;
@@ -44,9 +46,10 @@ template <class V, class PL, int FT, int... Rs> KernelEntry make_entry(int preci
     e.threads = PL::THREADS;
     e.slots_per_block = PL::SLOTS;
     const int rs[] = {Rs...};
+    static_assert(sizeof...(Rs) <= kMaxStages, "too many stages for the registry");
     e.n_stages = (int)sizeof...(Rs);
     for (int i = 0; i < e.n_stages; ++i) e.radices[i] = rs[i];
-    e.launch = &launch_fft<V, PL, FT, Rs...>;
+    e.launch = &launch_fft<V, PL, FT, IND, Rs...>;
     e.ragged_id = -1;
     return e;
 }
@@ -56,10 +59,10 @@ template <class V, class PL, int FT, int... Rs> KernelEntry make_entry(int preci
 template <class V, int KIND, int Ns, int E, int WC, int B, int... Rs>
 void add_plan(std::vector<KernelEntry>& out, int precision) {
     using PL = Plan<KIND, Ns, E, WC, B, Rs...>;
-    out.push_back(make_entry<V, PL, 0, Rs...>(precision));
-    out.push_back(make_entry<V, PL, 1, Rs...>(precision));
-    out.push_back(make_entry<V, PL, 2, Rs...>(precision));
-    if constexpr (KIND == kSingle) out.push_back(make_entry<V, PL, 3, Rs...>(precision));
+    out.push_back(make_entry<V, PL, 0, false, Rs...>(precision));
+    out.push_back(make_entry<V, PL, 1, false, Rs...>(precision));
+    out.push_back(make_entry<V, PL, 2, false, Rs...>(precision));
+    if constexpr (KIND == kSingle) out.push_back(make_entry<V, PL, 3, false, Rs...>(precision));
 }
 
 void register_fp32_single(std::vector<KernelEntry>& out);

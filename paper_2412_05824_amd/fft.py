@@ -89,3 +89,102 @@ def get_tuning(N: int, dtype):
     _lib.check(_lib.load().tfft_get_tuning(N, _precision(dtype), ctypes.byref(T), ctypes.byref(k)),
                "tfft_get_tuning")
     return T.value, k.value
+
+
+# ---- ragged batches ----
+RAGGED_PERSISTENT = 0
+RAGGED_PER_SIZE = 1
+_MODES = {"persistent": RAGGED_PERSISTENT, "per_size": RAGGED_PER_SIZE}
+
+
+def ragged_supported(N: int, dtype=torch.complex64) -> bool:
+    return bool(_lib.load().tfft_ragged_supported(N, _precision(dtype)))
+
+
+class RaggedPlan:
+    """A ragged batch: signals of lengths `sizes` packed back to back.
+
+    Built once (allocates device memory, outside any graph capture); each call
+    runs the whole batch either as one persistent launch ("persistent") or as
+    one launch per length and pass ("per_size"), on torch's current stream.
+    """
+
+    def __init__(self, sizes, dtype=torch.complex64, device=None):
+        import ctypes
+        self.sizes = [int(n) for n in sizes]
+        self.dtype = dtype
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        arr = (ctypes.c_longlong * max(1, len(self.sizes)))(*self.sizes)
+        h = ctypes.c_void_p()
+        lib = _lib.load()
+        with torch.cuda.device(self.device):
+            st = lib.tfft_ragged_plan_create(ctypes.byref(h), arr, len(self.sizes), _precision(dtype))
+        _lib.check(st, f"tfft_ragged_plan_create({len(self.sizes)} signals)")
+        self._h = h
+        self.total = sum(self.sizes)
+        self.offsets = [0]
+        for n in self.sizes:
+            self.offsets.append(self.offsets[-1] + n)
+
+    def info(self, device_state: bool = False) -> dict:
+        import ctypes
+        n = 8 if device_state else 6
+        buf = (ctypes.c_longlong * 8)()
+        with torch.cuda.device(self.device):
+            _lib.check(_lib.load().tfft_ragged_plan_info(self._h, buf, n), "tfft_ragged_plan_info")
+        keys = ("signals", "total", "items", "classes", "ws_elems", "grid", "queue_err", "queue_next")
+        return {k: int(buf[i]) for i, k in enumerate(keys[:n])}
+
+    def __call__(self, x: torch.Tensor, out: torch.Tensor | None = None, dir: int = -1,
+                 ft_mode: int = 2, counts: torch.Tensor | None = None, unit_scale: bool = False,
+                 mode: str = "persistent"):
+        if self._h is None:
+            raise RuntimeError("plan was closed")
+        if not x.is_cuda or x.dtype != self.dtype or not x.is_contiguous() or x.numel() != self.total:
+            raise ValueError(f"x must be a contiguous {self.dtype} device tensor of {self.total} elements")
+        if out is None:
+            out = torch.empty_like(x)
+        elif out.dtype != x.dtype or not out.is_contiguous() or out.numel() != self.total or out.device != x.device:
+            raise ValueError("out must match x")
+        if ft_mode != _lib.FT_OFF and counts is None:
+            counts = new_counts(x.device)
+        cptr = counts.data_ptr() if counts is not None else None
+        with torch.cuda.device(x.device):
+            st = _lib.load().tfft_c2c_ragged(self._h, x.data_ptr(), out.data_ptr(), dir,
+                                             1 if unit_scale else 0, _MODES[mode], ft_mode, cptr,
+                                             _stream_ptr(x.device))
+        _lib.check(st, f"tfft_c2c_ragged({len(self.sizes)} signals, mode={mode}, ft={ft_mode})")
+        return out, counts
+
+    def split(self, packed: torch.Tensor) -> list:
+        return [packed[self.offsets[i]:self.offsets[i + 1]] for i in range(len(self.sizes))]
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            with torch.cuda.device(self.device):
+                _lib.load().tfft_ragged_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_ragged_cache: dict = {}
+
+
+def fft_c2c_ragged(packed: torch.Tensor, sizes, dir: int = -1, ft_mode: int = 2,
+                   out: torch.Tensor | None = None, counts: torch.Tensor | None = None,
+                   mode: str = "persistent"):
+    """Transform the signals of lengths `sizes` packed back to back in `packed`.
+
+    Plans are cached per (device, sizes); the first call for a list builds it.
+    """
+    key = (str(packed.device), packed.dtype, tuple(int(n) for n in sizes))
+    plan = _ragged_cache.get(key)
+    if plan is None:
+        plan = RaggedPlan(key[2], dtype=packed.dtype, device=packed.device)
+        _ragged_cache[key] = plan
+    return plan(packed, out=out, dir=dir, ft_mode=ft_mode, counts=counts, mode=mode)

@@ -69,3 +69,32 @@ def test_supported_sizes_and_tuning_roundtrip():
     assert lib.tfft_set_tuning(512, 0, 2, 3.5) == 0
     assert lib.tfft_get_tuning(512, 0, ctypes.byref(T), ctypes.byref(k)) == 0
     assert (T.value, k.value) == (2, 3.5)
+
+
+def test_ragged_route_menu():
+    """Every length of the ragged menu (2^k, 3*2^k, 6 <= k <= 16) has a route,
+    lengths outside it do not; ragged batches are fp32 only."""
+    lib = _lib.load()
+    menu = [1 << k for k in range(6, 18)] + [3 << k for k in range(6, 17)]
+    for n in menu:
+        assert lib.tfft_ragged_supported(n, _lib.FP32) == 1, n
+    for n in (1, 32, 48, 96, 100, 3 << 17, 1 << 18):
+        assert lib.tfft_ragged_supported(n, _lib.FP32) == 0, n
+    assert lib.tfft_ragged_supported(1024, _lib.FP64) == 0
+
+
+def test_ragged_invalid_arguments_rejected_on_host():
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    sizes = (ctypes.c_longlong * 2)(64, 128)
+    assert lib.tfft_ragged_plan_create(None, sizes, 2, _lib.FP32) == _lib.TFFT_EINVAL
+    assert lib.tfft_ragged_plan_create(ctypes.byref(h), None, 2, _lib.FP32) == _lib.TFFT_EINVAL
+    assert lib.tfft_ragged_plan_create(ctypes.byref(h), sizes, -1, _lib.FP32) == _lib.TFFT_EINVAL
+    assert lib.tfft_ragged_plan_create(ctypes.byref(h), sizes, 2, 7) == _lib.TFFT_EINVAL
+    assert lib.tfft_ragged_plan_create(ctypes.byref(h), sizes, 2, _lib.FP64) == _lib.TFFT_EUNSUPPORTED
+    bad = (ctypes.c_longlong * 2)(64, 0)
+    assert lib.tfft_ragged_plan_create(ctypes.byref(h), bad, 2, _lib.FP32) == _lib.TFFT_EINVAL
+    assert lib.tfft_c2c_ragged(None, None, None, -1, 0, 0, 0, None, None) == _lib.TFFT_EINVAL
+    assert lib.tfft_ragged_plan_destroy(None) == _lib.TFFT_EINVAL
+    info = (ctypes.c_longlong * 8)()
+    assert lib.tfft_ragged_plan_info(None, info, 8) == _lib.TFFT_EINVAL
