@@ -113,9 +113,23 @@ int tfft_ragged_plan_destroy(tfft_ragged_plan plan);
 
 /* Up to n values: [0] signals, [1] total elements, [2] work items,
  * [3] classes (lengths x passes), [4] workspace elements, [5] persistent
- * grid; [6] the queue's error bits and [7] its next-item counter (both read
- * from the device with a synchronising copy; 0 and 0 between launches). */
+ * grid, [6] workspace batches and [7] window (elements per half; 0 when the
+ * workspace is flat); [8] the queue's error bits and [9] its next-item
+ * counter (read from the device with a synchronising copy when n > 8; both
+ * 0 between launches). */
 int tfft_ragged_plan_info(tfft_ragged_plan plan, long long* info, int n);
+
+/* Schedule of plans created from now on.  window_elems > 0: the persistent
+ * launch streams the two-pass signals through a workspace ring of two halves
+ * of window_elems elements (batches of whole checksum groups; a column pass
+ * reuses a half once the row passes of the batch before last have read it),
+ * so the intermediate can stay in the 256 MB on-die cache; 0 (default): one
+ * workspace slot per signal, all column passes queued first.  item_elems > 0
+ * sets the elements per work item (default 32768); 0 keeps it.  waves: 3
+ * (default) holds the ABFT kernels to three workgroups per CU (a few values
+ * spill; measured faster); 0 lets the compiler size their registers (two
+ * workgroups per CU).  Per-size launches are unaffected. */
+int tfft_ragged_set_schedule(long long window_elems, long long item_elems, int waves);
 
 /* Execute a plan.
  *   x, y        device buffers of total elements (complex64); x == y only
@@ -156,6 +170,27 @@ int tfft_get_tuning(long long N, int precision, int* T, double* kappa);
  * lives in a library workspace.  Sets the chunk size for (N, precision);
  * 0 keeps the current value. */
 int tfft_set_chunk(long long N, int precision, long long chunk_bytes);
+
+/* Routes.  A length runs either as one single-pass kernel or as a column
+ * pass of length n1 followed by a row pass of length N/n1 (the multi-pass
+ * decomposition of Sec. 3.1).  tfft_routes writes up to cap candidate routes
+ * for (N, precision, ft_mode) into n1_out (1 = single pass, n1 > 1 = that
+ * split) and returns how many exist.  tfft_set_route fixes the route of
+ * (N, precision) (0 = default policy: single pass when built, else the most
+ * balanced split), TFFT_EUNSUPPORTED if that route is not built.
+ * tfft_get_route reports the route tfft_c2c would take now. */
+int tfft_routes(long long N, int precision, int ft_mode, long long* n1_out, int cap);
+int tfft_set_route(long long N, int precision, long long split_n1);
+int tfft_get_route(long long N, int precision, int ft_mode, long long* n1);
+
+/* Load a tuning table (JSON, as written by the autotuner):
+ *   {"entries": [{"precision": "fp32" | "fp64", "N": n, "split_n1": s,
+ *                 "T": t, "kappa": k, "chunk_bytes": b, ...}, ...]}
+ * Each entry sets the fields it names for (N, precision); other keys are
+ * ignored.  All entries are checked before any is applied.  Returns the
+ * number of entries applied, or TFFT_EINVAL (unreadable file, malformed
+ * JSON or value out of range) / TFFT_EUNSUPPORTED (a route not built). */
+int tfft_load_tuning(const char* path);
 
 /* Calibration of the detection threshold (Sec. 5.3 ROC protocol): while on,
  * every ABFT call also records in counts->reserved[0] the largest ratio

@@ -10,6 +10,7 @@ import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtfft.so")
+TUNING_PATH = os.path.join(_HERE, "tuning", "mi355x.json")
 
 TFFT_OK = 0
 TFFT_EINVAL = -1
@@ -40,6 +41,7 @@ SIGNATURES = {
     "tfft_ragged_plan_create": ([ctypes.POINTER(_VP), ctypes.POINTER(_LL), _LL, _I], _I),
     "tfft_ragged_plan_destroy": ([_VP], _I),
     "tfft_ragged_plan_info": ([_VP, ctypes.POINTER(_LL), _I], _I),
+    "tfft_ragged_set_schedule": ([_LL, _LL, _I], _I),
     "tfft_supported": ([_LL, _I], _I),
     "tfft_inject_arm": ([_LL, _LL, _I, _I, _I], _I),
     "tfft_inject_disarm": ([], _I),
@@ -49,6 +51,10 @@ SIGNATURES = {
     "tfft_profile": ([_I], _I),
     "tfft_profile_read": ([ctypes.c_char_p, _LL], _I),
     "tfft_set_chunk": ([_LL, _I, _LL], _I),
+    "tfft_routes": ([_LL, _I, _I, ctypes.POINTER(_LL), _I], _I),
+    "tfft_set_route": ([_LL, _I, _LL], _I),
+    "tfft_get_route": ([_LL, _I, _I, ctypes.POINTER(_LL)], _I),
+    "tfft_load_tuning": ([ctypes.c_char_p], _I),
     "tfft_strerror": ([_I], ctypes.c_char_p),
     "tfft_last_hip_error": ([], _I),
 }
@@ -74,6 +80,11 @@ def load():
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = res
+    # the autotuner's table for this GPU, read by the host runtime
+    if os.environ.get("TFFT_TUNING", "") != "off" and os.path.exists(TUNING_PATH):
+        n = lib.tfft_load_tuning(TUNING_PATH.encode())
+        if n < 0:
+            raise TfftError(n, f"tfft_load_tuning({TUNING_PATH})")
     _lib = lib
     return lib
 

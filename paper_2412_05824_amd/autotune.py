@@ -1,0 +1,155 @@
+"""Offline autotuner: measure every built configuration of each length and
+write the fastest into a JSON tuning table that the library loads
+(tfft_load_tuning).
+
+Per (precision, N) it sweeps:
+  * the route: single pass (when built) or each column/row split n1 x N/n1
+    (the multi-pass decomposition of Sec. 3.1);
+  * T, the transactions per checksum group (Sec. 4.3), limited by the
+    accuracy bound below;
+  * for two-pass routes, the chunk of signals whose intermediate lives in
+    the workspace.
+Each candidate runs with ABFT correction on a 1 GiB seeded batch; it must
+count no detection on fault-free data and agree with the default
+configuration's output to within twice the precision's tolerance (two
+correct transforms differ by at most the sum of their errors).
+
+Accuracy bound on T: a flip just below the detection threshold changes one
+signal by about kappa * u * sqrt(T * log2 Ns) of its norm (Ns the longest
+pass), which must stay under the acceptance tolerance (2e-6 fp32, 1e-13
+fp64), so T <= (tol / (kappa * u))^2 / log2 Ns.
+
+    python -m paper_2412_05824_amd.autotune --out paper_2412_05824_amd/tuning/mi355x.json
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+TOL = {"fp32": 2e-6, "fp64": 1e-13}
+UNIT = {"fp32": 2.0 ** -24, "fp64": 2.0 ** -53}
+KAPPA = {"fp32": 8.0, "fp64": 16.0}
+T_CHOICES = (1, 2, 4, 8, 16)
+CHUNKS_MIB = (16, 32, 64, 128, 256, 512)
+
+
+def max_T(prec: str, longest_pass: int, kappa: float) -> int:
+    lim = (TOL[prec] / (kappa * UNIT[prec])) ** 2 / max(1.0, math.log2(longest_pass))
+    return max(1, int(lim))
+
+
+def _time(fn, torch, reps: int, warmup: int) -> float:
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def tune(precisions, logs, reps=5, warmup=2, total_bytes=1 << 30, log=print):
+    import numpy as np
+    import torch
+
+    import paper_2412_05824_amd as tf
+    from paper_2412_05824_amd import synth
+
+    dev = torch.device("cuda:0")
+    entries = []
+    for prec in precisions:
+        dtype = torch.complex64 if prec == "fp32" else torch.complex128
+        npdt = np.complex64 if prec == "fp32" else np.complex128
+        esize = 8 if prec == "fp32" else 16
+        total = total_bytes // esize
+        x = torch.from_numpy(synth.signals(1, total, seed=4000, dtype=npdt).reshape(-1)).to(dev)
+        y = torch.empty_like(x)
+        ref = torch.empty_like(x)
+        counts = tf.new_counts(dev)
+        for lg in logs:
+            N = 1 << lg
+            if not tf.supported(N, dtype):
+                continue
+            xv, yv, rv = x.view(-1, N), y.view(-1, N), ref.view(-1, N)
+            T0, k0 = tf.get_tuning(N, dtype)
+            tf.set_route(N, dtype, 0)
+            tf.fft_c2c(xv, ft_mode=tf.FT_CORRECT, out=rv, counts=counts)
+            torch.cuda.synchronize()
+            ref_norm = torch.linalg.vector_norm(rv).item()
+            best = None
+            for n1 in tf.routes(N, dtype, tf.FT_CORRECT):
+                longest = N if n1 == 1 else max(n1, N // n1)
+                tmax = max_T(prec, longest, KAPPA[prec])
+                chunks = [None] if n1 == 1 else [c << 20 for c in CHUNKS_MIB]
+                for T in [t for t in T_CHOICES if t <= tmax]:
+                    for chunk in chunks:
+                        tf.set_route(N, dtype, n1)
+                        tf.set_tuning(N, dtype, T, KAPPA[prec])
+                        if chunk:
+                            tf.set_chunk(N, dtype, chunk)
+                        counts.zero_()
+                        ms = _time(lambda: tf.fft_c2c(xv, ft_mode=tf.FT_CORRECT, out=yv, counts=counts),
+                                   torch, reps, warmup)
+                        det = tf.counts_dict(counts)["detected"]
+                        err = torch.linalg.vector_norm(yv - rv).item() / ref_norm
+                        ok = det == 0 and err <= 2 * TOL[prec]
+                        gbs = 2 * total * esize / (ms * 1e-3) / 1e9
+                        log(f"{prec} N={N} n1={n1} T={T} chunk={chunk} {ms:.4f} ms {gbs:.1f} GB/s "
+                            f"err={err:.2e} det={det}{'' if ok else ' REJECTED'}")
+                        if ok and (best is None or ms < best["ms"]):
+                            best = {"precision": prec, "N": N, "split_n1": n1, "T": T,
+                                    "kappa": KAPPA[prec], "ms": round(ms, 5), "gbs": round(gbs, 1)}
+                            if chunk:
+                                best["chunk_bytes"] = chunk
+            # back to the defaults before the next length
+            tf.set_route(N, dtype, 0)
+            tf.set_tuning(N, dtype, T0, k0)
+            tf.set_chunk(N, dtype, 128 << 20)
+            if best:
+                entries.append(best)
+                log(f"best {prec} N={N}: {best}")
+        del x, y, ref
+        torch.cuda.empty_cache()
+    return entries
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--precision", default="fp32,fp64")
+    ap.add_argument("--sizes", default="6-22", help="log2 N range lo-hi or comma list")
+    ap.add_argument("--reps", type=int, default=5)
+    args = ap.parse_args(argv)
+    if "-" in args.sizes:
+        lo, hi = (int(v) for v in args.sizes.split("-"))
+        logs = list(range(lo, hi + 1))
+    else:
+        logs = [int(v) for v in args.sizes.split(",")]
+    import torch
+    t0 = time.time()
+    entries = tune(args.precision.split(","), logs, reps=args.reps,
+                   log=lambda s: print(s, flush=True))
+    doc = {"format": "tfft-tuning-1",
+           "device": torch.cuda.get_device_name(0),
+           "workload": "1 GiB seeded batch per length, forward, ABFT correct",
+           "seconds": round(time.time() - t0, 1),
+           "entries": entries}
+    os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
+    with open(args.out, "w") as f:
+        json.dump(doc, f, indent=1)
+    # the library must accept what was written
+    import paper_2412_05824_amd as tf
+    n = tf.load_tuning(args.out)
+    print(f"wrote {args.out}: {n} entries", flush=True)
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -3,6 +3,9 @@
 
 namespace tfft {
 
-RaggedKernel ragged_kernel_ft0() { return make_ragged_kernel<0>(); }
+RaggedKernel ragged_kernel_ft0(int waves) {
+    (void)waves;   // already at four workgroups per CU
+    return make_ragged_kernel<0, false>();
+}
 
 }  // namespace tfft

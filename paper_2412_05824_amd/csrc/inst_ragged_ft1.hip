@@ -3,6 +3,8 @@
 
 namespace tfft {
 
-RaggedKernel ragged_kernel_ft1() { return make_ragged_kernel<1>(); }
+RaggedKernel ragged_kernel_ft1(int waves) {
+    return waves == 3 ? make_ragged_kernel<1, true>() : make_ragged_kernel<1, false>();
+}
 
 }  // namespace tfft

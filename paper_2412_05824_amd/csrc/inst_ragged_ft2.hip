@@ -3,6 +3,8 @@
 
 namespace tfft {
 
-RaggedKernel ragged_kernel_ft2() { return make_ragged_kernel<2>(); }
+RaggedKernel ragged_kernel_ft2(int waves) {
+    return waves == 3 ? make_ragged_kernel<2, true>() : make_ragged_kernel<2, false>();
+}
 
 }  // namespace tfft

@@ -17,6 +17,7 @@
 #include <mutex>
 #include <string>
 #include <cstdio>
+#include <cstdlib>
 #include <tuple>
 #include <vector>
 
@@ -70,6 +71,8 @@ struct Tuning {
     int T;
     double kappa;
     long long chunk_bytes;
+    long long split_n1;   // route: 0 default (single pass if built, else balanced split),
+                          // 1 single pass, > 1 column pass of this length then row pass
 };
 
 std::mutex g_mu;
@@ -130,19 +133,34 @@ struct Route {
     long long N1 = 0, N2 = 0;
 };
 
-bool route_for(int precision, long long N, int ft, Route* r) {
+// a two-pass split N = n1 * n2 with compiled column and row kernels whose
+// tiles divide the other length
+bool split_ok(int precision, long long N, int ft, long long n1) {
+    if (n1 < 2 || N % n1) return false;
+    const long long n2 = N / n1;
+    const KernelEntry* c = find_entry(precision, kColPass, n1, ft);
+    const KernelEntry* w = find_entry(precision, kRowPass, n2, ft);
+    return c && w && n2 % c->slots_per_block == 0 && n1 % w->slots_per_block == 0;
+}
+
+bool route_for(int precision, long long N, int ft, Route* r, long long split = 0) {
     *r = Route{};
-    if ((r->single = find_entry(precision, kSingle, N, ft))) return true;
-    // balanced split N = N1 * N2 with N1 <= N2, both with tile kernels
-    long long best1 = 0;
-    for (long long n1 = 2; n1 * n1 <= N; n1 <<= 1) {
-        if (N % n1) continue;
-        const long long n2 = N / n1;
-        if (find_entry(precision, kColPass, n1, ft) && find_entry(precision, kRowPass, n2, ft)) best1 = n1;
+    if (split <= 1) {
+        if ((r->single = find_entry(precision, kSingle, N, ft))) return true;
+        if (split == 1) return false;
     }
-    if (!best1) return false;
-    r->N1 = best1;
-    r->N2 = N / best1;
+    long long n1 = 0;
+    if (split > 1) {
+        if (!split_ok(precision, N, ft, split)) return false;
+        n1 = split;
+    } else {
+        // balanced split N = N1 * N2 with N1 <= N2
+        for (long long c = 2; c * c <= N; c <<= 1)
+            if (split_ok(precision, N, ft, c)) n1 = c;
+        if (!n1) return false;
+    }
+    r->N1 = n1;
+    r->N2 = N / n1;
     r->col = find_entry(precision, kColPass, r->N1, ft);
     r->row = find_entry(precision, kRowPass, r->N2, ft);
     return true;
@@ -155,6 +173,7 @@ Tuning default_tuning(int precision, long long N) {
     // under the 2e-6 relative tolerance; fp64 has ample margin.
     Tuning t{};
     t.chunk_bytes = 128ll << 20;
+    t.split_n1 = 0;
     if (precision == TFFT_FP32) {
         t.kappa = 8.0;
         t.T = N <= 128 ? 2 : 1;
@@ -465,15 +484,19 @@ bool ragged_route(long long N, RRoute* r) {
 }
 
 KernelEntry g_ragged_prof_entry[3];   // labels of the persistent launches in the profile
+long long g_ragged_window = 0;        // workspace window of new plans (elements, 0: flat)
+long long g_ragged_item = 32768;      // elements per work item of new plans
+int g_ragged_waves = 3;               // persistent kernel register budget of new plans
 
-RaggedKernel ragged_kernel(int ft) {
-    static RaggedKernel k[3];
-    static bool done[3] = {false, false, false};
-    if (!done[ft]) {
-        k[ft] = ft == 0 ? ragged_kernel_ft0() : ft == 1 ? ragged_kernel_ft1() : ragged_kernel_ft2();
-        done[ft] = true;
+RaggedKernel ragged_kernel(int ft, int waves) {
+    static RaggedKernel k[3][2];
+    static bool done[3][2] = {};
+    const int w = waves == 3 ? 1 : 0;
+    if (!done[ft][w]) {
+        k[ft][w] = ft == 0 ? ragged_kernel_ft0(waves) : ft == 1 ? ragged_kernel_ft1(waves) : ragged_kernel_ft2(waves);
+        done[ft][w] = true;
     }
-    return k[ft];
+    return k[ft][w];
 }
 
 }  // namespace
@@ -483,9 +506,11 @@ struct tfft_ragged_plan_s {
     int precision = TFFT_FP32;
     long long count = 0, total = 0, ws_elems = 0;
     std::vector<long long> sizes;          // host copy, for argument checks
-    std::vector<RClass> classes;           // host copy (per-size launches)
-    std::vector<int> order;                // launch order of the classes (per-size mode)
+    std::vector<RClass> classes;           // host copy (per-size launches, queue order)
     long long n_items = 0;
+    long long n_batches = 0;               // windowed workspace: batches of groups
+    long long window = 0;                  // windowed workspace: elements per half (0: flat)
+    int waves = 0;                         // persistent kernel variant (0 or 3)
     int cus = 0;
     void* buf = nullptr;                   // classes, items, desc, queue, counters, tables
     void* ws = nullptr;                    // column-pass results of the two-pass signals
@@ -503,130 +528,241 @@ int ragged_build(tfft_ragged_plan_s* P, const long long* sizes, long long count)
     for (long long i = 0; i < count; ++i) { xoff[i] = tot; tot += sizes[i]; }
     P->total = tot;
 
-    // classes: one per length (single) or two (column pass, row pass)
+    // one entry per distinct length, longest first
     std::map<long long, std::vector<long long>, std::greater<long long>> by_len;
     for (long long i = 0; i < count; ++i) by_len[sizes[i]].push_back(i);
-    struct Pending { RRoute rt; std::vector<long long> ids; };
-    std::vector<Pending> lens;
+    struct Len {
+        RRoute rt;
+        std::vector<long long> ids;
+        long long N = 0, groups = 0;
+        Tuning tu{};
+        int T = 1;
+        size_t ids_at = 0, xoff_at = 0, wsflat_at = 0, wsring_at = 0;
+        int k_single = 1, k_col = 1, k_row = 1;   // blocks per work item
+        RClass single{}, col{}, row{};
+        int ci_single = -1, ci_col = -1, ci_row = -1;
+    };
+    std::vector<Len> lens;
     for (auto& kv : by_len) {
-        Pending pd;
-        if (!ragged_route(kv.first, &pd.rt)) return TFFT_EUNSUPPORTED;
-        pd.ids = kv.second;
-        lens.push_back(std::move(pd));
+        Len L;
+        if (!ragged_route(kv.first, &L.rt)) return TFFT_EUNSUPPORTED;
+        L.ids = kv.second;
+        L.N = kv.first;
+        L.tu = get_tuning(TFFT_FP32, L.N);
+        L.T = L.tu.T;
+        L.groups = ((long long)L.ids.size() + L.T - 1) / L.T;
+        lens.push_back(std::move(L));
     }
-    // host tables: ids, x offsets, workspace offsets, per length
+    // blocks per work item: about g_ragged_item elements, so that the queue
+    // and descriptor traffic of an item is small next to its data; tile runs
+    // stay inside one group of signals
+    auto per_item = [](const KernelEntry& e, int T, int tiles) {
+        const long long per_block = (long long)e.slots_per_block * T * e.Ns;
+        long long k = g_ragged_item / per_block;
+        if (k < 1) k = 1;
+        if (tiles > 0) {
+            if (k > tiles) k = tiles;
+            while (tiles % k) --k;
+        }
+        return (int)k;
+    };
+
+    // host tables (int64): ids, x offsets, flat and ring workspace offsets
     std::vector<long long> tab;
-    long long ws_tot = 0, groups_tot = 0;
-    struct Made { RClass cl; size_t ids_at, xoff_at, wsoff_at; bool two; };
-    std::vector<Made> made;   // single classes and column passes first, row passes after
-    std::vector<Made> rows;
-    for (Pending& pd : lens) {
-        const long long N = pd.rt.single ? pd.rt.single->Ns : pd.rt.N1 * pd.rt.N2;
-        const long long n = (long long)pd.ids.size();
-        const Tuning tu = get_tuning(TFFT_FP32, N);
-        const size_t ids_at = tab.size();
-        for (long long i : pd.ids) tab.push_back(i);
-        const size_t xoff_at = tab.size();
-        for (long long i : pd.ids) tab.push_back(xoff[i]);
-        const long long groups = (n + tu.T - 1) / tu.T;
-        if (pd.rt.single) {
-            const KernelEntry& e = *pd.rt.single;
+    long long ws_flat = 0, groups_tot = 0, max_group = 0;
+    for (Len& L : lens) {
+        const long long n = (long long)L.ids.size();
+        L.ids_at = tab.size();
+        for (long long i : L.ids) tab.push_back(i);
+        L.xoff_at = tab.size();
+        for (long long i : L.ids) tab.push_back(xoff[i]);
+        if (L.rt.single) {
+            const KernelEntry& e = *L.rt.single;
             SubTables* st = nullptr;
             int rc = get_sub(e, true, &st);
             if (rc != TFFT_OK) return rc;
-            RClass c{};
-            fill_common(c.args, e, *st, tu, nullptr);
+            RClass& c = L.single;
+            fill_common(c.args, e, *st, L.tu, nullptr);
             c.args.batch = n;
-            c.args.N = N;
+            c.args.N = L.N;
             c.args.x_intact = 1;
             c.plan = e.ragged_id;
             c.final_pass = 1;
-            const long long per_block = (long long)e.slots_per_block * tu.T;
+            const long long per_block = (long long)e.slots_per_block * L.T;
             c.nblocks = (int)((n + per_block - 1) / per_block);
             c.cnt_base = -1;
-            made.push_back(Made{c, ids_at, xoff_at, xoff_at, false});
+            L.k_single = per_item(e, L.T, 0);
             continue;
         }
-        const size_t wsoff_at = tab.size();
-        for (long long j = 0; j < n; ++j) { tab.push_back(ws_tot); ws_tot += N; }
+        L.wsflat_at = tab.size();
+        for (long long j = 0; j < n; ++j) { tab.push_back(ws_flat); ws_flat += L.N; }
+        L.wsring_at = tab.size();
+        tab.resize(tab.size() + (size_t)n, 0);   // filled below when windowed
+        max_group = std::max(max_group, (long long)L.T * L.N);
         SubTables *sa = nullptr, *sb = nullptr;
         PassTwiddle* pt = nullptr;
-        int rc = get_sub(*pd.rt.col, true, &sa);
-        if (rc == TFFT_OK) rc = get_sub(*pd.rt.row, true, &sb);
-        if (rc == TFFT_OK) rc = get_pass(TFFT_FP32, N, true, &pt);
+        int rc = get_sub(*L.rt.col, true, &sa);
+        if (rc == TFFT_OK) rc = get_sub(*L.rt.row, true, &sb);
+        if (rc == TFFT_OK) rc = get_pass(TFFT_FP32, L.N, true, &pt);
         if (rc != TFFT_OK) return rc;
-        RClass A{}, B{};
-        fill_common(A.args, *pd.rt.col, *sa, tu, nullptr);
-        fill_common(B.args, *pd.rt.row, *sb, tu, nullptr);
+        RClass& A = L.col;
+        RClass& B = L.row;
+        fill_common(A.args, *L.rt.col, *sa, L.tu, nullptr);
+        fill_common(B.args, *L.rt.row, *sb, L.tu, nullptr);
         for (RClass* k : {&A, &B}) {
             k->args.batch = n;
-            k->args.N = N;
-            k->args.N1 = (int)pd.rt.N1;
-            k->args.N2 = (int)pd.rt.N2;
+            k->args.N = L.N;
+            k->args.N1 = (int)L.rt.N1;
+            k->args.N2 = (int)L.rt.N2;
             k->args.x_intact = 1;
             k->cnt_base = (int)groups_tot;
         }
         B.args.tw_hi = static_cast<const float2*>(pt->hi);
         B.args.tw_lo = static_cast<const float2*>(pt->lo);
         B.args.tw_bits = pt->bits;
-        A.args.tiles = A.tiles = (int)(pd.rt.N2 / pd.rt.col->slots_per_block);
-        B.args.tiles = B.tiles = (int)(pd.rt.N1 / pd.rt.row->slots_per_block);
-        A.plan = pd.rt.col->ragged_id;
-        B.plan = pd.rt.row->ragged_id;
+        A.args.tiles = A.tiles = (int)(L.rt.N2 / L.rt.col->slots_per_block);
+        B.args.tiles = B.tiles = (int)(L.rt.N1 / L.rt.row->slots_per_block);
+        A.plan = L.rt.col->ragged_id;
+        B.plan = L.rt.row->ragged_id;
         A.dst_ws = 1;
         A.signal_after = 1;
         B.src_ws = 1;
         B.final_pass = 1;
-        B.need = A.tiles;
-        A.nblocks = (int)(groups * A.tiles);
-        B.nblocks = (int)(groups * B.tiles);
-        if ((long long)A.nblocks != groups * A.tiles || (long long)B.nblocks != groups * B.tiles)
-            return TFFT_EUNSUPPORTED;
-        groups_tot += groups;
-        // column passes go first in the queue
-        made.insert(made.begin(), Made{A, ids_at, xoff_at, wsoff_at, true});
-        rows.push_back(Made{B, ids_at, wsoff_at, xoff_at, true});
+        L.k_col = per_item(*L.rt.col, L.T, A.tiles);
+        L.k_row = per_item(*L.rt.row, L.T, B.tiles);
+        A.items_per_group = A.tiles / L.k_col;
+        B.items_per_group = B.tiles / L.k_row;
+        B.need = A.items_per_group;
+        if (L.groups * A.tiles > 0x7fffffffLL || L.groups * B.tiles > 0x7fffffffLL) return TFFT_EUNSUPPORTED;
+        A.nblocks = (int)(L.groups * A.tiles);
+        B.nblocks = (int)(L.groups * B.tiles);
+        groups_tot += L.groups;
     }
-    for (Made& m : rows) made.push_back(m);
-    // the column passes were inserted at the front in reverse: largest first
-    {
-        size_t ncol = 0;
-        while (ncol < made.size() && made[ncol].cl.signal_after) ++ncol;
-        std::reverse(made.begin(), made.begin() + ncol);
-    }
-    P->ws_elems = ws_tot;
 
-    // items, in class order
+    // class order (also the per-size launch order): column passes, single
+    // passes, row passes, each longest first
+    std::vector<RClass> classes;
+    for (Len& L : lens)
+        if (!L.rt.single) { L.ci_col = (int)classes.size(); classes.push_back(L.col); }
+    for (Len& L : lens)
+        if (L.rt.single) { L.ci_single = (int)classes.size(); classes.push_back(L.single); }
+    for (Len& L : lens)
+        if (!L.rt.single) { L.ci_row = (int)classes.size(); classes.push_back(L.row); }
+
+    // workspace window: batches of whole groups of at most W elements; batch
+    // k uses half k % 2 of a 2W ring
+    long long W = g_ragged_window;
+    const bool windowed = W > 0 && ws_flat > 0;
+    if (windowed && W < max_group) W = max_group;
+    struct GroupRef { Len* L; long long g; };
+    std::vector<std::vector<GroupRef>> batches;
+    if (windowed) {
+        long long fill = W;   // forces a first batch
+        for (Len& L : lens) {
+            if (L.rt.single) continue;
+            const long long n = (long long)L.ids.size();
+            for (long long g = 0; g < L.groups; ++g) {
+                const long long s0 = g * L.T, s1 = std::min(n, s0 + L.T);
+                const long long e = (s1 - s0) * L.N;
+                if (fill + e > W) { batches.emplace_back(); fill = 0; }
+                const long long base = (long long)((batches.size() - 1) % 2) * W + fill;
+                for (long long j = s0; j < s1; ++j) tab[L.wsring_at + (size_t)j] = base + (j - s0) * L.N;
+                fill += e;
+                batches.back().push_back(GroupRef{&L, g});
+            }
+        }
+    }
+    P->n_batches = (long long)batches.size();
+
+    // items (the queue order)
     std::vector<RItem> items;
-    for (size_t c = 0; c < made.size(); ++c)
-        for (int b = 0; b < made[c].cl.nblocks; ++b) items.push_back(RItem{(int)c, b});
+    auto run = [&](int ci, long long b0, long long b1, int k, int batch, int wait_batch, int wait_need) {
+        for (long long b = b0; b < b1; b += k)
+            items.push_back(RItem{ci, (int)b, (int)std::min<long long>(k, b1 - b), batch, wait_batch,
+                                  wait_need, 0, 0});
+    };
+    std::vector<int> rows_in_batch(batches.size(), 0);
+    for (size_t k = 0; k < batches.size(); ++k)
+        for (GroupRef& gr : batches[k]) rows_in_batch[k] += gr.L->row.items_per_group;
+    auto col_items = [&](size_t k) {
+        const int wb = k >= 2 ? (int)(k - 2) : -1;
+        const int wn = k >= 2 ? rows_in_batch[k - 2] : 0;
+        for (GroupRef& gr : batches[k]) {
+            const long long t = gr.L->col.tiles;
+            run(gr.L->ci_col, gr.g * t, (gr.g + 1) * t, gr.L->k_col, -1, wb, wn);
+        }
+    };
+    auto row_items = [&](size_t k) {
+        for (GroupRef& gr : batches[k]) {
+            const long long t = gr.L->row.tiles;
+            run(gr.L->ci_row, gr.g * t, (gr.g + 1) * t, gr.L->k_row, (int)k, -1, 0);
+        }
+    };
+    if (windowed) {
+        for (size_t k = 0; k < batches.size(); ++k) {
+            col_items(k);
+            if (k >= 1) row_items(k - 1);
+        }
+        if (!batches.empty()) row_items(batches.size() - 1);
+        for (Len& L : lens)
+            if (L.rt.single) run(L.ci_single, 0, L.single.nblocks, L.k_single, -1, -1, 0);
+    } else {
+        for (Len& L : lens)
+            if (!L.rt.single) run(L.ci_col, 0, L.col.nblocks, L.k_col, -1, -1, 0);
+        for (Len& L : lens)
+            if (L.rt.single) run(L.ci_single, 0, L.single.nblocks, L.k_single, -1, -1, 0);
+        for (Len& L : lens)
+            if (!L.rt.single) run(L.ci_row, 0, L.row.nblocks, L.k_row, -1, -1, 0);
+    }
     P->n_items = (long long)items.size();
+    const long long ws_elems = std::max(ws_flat, windowed ? 2 * W : 0ll);
+    P->ws_elems = ws_elems;
+    P->window = windowed ? W : 0;
 
-    // one device buffer: classes | items | desc | queue | cnt_a | cnt_b | tables
+    // one device buffer: classes | items | desc | queue | cnt_a | cnt_b | cnt_r | tables
     auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
     const size_t o_cls = 0;
-    const size_t o_items = al(o_cls + made.size() * sizeof(RClass));
+    const size_t o_items = al(o_cls + classes.size() * sizeof(RClass));
     const size_t o_desc = al(o_items + items.size() * sizeof(RItem));
     const size_t o_q = al(o_desc + sizeof(RaggedDesc));
     const size_t o_ca = al(o_q + sizeof(RQueue));
     const size_t o_cb = al(o_ca + (size_t)groups_tot * sizeof(unsigned));
-    const size_t o_tab = al(o_cb + (size_t)groups_tot * sizeof(unsigned));
+    const size_t o_cr = al(o_cb + (size_t)groups_tot * sizeof(unsigned));
+    const size_t o_tab = al(o_cr + batches.size() * sizeof(unsigned));
     const size_t bytes = al(o_tab + tab.size() * sizeof(long long));
     hipError_t err = hipMalloc(&P->buf, bytes);
     if (err != hipSuccess) { g_last_hip = (int)err; P->buf = nullptr; return TFFT_ENOMEM; }
-    if (ws_tot > 0) {
-        err = hipMalloc(&P->ws, (size_t)ws_tot * sizeof(float2));
+    if (ws_elems > 0) {
+        err = hipMalloc(&P->ws, (size_t)ws_elems * sizeof(float2));
         if (err != hipSuccess) { g_last_hip = (int)err; P->ws = nullptr; return TFFT_ENOMEM; }
     }
     char* base = static_cast<char*>(P->buf);
     const long long* dtab = reinterpret_cast<const long long*>(base + o_tab);
-    for (Made& m : made) {
-        m.cl.args.id_tab = dtab + m.ids_at;
-        m.cl.args.in_tab = dtab + m.xoff_at;
-        m.cl.args.out_tab = dtab + m.wsoff_at;
+    // host copies (per-size launches) use the flat workspace offsets, the
+    // device copies (persistent launch) the ring offsets when windowed
+    std::vector<RClass> dev_classes = classes;
+    for (Len& L : lens) {
+        if (L.rt.single) {
+            for (std::vector<RClass>* v : {&classes, &dev_classes}) {
+                RClass& c = (*v)[L.ci_single];
+                c.args.id_tab = dtab + L.ids_at;
+                c.args.in_tab = c.args.out_tab = dtab + L.xoff_at;
+            }
+            continue;
+        }
+        for (int pass = 0; pass < 2; ++pass) {
+            std::vector<RClass>& v = pass == 0 ? classes : dev_classes;
+            const long long* ws = dtab + ((pass == 1 && windowed) ? L.wsring_at : L.wsflat_at);
+            RClass& A = v[L.ci_col];
+            RClass& B = v[L.ci_row];
+            A.args.id_tab = B.args.id_tab = dtab + L.ids_at;
+            A.args.in_tab = dtab + L.xoff_at;
+            A.args.out_tab = ws;
+            B.args.in_tab = ws;
+            B.args.out_tab = dtab + L.xoff_at;
+        }
     }
-    P->classes.clear();
-    for (Made& m : made) P->classes.push_back(m.cl);
+    P->classes = classes;
     RaggedDesc desc{};
     desc.classes = reinterpret_cast<const RClass*>(base + o_cls);
     desc.items = reinterpret_cast<const RItem*>(base + o_items);
@@ -634,12 +770,14 @@ int ragged_build(tfft_ragged_plan_s* P, const long long* sizes, long long count)
     desc.q = reinterpret_cast<RQueue*>(base + o_q);
     desc.cnt_a = reinterpret_cast<unsigned*>(base + o_ca);
     desc.cnt_b = reinterpret_cast<unsigned*>(base + o_cb);
+    desc.cnt_r = reinterpret_cast<unsigned*>(base + o_cr);
+    desc.n_batches = (long long)batches.size();
     desc.ws = static_cast<float2*>(P->ws);
     P->d_desc = reinterpret_cast<RaggedDesc*>(base + o_desc);
     P->d_queue = desc.q;
 
     std::vector<char> host(bytes, 0);
-    memcpy(host.data() + o_cls, P->classes.data(), P->classes.size() * sizeof(RClass));
+    memcpy(host.data() + o_cls, dev_classes.data(), dev_classes.size() * sizeof(RClass));
     memcpy(host.data() + o_items, items.data(), items.size() * sizeof(RItem));
     memcpy(host.data() + o_desc, &desc, sizeof(desc));
     memcpy(host.data() + o_tab, tab.data(), tab.size() * sizeof(long long));
@@ -668,7 +806,7 @@ int ragged_exec(tfft_ragged_plan_s* P, const void* x, void* y, int dir, int unit
     c.stats = g_stats ? 1 : 0;
     if (P->n_items == 0) return TFFT_OK;
     if (mode == TFFT_RAGGED_PERSISTENT) {
-        const RaggedKernel k = ragged_kernel(ft);
+        const RaggedKernel k = ragged_kernel(ft, P->waves);
         if (!k.launch || k.blocks_per_cu <= 0) return TFFT_EUNSUPPORTED;
         long long grid = (long long)k.blocks_per_cu * P->cus;
         if (grid > P->n_items) grid = P->n_items;
@@ -715,6 +853,120 @@ int ragged_exec(tfft_ragged_plan_s* P, const void* x, void* y, int dir, int unit
     return TFFT_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// Tuning table file (JSON): {"entries": [{"precision": "fp32" | "fp64" | 0 | 1,
+// "N": n, "split_n1": s, "T": t, "kappa": k, "chunk_bytes": b, ...}, ...]}.
+// Unknown keys are ignored; missing ones keep their current value.
+// ---------------------------------------------------------------------------
+struct JVal {
+    enum Kind { kNull, kBool, kNum, kStr, kArr, kObj } kind = kNull;
+    double num = 0;
+    std::string str;
+    std::vector<JVal> arr;
+    std::vector<std::pair<std::string, JVal>> obj;
+    const JVal* get(const char* k) const {
+        for (auto& kv : obj)
+            if (kv.first == k) return &kv.second;
+        return nullptr;
+    }
+};
+
+struct JParser {
+    const std::string& t;
+    size_t i = 0;
+    explicit JParser(const std::string& text) : t(text) {}
+    void ws() { while (i < t.size() && (t[i] == ' ' || t[i] == '\n' || t[i] == '\r' || t[i] == '\t')) ++i; }
+    bool lit(const char* w) {
+        const size_t n = strlen(w);
+        if (t.compare(i, n, w) != 0) return false;
+        i += n;
+        return true;
+    }
+    bool str(std::string* out) {
+        if (i >= t.size() || t[i] != '"') return false;
+        ++i;
+        out->clear();
+        while (i < t.size() && t[i] != '"') {
+            char ch = t[i++];
+            if (ch == '\\') {
+                if (i >= t.size()) return false;
+                const char e = t[i++];
+                if (e == 'u') {   // keep ASCII only
+                    if (i + 4 > t.size()) return false;
+                    ch = (char)std::strtol(t.substr(i, 4).c_str(), nullptr, 16);
+                    i += 4;
+                } else {
+                    ch = e == 'n' ? '\n' : e == 't' ? '\t' : e == 'r' ? '\r' : e == 'b' ? '\b' : e == 'f' ? '\f' : e;
+                }
+            }
+            out->push_back(ch);
+        }
+        if (i >= t.size()) return false;
+        ++i;
+        return true;
+    }
+    bool value(JVal* v, int depth) {
+        if (depth > 32) return false;
+        ws();
+        if (i >= t.size()) return false;
+        const char c = t[i];
+        if (c == '{') {
+            ++i;
+            v->kind = JVal::kObj;
+            ws();
+            if (i < t.size() && t[i] == '}') { ++i; return true; }
+            for (;;) {
+                ws();
+                std::string k;
+                if (!str(&k)) return false;
+                ws();
+                if (i >= t.size() || t[i] != ':') return false;
+                ++i;
+                JVal e;
+                if (!value(&e, depth + 1)) return false;
+                v->obj.emplace_back(std::move(k), std::move(e));
+                ws();
+                if (i < t.size() && t[i] == ',') { ++i; continue; }
+                if (i < t.size() && t[i] == '}') { ++i; return true; }
+                return false;
+            }
+        }
+        if (c == '[') {
+            ++i;
+            v->kind = JVal::kArr;
+            ws();
+            if (i < t.size() && t[i] == ']') { ++i; return true; }
+            for (;;) {
+                JVal e;
+                if (!value(&e, depth + 1)) return false;
+                v->arr.push_back(std::move(e));
+                ws();
+                if (i < t.size() && t[i] == ',') { ++i; continue; }
+                if (i < t.size() && t[i] == ']') { ++i; return true; }
+                return false;
+            }
+        }
+        if (c == '"') { v->kind = JVal::kStr; return str(&v->str); }
+        if (lit("true")) { v->kind = JVal::kBool; v->num = 1; return true; }
+        if (lit("false")) { v->kind = JVal::kBool; v->num = 0; return true; }
+        if (lit("null")) { v->kind = JVal::kNull; return true; }
+        char* end = nullptr;
+        const double d = std::strtod(t.c_str() + i, &end);
+        if (end == t.c_str() + i) return false;
+        i = (size_t)(end - t.c_str());
+        v->kind = JVal::kNum;
+        v->num = d;
+        return true;
+    }
+};
+
+bool json_int(const JVal* v, long long* out) {
+    if (!v || v->kind != JVal::kNum || v->num != std::floor(v->num)) return false;
+    *out = (long long)v->num;
+    return true;
+}
+
 bool is_pow2(long long n) { return n > 0 && (n & (n - 1)) == 0; }
 
 int check_precision(int p) { return (p == TFFT_FP32 || p == TFFT_FP64) ? TFFT_OK : TFFT_EINVAL; }
@@ -751,7 +1003,7 @@ int tfft_prepare(long long N, int precision, int ft_mode) {
     std::lock_guard<std::mutex> lk(g_mu);
     ensure_registry();
     Route r;
-    if (!route_for(precision, N, ft_mode, &r)) return TFFT_EUNSUPPORTED;
+    if (!route_for(precision, N, ft_mode, &r, get_tuning(precision, N).split_n1)) return TFFT_EUNSUPPORTED;
     SubTables* st = nullptr;
     if (r.single) return get_sub(*r.single, true, &st);
     int rc = get_sub(*r.col, true, &st);
@@ -769,6 +1021,100 @@ int tfft_set_tuning(long long N, int precision, int T, double kappa) {
     if (kappa > 0) tu.kappa = kappa;
     g_tuning[std::make_pair(precision, N)] = tu;
     return TFFT_OK;
+}
+
+int tfft_routes(long long N, int precision, int ft_mode, long long* n1_out, int cap) {
+    if (N < 1 || check_precision(precision) != TFFT_OK || ft_mode < 0 || ft_mode > 2 || cap < 0 ||
+        (cap > 0 && !n1_out))
+        return TFFT_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    ensure_registry();
+    int n = 0;
+    auto put_route = [&](long long v) {
+        if (n < cap) n1_out[n] = v;
+        ++n;
+    };
+    if (find_entry(precision, kSingle, N, ft_mode)) put_route(1);
+    for (long long c = 2; c < N; c <<= 1)
+        if (split_ok(precision, N, ft_mode, c)) put_route(c);
+    return n;
+}
+
+int tfft_set_route(long long N, int precision, long long split_n1) {
+    if (N < 1 || check_precision(precision) != TFFT_OK || split_n1 < 0) return TFFT_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    ensure_registry();
+    Route r;
+    if (split_n1 != 0 && !route_for(precision, N, TFFT_FT_OFF, &r, split_n1)) return TFFT_EUNSUPPORTED;
+    Tuning tu = get_tuning(precision, N);
+    tu.split_n1 = split_n1;
+    g_tuning[std::make_pair(precision, N)] = tu;
+    return TFFT_OK;
+}
+
+int tfft_get_route(long long N, int precision, int ft_mode, long long* n1) {
+    if (!n1 || N < 1 || check_precision(precision) != TFFT_OK || ft_mode < 0 || ft_mode > 2)
+        return TFFT_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    ensure_registry();
+    Route r;
+    if (!route_for(precision, N, ft_mode, &r, get_tuning(precision, N).split_n1)) return TFFT_EUNSUPPORTED;
+    *n1 = r.single ? 1 : r.N1;
+    return TFFT_OK;
+}
+
+int tfft_load_tuning(const char* path) {
+    if (!path) return TFFT_EINVAL;
+    FILE* f = fopen(path, "rb");
+    if (!f) return TFFT_EINVAL;
+    std::string text;
+    char buf[4096];
+    size_t got;
+    while ((got = fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, got);
+    fclose(f);
+    JVal root;
+    JParser jp(text);
+    if (!jp.value(&root, 0) || root.kind != JVal::kObj) return TFFT_EINVAL;
+    const JVal* entries = root.get("entries");
+    if (!entries || entries->kind != JVal::kArr) return TFFT_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    ensure_registry();
+    // validate every entry before applying any
+    std::vector<std::pair<std::pair<int, long long>, Tuning>> pending;
+    for (const JVal& e : entries->arr) {
+        if (e.kind != JVal::kObj) return TFFT_EINVAL;
+        const JVal* pv = e.get("precision");
+        int prec = -1;
+        if (pv && pv->kind == JVal::kStr) prec = pv->str == "fp32" ? TFFT_FP32 : pv->str == "fp64" ? TFFT_FP64 : -1;
+        else if (pv && pv->kind == JVal::kNum) prec = (int)pv->num;
+        long long N = 0;
+        if (check_precision(prec) != TFFT_OK || !json_int(e.get("N"), &N) || N < 1) return TFFT_EINVAL;
+        Tuning tu = get_tuning(prec, N);
+        for (auto& q : pending)
+            if (q.first == std::make_pair(prec, N)) tu = q.second;
+        long long v = 0;
+        if (e.get("split_n1")) {
+            if (!json_int(e.get("split_n1"), &v) || v < 0) return TFFT_EINVAL;
+            Route r;
+            if (v != 0 && !route_for(prec, N, TFFT_FT_OFF, &r, v)) return TFFT_EUNSUPPORTED;
+            tu.split_n1 = v;
+        }
+        if (e.get("T")) {
+            if (!json_int(e.get("T"), &v) || v < 1 || v > 32) return TFFT_EINVAL;
+            tu.T = (int)v;
+        }
+        if (e.get("chunk_bytes")) {
+            if (!json_int(e.get("chunk_bytes"), &v) || v < 1) return TFFT_EINVAL;
+            tu.chunk_bytes = v;
+        }
+        if (const JVal* k = e.get("kappa")) {
+            if (k->kind != JVal::kNum || !(k->num > 0)) return TFFT_EINVAL;
+            tu.kappa = k->num;
+        }
+        pending.emplace_back(std::make_pair(prec, N), tu);
+    }
+    for (auto& q : pending) g_tuning[q.first] = q.second;
+    return (int)pending.size();
 }
 
 int tfft_get_tuning(long long N, int precision, int* T, double* kappa) {
@@ -877,8 +1223,9 @@ int tfft_c2c(const void* x, void* y, long long N, long long batch, int dir, int 
 
     std::lock_guard<std::mutex> lk(g_mu);
     ensure_registry();
+    const Tuning tu = get_tuning(precision, N);
     Route rt;
-    if (!route_for(precision, N, ft_mode, &rt)) return TFFT_EUNSUPPORTED;
+    if (!route_for(precision, N, ft_mode, &rt, tu.split_n1)) return TFFT_EUNSUPPORTED;
     if (rt.single && ft_mode == TFFT_FT_CORRECT && x == y) {
         // in place: the kernel variant that keeps the right-side input sum
         rt.single = find_entry(precision, kSingle, N, 3);
@@ -888,7 +1235,6 @@ int tfft_c2c(const void* x, void* y, long long N, long long batch, int dir, int 
     if (inj.armed && (inj.precision != precision || inj.signal >= batch || inj.element >= N))
         return TFFT_EINVAL;
     const bool may_alloc = !capturing(stream);
-    const Tuning tu = get_tuning(precision, N);
     int rc;
     if (precision == TFFT_FP32)
         rc = transform<float2>(rt, x, y, N, batch, dir, scale, counts, tu, inj, stream, may_alloc);
@@ -919,6 +1265,7 @@ int tfft_ragged_plan_create(tfft_ragged_plan* plan, const long long* sizes_host,
     tfft_ragged_plan_s* P = new tfft_ragged_plan_s();
     P->device = current_device();
     P->precision = precision;
+    P->waves = g_ragged_waves;
     int rc = ragged_build(P, sizes_host, count);
     if (rc != TFFT_OK) {
         if (P->buf) (void)hipFree(P->buf);
@@ -942,19 +1289,28 @@ int tfft_ragged_plan_destroy(tfft_ragged_plan plan) {
 int tfft_ragged_plan_info(tfft_ragged_plan plan, long long* info, int n) {
     if (!plan || !info || n < 1) return TFFT_EINVAL;
     std::lock_guard<std::mutex> lk(g_mu);
-    long long v[8] = {plan->count, plan->total, plan->n_items, (long long)plan->classes.size(),
-                      plan->ws_elems, 0, 0, 0};
-    RaggedKernel k = ragged_kernel(TFFT_FT_CORRECT);
+    long long v[10] = {plan->count, plan->total, plan->n_items, (long long)plan->classes.size(),
+                       plan->ws_elems, 0, plan->n_batches, plan->window, 0, 0};
+    RaggedKernel k = ragged_kernel(TFFT_FT_CORRECT, plan->waves);
     long long grid = (long long)k.blocks_per_cu * plan->cus;
     v[5] = grid < plan->n_items ? grid : plan->n_items;
-    if (n > 6) {
+    if (n > 8) {
         RQueue q{};
         hipError_t err = hipMemcpy(&q, plan->d_queue, sizeof(q), hipMemcpyDeviceToHost);
         if (err != hipSuccess) return hip_fail(err);
-        v[6] = (long long)q.err;
-        v[7] = (long long)q.next;
+        v[8] = (long long)q.err;
+        v[9] = (long long)q.next;
     }
-    for (int i = 0; i < n && i < 8; ++i) info[i] = v[i];
+    for (int i = 0; i < n && i < 10; ++i) info[i] = v[i];
+    return TFFT_OK;
+}
+
+int tfft_ragged_set_schedule(long long window_elems, long long item_elems, int waves) {
+    if (window_elems < 0 || item_elems < 0 || (waves != 0 && waves != 3)) return TFFT_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_ragged_window = window_elems;
+    if (item_elems > 0) g_ragged_item = item_elems;
+    g_ragged_waves = waves;
     return TFFT_OK;
 }
 

@@ -55,7 +55,22 @@ struct FtCounts {   // mirrors tfft_ft_counts in the public header
 enum Kind { kSingle = 0, kColPass = 1, kRowPass = 2 };
 
 // Kernel arguments shared by all transform kernels.
-template <class V> struct KArgs {
+// Per-call arguments: direction, scaling, counters and the injection hook.
+template <class R> struct KCall {
+    int conj_in;          // 1: conjugate loaded values (inverse direction, first pass)
+    int conj_out;         // 1: conjugate stored values (inverse direction, last pass)
+    R scale;              // applied to every stored value
+    int stats;            // 1: record max |D0| / tau over groups (calibration)
+    FtCounts* counts;     // device counters (ABFT only)
+    long long inj_signal; // signal to corrupt (-1: none)
+    long long inj_elem;   // element index in this kernel's output numbering
+    int inj_part;         // 0 real, 1 imaginary
+    int inj_bit;          // bit to flip
+};
+
+// Arguments of one launch (a plain launch passes them as its kernel argument;
+// the persistent ragged kernel reads the per-class part from device memory).
+template <class V> struct KArgs : KCall<typename RealOf<V>::type> {
     using R = typename RealOf<V>::type;
     const V* tw;          // stage twiddle tables of the sub-length, concatenated
     const V* left;        // e^T W of the sub-length (ABFT only)
@@ -66,18 +81,9 @@ template <class V> struct KArgs {
     long long N;          // full transform length (signal stride in elements)
     int N1, N2;           // two-pass split, N = N1 * N2
     int T;                // transactions (signals) per slot
-    int conj_in;          // 1: conjugate loaded values (inverse direction, first pass)
-    int conj_out;         // 1: conjugate stored values (inverse direction, last pass)
-    R scale;              // applied to every stored value
     long long sig_base;   // global index of local signal 0 (counters only)
     R tau_coef;           // kappa * u * sqrt(Ns log2 Ns); tau = tau_coef * sqrt(nu)
     R cap;                // magnitude cap: larger outputs mark their signal corrupted
-    FtCounts* counts;     // device counters (ABFT only)
-    long long inj_signal; // signal to corrupt (-1: none)
-    long long inj_elem;   // element index in this kernel's output numbering
-    int inj_part;         // 0 real, 1 imaginary
-    int inj_bit;          // bit to flip
-    int stats;            // 1: record max |D0| / tau over groups (calibration)
     int x_intact;         // 1: inputs can be re-read on the error path
     int tiles;            // workgroups per signal group (tile geometries)
     // Indirection (ragged batches, kernels built with IND): element offset of
@@ -305,10 +311,11 @@ template <class V, class PL, bool IND> struct Geo {
         else return out_base(a, s) + line + (long long)a.N1 * k;
     }
     // is output element k of this slot the injected one (this kernel's numbering)?
-    __device__ __forceinline__ bool inj_hit(const KArgs<V>& a, int k) const {
-        if constexpr (PL::KIND == kSingle) return k == a.inj_elem;
-        else if constexpr (PL::KIND == kColPass) return (long long)k * a.N2 + line == a.inj_elem;
-        else return line + (long long)a.N1 * k == a.inj_elem;
+    __device__ __forceinline__ bool inj_hit(const KArgs<V>& a, const KCall<typename RealOf<V>::type>& kc,
+                                            int k) const {
+        if constexpr (PL::KIND == kSingle) return k == kc.inj_elem;
+        else if constexpr (PL::KIND == kColPass) return (long long)k * a.N2 + line == kc.inj_elem;
+        else return line + (long long)a.N1 * k == kc.inj_elem;
     }
     __device__ __forceinline__ auto lidx() const {
         if constexpr (PL::KIND == kSingle) return LdsPad<PL::B>{lds_off};
@@ -440,7 +447,8 @@ template <int COH, class V> __device__ __forceinline__ void st_y(V* y, long long
 // One workgroup's share of a transform: block `block` of `nblocks`.
 template <class V, class PL, int FT, bool IND, int COH, int... Rs>
 __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict__ y, const KArgs<V>& a,
-                                         long long block, long long nblocks, char* smem) {
+                                         const KCall<typename RealOf<V>::type>& kc, long long block,
+                                         long long nblocks, char* smem) {
     using R = typename RealOf<V>::type;
     constexpr int E = PL::E, P = PL::P, M = PL::M, Ns = PL::Ns;
     constexpr bool BLOCK = PL::MULTI_WAVE;
@@ -491,7 +499,7 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
 #pragma unroll
             for (int r = 0; r < E; ++r) reg[r] = V{0, 0};
         }
-        if (a.conj_in) {
+        if (kc.conj_in) {
 #pragma unroll
             for (int r = 0; r < E; ++r) reg[r].y = -reg[r].y;
         }
@@ -522,12 +530,12 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
 
         slot_fft<V, E, P, BLOCK, decltype(li), 1, Rs...>(reg, a.tw, t, lds, li);
 
-        if (a.inj_signal >= 0 && valid && g.gid(a, s) == a.inj_signal) {   // test hook: one bit flip
+        if (kc.inj_signal >= 0 && valid && g.gid(a, s) == kc.inj_signal) {   // test hook: one bit flip
 #pragma unroll
             for (int r = 0; r < E; ++r) {
-                if (g.inj_hit(a, t + P * r)) {
-                    if (a.inj_part == 0) reg[r].x = flip_bit(reg[r].x, a.inj_bit);
-                    else reg[r].y = flip_bit(reg[r].y, a.inj_bit);
+                if (g.inj_hit(a, kc, t + P * r)) {
+                    if (kc.inj_part == 0) reg[r].x = flip_bit(reg[r].x, kc.inj_bit);
+                    else reg[r].y = flip_bit(reg[r].y, kc.inj_bit);
                 }
             }
         }
@@ -544,8 +552,8 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
 #pragma unroll
             for (int r = 0; r < E; ++r) {
                 V v = reg[r];
-                if (a.conj_out) v.y = -v.y;
-                st_y<COH>(y, g.out_off(a, s, t + P * r), V{v.x * a.scale, v.y * a.scale});
+                if (kc.conj_out) v.y = -v.y;
+                st_y<COH>(y, g.out_off(a, s, t + P * r), V{v.x * kc.scale, v.y * kc.scale});
             }
         }
     }
@@ -602,10 +610,10 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
                 else action = 3;
             }
         }
-        if (a.stats && checked && nf == 0 && t == 0 && tau > (R)0) {
+        if (kc.stats && checked && nf == 0 && t == 0 && tau > (R)0) {
             // calibration: largest |D0| / tau seen (non-negative doubles order as integers)
             const double q = (double)d0 / (double)tau;
-            atomicMax(&a.counts->reserved[0], (unsigned long long)__double_as_longlong(q));
+            atomicMax(&kc.counts->reserved[0], (unsigned long long)__double_as_longlong(q));
         }
 
         // Location fallback on the error path: when D1/D0 is not an index (an
@@ -628,13 +636,13 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
 #pragma unroll
                     for (int r = 0; r < E; ++r) {
                         V xv = ld_x<COH>(x, g.in_off(a, sb, t + P * r));
-                        if (a.conj_in) xv.y = -xv.y;
+                        if (kc.conj_in) xv.y = -xv.y;
                         V av = aw[r];
                         if constexpr (PL::KIND == kRowPass) av = cmul(av, g.twiddle(a, t + P * r));
                         p = cadd(p, cmul(av, xv));
                         V yv = ld_y<COH>(y, g.out_off(a, sb, t + P * r));
-                        if (a.conj_out) yv.y = -yv.y;
-                        bucket[(P * r) % M] = cadd(bucket[(P * r) % M], V{yv.x / a.scale, yv.y / a.scale});
+                        if (kc.conj_out) yv.y = -yv.y;
+                        bucket[(P * r) % M] = cadd(bucket[(P * r) % M], V{yv.x / kc.scale, yv.y / kc.scale});
                     }
                 }
                 V q = bucket[0];
@@ -652,9 +660,9 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
 
         if constexpr (FT == 1) {
             if (action != 0 && t == 0) {
-                atomicAdd(&a.counts->detected, 1ull);
-                if (action == 3) atomicAdd(&a.counts->uncorrectable, 1ull);
-                else atomicExch(&a.counts->last_signal, (unsigned long long)g.gid(a, sstar));
+                atomicAdd(&kc.counts->detected, 1ull);
+                if (action == 3) atomicAdd(&kc.counts->uncorrectable, 1ull);
+                else atomicExch(&kc.counts->last_signal, (unsigned long long)g.gid(a, sstar));
             }
         } else {
             if (g.domain_any(action == 1 || action == 2)) {
@@ -673,7 +681,7 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
                             const long long sb = g.sig(b);
                             if (sb >= a.batch) continue;
                             V xv = ld_x<COH>(x, g.in_off(a, sb, t + P * r));
-                            if (a.conj_in) xv.y = -xv.y;
+                            if (kc.conj_in) xv.y = -xv.y;
                             acc = cadd(acc, xv);
                         }
                     }
@@ -689,8 +697,8 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
                         const long long sb = g.sig(b);
                         if (sb >= a.batch || b == skip) continue;
                         V yv = ld_y<COH>(y, g.out_off(a, sb, t + P * r));
-                        if (a.conj_out) yv.y = -yv.y;
-                        acc = V{acc.x - yv.x / a.scale, acc.y - yv.y / a.scale};
+                        if (kc.conj_out) yv.y = -yv.y;
+                        acc = V{acc.x - yv.x / kc.scale, acc.y - yv.y / kc.scale};
                     }
                     return acc;
                 };
@@ -726,18 +734,18 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
 #pragma unroll
                     for (int r = 0; r < E; ++r) {
                         V cc = corr_elem(r, -1);
-                        if (a.conj_out) cc.y = -cc.y;
+                        if (kc.conj_out) cc.y = -cc.y;
                         const long long o = g.out_off(a, sstar, t + P * r);
                         const V old = ld_y<COH>(y, o);
-                        st_y<COH>(y, o, V{old.x + a.scale * cc.x, old.y + a.scale * cc.y});
+                        st_y<COH>(y, o, V{old.x + kc.scale * cc.x, old.y + kc.scale * cc.y});
                     }
                 } else if (action == 2) {
                     // y_b* = scale * cj(W x_s - sum_{b != b*} y_b)
 #pragma unroll
                     for (int r = 0; r < E; ++r) {
                         V vv = corr_elem(r, bstar);
-                        if (a.conj_out) vv.y = -vv.y;
-                        vv = V{a.scale * vv.x, a.scale * vv.y};
+                        if (kc.conj_out) vv.y = -vv.y;
+                        vv = V{kc.scale * vv.x, kc.scale * vv.y};
                         rebuilt_ok = rebuilt_ok && cfin(vv.x, vv.y, a.cap);
                         st_y<COH>(y, g.out_off(a, sstar, t + P * r), vv);
                     }
@@ -746,16 +754,16 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
                 g.template reduce<OpOr>(badv, reinterpret_cast<unsigned*>(red));
                 if (action == 2 && badv[0] != 0u) ok = false;
                 if ((action == 1 || action == 2) && t == 0) {
-                    atomicAdd(&a.counts->detected, 1ull);
-                    if (!ok) atomicAdd(&a.counts->uncorrectable, 1ull);
-                    else if (action == 1) atomicAdd(&a.counts->corrected, 1ull);
-                    else atomicAdd(&a.counts->rebuilt, 1ull);
-                    atomicExch(&a.counts->last_signal, (unsigned long long)g.gid(a, sstar));
+                    atomicAdd(&kc.counts->detected, 1ull);
+                    if (!ok) atomicAdd(&kc.counts->uncorrectable, 1ull);
+                    else if (action == 1) atomicAdd(&kc.counts->corrected, 1ull);
+                    else atomicAdd(&kc.counts->rebuilt, 1ull);
+                    atomicExch(&kc.counts->last_signal, (unsigned long long)g.gid(a, sstar));
                 }
             }
             if (action == 3 && t == 0) {
-                atomicAdd(&a.counts->detected, 1ull);
-                atomicAdd(&a.counts->uncorrectable, 1ull);
+                atomicAdd(&kc.counts->detected, 1ull);
+                atomicAdd(&kc.counts->uncorrectable, 1ull);
             }
         }
     }
@@ -765,7 +773,7 @@ template <class V, class PL, int FT, bool IND, int... Rs>
 __global__ __launch_bounds__(PL::THREADS) void k_fft(const V* __restrict__ x, V* __restrict__ y,
                                                      KArgs<V> a) {
     __shared__ __align__(16) char smem[Smem<V, PL, FT>::BYTES];
-    fft_body<V, PL, FT, IND, 0, Rs...>(x, y, a, blockIdx.x, gridDim.x, smem);
+    fft_body<V, PL, FT, IND, 0, Rs...>(x, y, a, a, blockIdx.x, gridDim.x, smem);
 }
 
 }  // namespace tfft

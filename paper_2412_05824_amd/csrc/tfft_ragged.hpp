@@ -27,14 +27,24 @@ struct RClass {
     int nblocks;             // grid of the class
     int tiles;               // workgroups per group of signals (column / row passes)
     int cnt_base;            // first per-group counter of this class (-1: none)
-    int need;                // row pass: column-pass workgroups per group to wait for
+    int need;                // row pass: column-pass items per group to wait for
     int signal_after;        // column pass: 1 = bump the group's counter when done
-    int pad;
+    int items_per_group;     // column / row passes: items covering one group
 };
 
+// A work item: blocks [blk, blk + nblk) of one class, never straddling two
+// groups of signals of a column / row pass.  With a windowed workspace, a
+// row-pass item counts itself into its batch (batch >= 0) and a column-pass
+// item first waits until wait_need row-pass items of batch wait_batch have
+// finished reading the workspace half it is about to overwrite.
 struct RItem {
     int cls;
     int blk;
+    int nblk;
+    int batch;
+    int wait_batch;
+    int wait_need;
+    int pad0, pad1;
 };
 
 struct RQueue {
@@ -51,7 +61,9 @@ struct RaggedDesc {
     long long n_items;
     RQueue* q;
     unsigned* cnt_a;           // per group: finished column-pass workgroups
-    unsigned* cnt_b;           // per group: finished row-pass workgroups
+    unsigned* cnt_b;           // per group: row-pass items past their wait
+    unsigned* cnt_r;           // per batch: finished row-pass items (windowed workspace)
+    long long n_batches;
     float2* ws;                // column-pass results of the two-pass signals
 };
 
@@ -82,8 +94,9 @@ struct RaggedKernel {
 // per-size launches) and the persistent kernel per ABFT mode
 void register_fp32_ragged_single(std::vector<KernelEntry>& out);
 void register_fp32_ragged_tiles(std::vector<KernelEntry>& out);
-RaggedKernel ragged_kernel_ft0();
-RaggedKernel ragged_kernel_ft1();
-RaggedKernel ragged_kernel_ft2();
+// waves: 0 = the compiler's register budget, 3 = held to three workgroups per CU
+RaggedKernel ragged_kernel_ft0(int waves);
+RaggedKernel ragged_kernel_ft1(int waves);
+RaggedKernel ragged_kernel_ft2(int waves);
 
 }  // namespace tfft

@@ -82,66 +82,98 @@ constexpr unsigned kMaxPolls = 1u << 20;
 // to the other needs no cache-wide write-back or invalidation: the column
 // pass waits for its stores to complete before it counts itself done, and a
 // row pass starts loading only after every count of its group is in.
+// Thread 0 waits until *ctr reaches need (bounded; see kMaxPolls).
+__device__ __forceinline__ void wait_count(const RaggedDesc& d, unsigned* ctr, unsigned need) {
+    unsigned polls = 0;
+    while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+        if (++polls > kMaxPolls ||
+            __hip_atomic_load(&d.q->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0ull) {
+            atomicOr(&d.q->err, 1ull);
+            break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+}
+
 template <class PL, int FT, int... Rs>
 __device__ __forceinline__ void ragged_step(const RaggedCall& c, const RaggedDesc& d,
-                                            cptr<RClass> cl, int blk) {
+                                            cptr<RClass> cl, const RItem& it) {
     constexpr int COH = PL::KIND == kColPass ? 1 : PL::KIND == kRowPass ? 2 : 0;
+    const int blk = it.blk, nblk = it.nblk;
     const int tiles = cl->tiles;
     const int need = cl->need;
     const int grp = tiles > 0 ? blk / tiles : 0;
     const int cnt = cl->cnt_base + grp;
+    if constexpr (PL::KIND == kColPass) {
+        // windowed workspace: the half this batch writes has been read out
+        if (it.wait_batch >= 0) {
+            if (threadIdx.x == 0) wait_count(d, &d.cnt_r[it.wait_batch], (unsigned)it.wait_need);
+            __syncthreads();
+        }
+    }
     if constexpr (PL::KIND == kRowPass) {
-        // every column-pass workgroup of this group has finished
+        // every column-pass item of this group has finished
         if (threadIdx.x == 0) {
-            unsigned polls = 0;
-            while (__hip_atomic_load(&d.cnt_a[cnt], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
-                   (unsigned)need) {
-                if (++polls > kMaxPolls ||
-                    __hip_atomic_load(&d.q->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0ull) {
-                    atomicOr(&d.q->err, 1ull);
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(2);
-            }
-            // the last row-pass workgroup of the group resets both counters
-            // for the next launch; the others have all passed their wait
-            if (atomicAdd(&d.cnt_b[cnt], 1u) == (unsigned)(tiles - 1)) {
+            wait_count(d, &d.cnt_a[cnt], (unsigned)need);
+            // the last row-pass item of the group resets both counters for
+            // the next launch; the others have all passed their wait
+            if (atomicAdd(&d.cnt_b[cnt], 1u) == (unsigned)(cl->items_per_group - 1)) {
                 atomicExch(&d.cnt_a[cnt], 0u);
                 atomicExch(&d.cnt_b[cnt], 0u);
             }
         }
         __syncthreads();
     }
-    KArgs<float2> ka = cload(&cl->args);
-    const int final_pass = cl->final_pass;
-    ka.conj_in = PL::KIND == kRowPass ? 0 : c.conj;
-    ka.conj_out = final_pass ? c.conj : 0;
-    ka.scale = (final_pass && c.conj && !c.unit_scale) ? 1.0f / (float)ka.N : 1.0f;
-    ka.counts = c.counts;
-    ka.stats = c.stats;
-    ka.inj_signal = final_pass ? c.inj_signal : -1;
-    ka.inj_elem = c.inj_elem;
-    ka.inj_part = c.inj_part;
-    ka.inj_bit = c.inj_bit;
+    // the class's arguments are read in place from constant memory (scalar
+    // loads the compiler may repeat instead of holding them in registers, as
+    // it does for kernel arguments); only the per-call part is built here
+    const KArgs<float2>& ka = *(const KArgs<float2>*)&cl->args;
+    const int final_pass = PL::KIND != kColPass;
+    KCall<float> kc;
+    kc.conj_in = PL::KIND == kRowPass ? 0 : c.conj;
+    kc.conj_out = final_pass ? c.conj : 0;
+    kc.scale = (final_pass && c.conj && !c.unit_scale) ? 1.0f / (float)ka.N : 1.0f;
+    kc.counts = c.counts;
+    kc.stats = c.stats;
+    kc.inj_signal = final_pass ? c.inj_signal : -1;
+    kc.inj_elem = c.inj_elem;
+    kc.inj_part = c.inj_part;
+    kc.inj_bit = c.inj_bit;
     const float2* src = PL::KIND == kRowPass ? d.ws : c.x;
     float2* dst = PL::KIND == kColPass ? d.ws : c.y;
-    fft_body<float2, PL, FT, true, COH, Rs...>(src, dst, ka, blk, cl->nblocks,
-                                               tfft_ragged_smem + kRaggedSlotBytes);
+    const int nblocks = cl->nblocks;
+    for (int b = blk; b < blk + nblk; ++b) {
+        if (b != blk) __syncthreads();   // the previous block is done with the LDS buffer
+        fft_body<float2, PL, FT, true, COH, Rs...>(src, dst, ka, kc, b, nblocks,
+                                                   tfft_ragged_smem + kRaggedSlotBytes);
+    }
     if constexpr (PL::KIND == kColPass) {
         __builtin_amdgcn_s_waitcnt(0);   // this lane's workspace stores are complete
         __syncthreads();
         if (threadIdx.x == 0) atomicAdd(&d.cnt_a[cnt], 1u);
     }
+    if constexpr (PL::KIND == kRowPass) {
+        if (it.batch >= 0) {   // this item's workspace reads are complete
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            if (threadIdx.x == 0) atomicAdd(&d.cnt_r[it.batch], 1u);
+        }
+    }
 }
 
 template <int FT>
-__global__ __launch_bounds__(kRaggedThreads) void k_ragged(RaggedCall c, const RaggedDesc* dp) {
-    const RaggedDesc d = cload(as_const(dp));
-    long long item = share_item(threadIdx.x == 0 ? (long long)atomicAdd(&d.q->next, 1ull) : 0);
-    while (item < d.n_items) {
+__device__ __forceinline__ void ragged_loop(const RaggedCall& c, const RaggedDesc* dp) {
+    const long long n_items = cload(as_const(dp)).n_items;
+    long long item = share_item(threadIdx.x == 0 ? (long long)atomicAdd(&cload(as_const(dp)).q->next, 1ull) : 0);
+    while (item < n_items) {
+        // the descriptor is read again each item (an opaque pointer keeps the
+        // compiler from holding all of it in registers across the item)
+        const RaggedDesc* dpi = dp;
+        asm volatile("" : "+s"(dpi));
+        const RaggedDesc d = cload(as_const(dpi));
         // take the next item now; its index is waited for only after this one.
-        // Column-pass items all precede row-pass items in the queue, so an
-        // item taken while a row pass waits is never one it waits for.
+        // Every item waits only on items queued before it, so an item taken
+        // while this one waits is never one it waits for.
         unsigned long long pre = 0;
         if (threadIdx.x == 0) pre = atomicAdd(&d.q->next, 1ull);
         const RItem it = cload(as_const(d.items) + item);
@@ -150,7 +182,7 @@ __global__ __launch_bounds__(kRaggedThreads) void k_ragged(RaggedCall c, const R
 #define TFFT_CASE(id, kind, Ns, E, WC, B, ...)                                                 \
     case id:                                                                                    \
         ragged_step<TFFT_PLAN_T(id, kind, Ns, E, WC, B, __VA_ARGS__), FT, __VA_ARGS__>(c, d, cl, \
-                                                                                      it.blk);   \
+                                                                                      it);       \
         break;
             TFFT_RAGGED_PLANS(TFFT_CASE)
 #undef TFFT_CASE
@@ -159,30 +191,55 @@ __global__ __launch_bounds__(kRaggedThreads) void k_ragged(RaggedCall c, const R
         }
         item = share_item((long long)pre);
     }
-    // the last workgroup out resets the queue for the next launch
-    if (threadIdx.x == 0) {
-        if (atomicAdd(&d.q->done, 1ull) == (unsigned long long)gridDim.x - 1ull) {
+    // the last workgroup out resets the queue and the batch counters for the
+    // next launch
+    const RaggedDesc d = cload(as_const(dp));
+    const long long last =
+        share_item(threadIdx.x == 0 && atomicAdd(&d.q->done, 1ull) == (unsigned long long)gridDim.x - 1ull
+                       ? 1
+                       : 0);
+    if (last) {
+        for (long long i = threadIdx.x; i < d.n_batches; i += kRaggedThreads) atomicExch(&d.cnt_r[i], 0u);
+        if (threadIdx.x == 0) {
             atomicExch(&d.q->next, 0ull);
             atomicExch(&d.q->done, 0ull);
         }
     }
 }
 
+// The register budget is the compiler's choice (two workgroups per CU for
+// the ABFT modes) or held to three workgroups per CU, at the price of a few
+// spilled values; which is faster is a measured, per-plan choice.
 template <int FT>
+__global__ __launch_bounds__(kRaggedThreads) void k_ragged(RaggedCall c, const RaggedDesc* dp) {
+    ragged_loop<FT>(c, dp);
+}
+template <int FT>
+__global__ __launch_bounds__(kRaggedThreads) __attribute__((amdgpu_waves_per_eu(3, 3))) void
+k_ragged_w3(RaggedCall c, const RaggedDesc* dp) {
+    ragged_loop<FT>(c, dp);
+}
+
+template <int FT, bool W3>
 hipError_t launch_ragged(const RaggedCall& c, const RaggedDesc* d, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_ragged<FT>), dim3(grid), dim3(kRaggedThreads), ragged_smem<FT>(), s, c, d);
+    if constexpr (W3)
+        hipLaunchKernelGGL((k_ragged_w3<FT>), dim3(grid), dim3(kRaggedThreads), ragged_smem<FT>(), s, c, d);
+    else
+        hipLaunchKernelGGL((k_ragged<FT>), dim3(grid), dim3(kRaggedThreads), ragged_smem<FT>(), s, c, d);
     return hipGetLastError();
 }
 
-template <int FT> RaggedKernel make_ragged_kernel() {
+template <int FT, bool W3> RaggedKernel make_ragged_kernel() {
     RaggedKernel k{};
-    k.launch = &launch_ragged<FT>;
+    k.launch = &launch_ragged<FT, W3>;
     k.lds_bytes = ragged_smem<FT>();
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_ragged<FT>, kRaggedThreads,
-                                                     ragged_smem<FT>()) != hipSuccess)
-        n = 0;
-    k.blocks_per_cu = n;
+    hipError_t e;
+    if constexpr (W3)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_ragged_w3<FT>, kRaggedThreads, ragged_smem<FT>());
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_ragged<FT>, kRaggedThreads, ragged_smem<FT>());
+    k.blocks_per_cu = e == hipSuccess ? n : 0;
     return k;
 }
 

@@ -97,6 +97,12 @@ RAGGED_PER_SIZE = 1
 _MODES = {"persistent": RAGGED_PERSISTENT, "per_size": RAGGED_PER_SIZE}
 
 
+def ragged_set_schedule(window_elems: int = 0, item_elems: int = 0, waves: int = 3) -> None:
+    """Schedule of ragged plans created afterwards (see tfft_ragged_set_schedule)."""
+    _lib.check(_lib.load().tfft_ragged_set_schedule(int(window_elems), int(item_elems), int(waves)),
+               "tfft_ragged_set_schedule")
+
+
 def ragged_supported(N: int, dtype=torch.complex64) -> bool:
     return bool(_lib.load().tfft_ragged_supported(N, _precision(dtype)))
 
@@ -128,11 +134,12 @@ class RaggedPlan:
 
     def info(self, device_state: bool = False) -> dict:
         import ctypes
-        n = 8 if device_state else 6
-        buf = (ctypes.c_longlong * 8)()
+        n = 10 if device_state else 8
+        buf = (ctypes.c_longlong * 10)()
         with torch.cuda.device(self.device):
             _lib.check(_lib.load().tfft_ragged_plan_info(self._h, buf, n), "tfft_ragged_plan_info")
-        keys = ("signals", "total", "items", "classes", "ws_elems", "grid", "queue_err", "queue_next")
+        keys = ("signals", "total", "items", "classes", "ws_elems", "grid", "batches", "window",
+                "queue_err", "queue_next")
         return {k: int(buf[i]) for i, k in enumerate(keys[:n])}
 
     def __call__(self, x: torch.Tensor, out: torch.Tensor | None = None, dir: int = -1,
@@ -188,3 +195,38 @@ def fft_c2c_ragged(packed: torch.Tensor, sizes, dir: int = -1, ft_mode: int = 2,
         plan = RaggedPlan(key[2], dtype=packed.dtype, device=packed.device)
         _ragged_cache[key] = plan
     return plan(packed, out=out, dir=dir, ft_mode=ft_mode, counts=counts, mode=mode)
+
+
+# ---- routes and the tuning table ----
+def routes(N: int, dtype=torch.complex64, ft_mode: int = 2) -> list:
+    """Candidate routes of length N: 1 = single pass, n1 > 1 = column pass n1, row pass N/n1."""
+    import ctypes
+    lib = _lib.load()
+    n = lib.tfft_routes(N, _precision(dtype), ft_mode, None, 0)
+    _lib.check(min(n, 0), f"tfft_routes(N={N})")
+    buf = (ctypes.c_longlong * max(1, n))()
+    lib.tfft_routes(N, _precision(dtype), ft_mode, buf, n)
+    return [int(buf[i]) for i in range(n)]
+
+
+def set_route(N: int, dtype, split_n1: int) -> None:
+    _lib.check(_lib.load().tfft_set_route(N, _precision(dtype), split_n1), f"tfft_set_route(N={N})")
+
+
+def get_route(N: int, dtype=torch.complex64, ft_mode: int = 2) -> int:
+    import ctypes
+    v = ctypes.c_longlong()
+    _lib.check(_lib.load().tfft_get_route(N, _precision(dtype), ft_mode, ctypes.byref(v)),
+               f"tfft_get_route(N={N})")
+    return int(v.value)
+
+
+def set_chunk(N: int, dtype, chunk_bytes: int) -> None:
+    _lib.check(_lib.load().tfft_set_chunk(N, _precision(dtype), chunk_bytes), f"tfft_set_chunk(N={N})")
+
+
+def load_tuning(path: str) -> int:
+    """Apply a tuning table written by the autotuner; returns the entries applied."""
+    n = _lib.load().tfft_load_tuning(str(path).encode())
+    _lib.check(min(n, 0), f"tfft_load_tuning({path})")
+    return n

@@ -2,6 +2,7 @@
 declared in include/tfft.h, and rejects invalid arguments before any device
 work."""
 import ctypes
+import json
 import os
 import re
 
@@ -98,3 +99,70 @@ def test_ragged_invalid_arguments_rejected_on_host():
     assert lib.tfft_ragged_plan_destroy(None) == _lib.TFFT_EINVAL
     info = (ctypes.c_longlong * 8)()
     assert lib.tfft_ragged_plan_info(None, info, 8) == _lib.TFFT_EINVAL
+
+
+def test_routes_and_forced_split():
+    """Multi-pass decomposition choices (Sec. 3.1): the default route of a
+    length, the candidate list, and forcing a split."""
+    lib = _lib.load()
+    FP32 = _lib.FP32
+
+    def routes(n, prec=FP32):
+        cnt = lib.tfft_routes(n, prec, 2, None, 0)
+        buf = (ctypes.c_longlong * max(1, cnt))()
+        assert lib.tfft_routes(n, prec, 2, buf, cnt) == cnt
+        return [buf[i] for i in range(cnt)]
+
+    def route(n, prec=FP32):
+        v = ctypes.c_longlong()
+        assert lib.tfft_get_route(n, prec, 2, ctypes.byref(v)) == _lib.TFFT_OK
+        return v.value
+
+    r4096 = routes(4096)
+    assert r4096[0] == 1 and len(r4096) > 1          # single pass, and splits
+    assert route(4096) == 1
+    big = routes(1 << 20)
+    assert 1 not in big and all((1 << 20) % n1 == 0 for n1 in big)
+    default = route(1 << 20)
+    assert default in big and default * default <= (1 << 20)
+    try:
+        alt = [n1 for n1 in r4096 if n1 > 1][0]
+        assert lib.tfft_set_route(4096, FP32, alt) == _lib.TFFT_OK
+        assert route(4096) == alt
+        assert lib.tfft_set_route(4096, FP32, 3) == _lib.TFFT_EUNSUPPORTED
+        assert lib.tfft_set_route(1 << 20, FP32, 1) == _lib.TFFT_EUNSUPPORTED
+    finally:
+        assert lib.tfft_set_route(4096, FP32, 0) == _lib.TFFT_OK
+    assert route(4096) == 1
+
+
+def test_load_tuning_table(tmp_path):
+    lib = _lib.load()
+    T = ctypes.c_int()
+    k = ctypes.c_double()
+    good = tmp_path / "good.json"
+    good.write_text(json.dumps({"format": "x", "entries": [
+        {"precision": "fp32", "N": 2048, "T": 1, "kappa": 9.5, "split_n1": 0, "gbs": 1.0},
+        {"precision": "fp64", "N": 1024, "T": 4, "chunk_bytes": 1 << 26},
+    ]}))
+    try:
+        assert lib.tfft_load_tuning(str(good).encode()) == 2
+        assert lib.tfft_get_tuning(2048, _lib.FP32, ctypes.byref(T), ctypes.byref(k)) == 0
+        assert (T.value, k.value) == (1, 9.5)
+        assert lib.tfft_get_tuning(1024, _lib.FP64, ctypes.byref(T), ctypes.byref(k)) == 0
+        assert T.value == 4
+        # malformed, out of range, unbuilt route: nothing applied
+        for bad in ('{"entries": [', '{"entries": [{"precision": "fp32", "N": 2048, "T": 99}]}',
+                    '{"entries": [{"precision": "fp32", "N": 2048, "T": 2}, '
+                    '{"precision": "fp32", "N": 4096, "split_n1": 3}]}',
+                    '[]', '{"entries": [{"precision": "fp16", "N": 64}]}'):
+            p = tmp_path / "bad.json"
+            p.write_text(bad)
+            assert lib.tfft_load_tuning(str(p).encode()) < 0, bad
+        assert lib.tfft_get_tuning(2048, _lib.FP32, ctypes.byref(T), ctypes.byref(k)) == 0
+        assert T.value == 1
+        assert lib.tfft_load_tuning(str(tmp_path / "missing.json").encode()) == _lib.TFFT_EINVAL
+    finally:
+        lib.tfft_set_tuning(2048, _lib.FP32, 1, 8.0)
+        lib.tfft_set_tuning(1024, _lib.FP64, 8, 16.0)
+        lib.tfft_set_chunk(1024, _lib.FP64, 128 << 20)

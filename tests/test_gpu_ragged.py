@@ -65,6 +65,24 @@ def _small_sizes(seed=11):
     return [int(s) for s in sizes]
 
 
+def _plan(sizes, dev, window=0, waves=3):
+    """A plan built under a schedule (window = 0: flat workspace; waves = 3:
+    the persistent kernel held to three workgroups per CU, the default;
+    0: the compiler's register budget)."""
+    tf.ragged_set_schedule(window, 0, waves)
+    try:
+        return tf.RaggedPlan(sizes, device=dev)
+    finally:
+        tf.ragged_set_schedule(0, 0, 3)
+
+
+# (window, waves): flat workspace; a ring of two 2^18-element halves (many
+# batches, so column passes of later batches wait for earlier row passes);
+# the compiler's register budget instead of three workgroups per CU
+SCHEDULES = [(0, 3), (1 << 18, 3), (0, 0)]
+WINDOWS = [0, 1 << 18]
+
+
 def _check_signals(y, x_host, sizes, refs, tol=TOL):
     off = _offsets(sizes)
     worst = 0.0
@@ -76,14 +94,16 @@ def _check_signals(y, x_host, sizes, refs, tol=TOL):
     return worst
 
 
+@pytest.mark.parametrize("window,waves", SCHEDULES)
 @pytest.mark.parametrize("ft", [tf.FT_OFF, tf.FT_CORRECT])
-def test_ragged_parity_and_modes(dev, ft):
+def test_ragged_parity_and_modes(dev, ft, window, waves):
     sizes = _small_sizes()
     x_host = _ragged_input(sizes, seed=101)
     x = torch.from_numpy(x_host).to(dev)
-    plan = tf.RaggedPlan(sizes, device=dev)
+    plan = _plan(sizes, dev, window, waves)
     info = plan.info()
     assert info["signals"] == len(sizes) and info["total"] == x.numel()
+    assert (info["batches"] > 2) == (window > 0), info
     outs = {}
     for mode in MODES:
         counts = tf.new_counts(dev)
@@ -140,13 +160,14 @@ def test_ragged_inverse_and_unit_scale(dev, mode):
 INJ = [(64, 27), (192, 22), (3072, 30), (4096, 26), (6144, 29), (196608, 28), (1 << 16, 23)]
 
 
-@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("mode", MODES + ("windowed", "w0"))
 @pytest.mark.parametrize("n,bit", INJ)
 def test_ragged_injection_corrected(dev, mode, n, bit):
     sizes = _small_sizes(seed=14)
     x_host = _ragged_input(sizes, seed=104)
     x = torch.from_numpy(x_host).to(dev)
-    plan = tf.RaggedPlan(sizes, device=dev)
+    plan = _plan(sizes, dev, WINDOWS[1] if mode == "windowed" else 0, 0 if mode == "w0" else 3)
+    mode = "persistent" if mode in ("windowed", "w0") else mode
     clean, _ = plan(x, ft_mode=tf.FT_CORRECT, mode=mode)
     cands = [i for i, s in enumerate(sizes) if s == n]
     g = synth.rng(1000 + n + bit)
@@ -172,11 +193,12 @@ def test_ragged_injection_corrected(dev, mode, n, bit):
     assert np.array_equal(yh[mask].view(np.uint32), ch[mask].view(np.uint32))
 
 
-def test_ragged_graph_replay(dev):
+@pytest.mark.parametrize("window,waves", SCHEDULES)
+def test_ragged_graph_replay(dev, window, waves):
     sizes = _small_sizes(seed=15)
     x_host = _ragged_input(sizes, seed=105)
     x = torch.from_numpy(x_host).to(dev)
-    plan = tf.RaggedPlan(sizes, device=dev)
+    plan = _plan(sizes, dev, window, waves)
     y = torch.empty_like(x)
     counts = tf.new_counts(dev)
     s = torch.cuda.Stream()
@@ -234,13 +256,14 @@ def test_ragged_edges(dev):
         p(xi, out=xi, ft_mode=tf.FT_CORRECT)
 
 
-def test_ragged_full_workload(dev):
+@pytest.mark.parametrize("window,waves", [(0, 3), (1 << 23, 3), (0, 0)])
+def test_ragged_full_workload(dev, window, waves):
     """The 10,000-signal workload (lengths drawn from the 22-length menu),
     persistent vs per-size bit for bit, sampled signals against the oracle."""
     sizes = [int(s) for s in synth.ragged_sizes(10000, seed=5)]
     x_host = _ragged_input(sizes, seed=2005)
     x = torch.from_numpy(x_host).to(dev)
-    plan = tf.RaggedPlan(sizes, device=dev)
+    plan = _plan(sizes, dev, window, waves)
     cp, cs = tf.new_counts(dev), tf.new_counts(dev)
     yp, _ = plan(x, ft_mode=tf.FT_CORRECT, counts=cp, mode="persistent")
     ys, _ = plan(x, ft_mode=tf.FT_CORRECT, counts=cs, mode="per_size")
