@@ -35,12 +35,17 @@ TOTAL_ELEMS = 1 << 27          # 1 GiB of complex64 per buffer
 
 
 def kernel_fingerprint() -> str:
-    """Hash of the kernel sources, to match stored counter readings to this build."""
+    """Hash of the kernel sources and the tuning table (which sets the bytes
+    per launch), to match stored counter readings to this build."""
     import hashlib
     m = hashlib.sha256()
-    for f in ("tfft_device.hpp", "tfft_kernels.hpp", "inst_fp32_single.hip", "inst_fp32_tiles.hip"):
-        with open(os.path.join(ROOT, "paper_2412_05824_amd", "csrc", f), "rb") as fh:
-            m.update(fh.read())
+    pkg = os.path.join(ROOT, "paper_2412_05824_amd")
+    for f in ("csrc/tfft_device.hpp", "csrc/tfft_kernels.hpp", "csrc/inst_fp32_single.hip",
+              "csrc/inst_fp32_tiles.hip", "tuning/mi355x.json"):
+        path = os.path.join(pkg, f)
+        if os.path.exists(path):
+            with open(path, "rb") as fh:
+                m.update(fh.read())
     return m.hexdigest()[:16]
 
 
@@ -54,6 +59,8 @@ def parse():
     p.add_argument("--no-extra", action="store_true", help="skip the off/injection sweep")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--no-ragged", action="store_true", help="skip the ragged-batch comparison")
+    p.add_argument("--ragged-only", action="store_true",
+                   help="only run the ragged-batch comparison (for profiling its kernels)")
     p.add_argument("--ragged-signals", type=int, default=10000)
     p.add_argument("--copy-ref", action="store_true",
                    help="only run a plain 1 GiB device copy (reference for counter scaling)")
@@ -76,6 +83,9 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
+    if args.ragged_only:
+        print(json.dumps({"ragged": ragged_compare(tf, synth, np, torch, dev, args)}), flush=True)
+        return
     if args.copy_ref:
         src = torch.zeros(TOTAL_ELEMS, dtype=torch.complex64, device=dev)
         dst = torch.empty_like(src)
