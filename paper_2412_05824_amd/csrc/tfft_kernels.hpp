@@ -249,6 +249,9 @@ template <class V, class PL, bool IND> struct Geo {
     int lds_off;         // single: start of the slot's LDS region
     int par = 0;         // which half of the reduction scratch the next reduce uses
     int tid;             // lane in the workgroup
+    int tile = 0;        // tiles: tile index within the signal group
+    V tw_base{(R)1, (R)0};       // row pass: w_N^{t k1} of this lane
+    const V* tw_step = nullptr;  // row pass: LDS table w_N^{P r k1} of the tile's rows
 
     __device__ __forceinline__ Geo(const KArgs<V>& a, long long block, long long nblocks, int tid_)
         : tid(tid_) {
@@ -279,9 +282,10 @@ template <class V, class PL, bool IND> struct Geo {
             long long bid = block;
             const long long G = nblocks;
             if (!IND && (G & 7) == 0) bid = (bid & 7) * (G >> 3) + (bid >> 3);
-            const long long tile = bid % a.tiles;   // tiles of one signal group are consecutive
+            const long long tl = bid % a.tiles;   // tiles of one signal group are consecutive
             const long long grp = bid / a.tiles;
-            line = (int)(tile * C + slot);
+            tile = (int)tl;
+            line = (int)(tl * C + slot);
             sig0 = grp * a.T;
             sig_step = 1;
         }
@@ -322,12 +326,32 @@ template <class V, class PL, bool IND> struct Geo {
         else return LdsCol<C>{slot};
     }
     // row pass: w_N^{n k1} for sub-signal element n (two table values, one product)
-    __device__ __forceinline__ V twiddle(const KArgs<V>& a, int n) const {
+    // w_N^m from the two-level table (m < N)
+    __device__ __forceinline__ static V twiddle_at(const KArgs<V>& a, unsigned m) {
+        const V hi = a.tw_hi[m >> a.tw_bits];
+        const V lo = a.tw_lo[m & ((1u << a.tw_bits) - 1u)];
+        return cmul(hi, lo);
+    }
+    // Row pass: build w_N^{P r k1} for the C rows k1 of this tile and r < E
+    // in LDS (shared by every lane of a row), and this lane's w_N^{t k1}.
+    // The inter-pass twiddle of element t + P r is then their product: one
+    // LDS read and one multiply instead of two table gathers per element.
+    __device__ __forceinline__ void twiddle_setup(const KArgs<V>& a, V* steps) {
         if constexpr (PL::KIND == kRowPass) {
-            const unsigned m = (unsigned)n * (unsigned)line;   // n < N2, k1 < N1: m < N
-            const V hi = a.tw_hi[m >> a.tw_bits];
-            const V lo = a.tw_lo[m & ((1u << a.tw_bits) - 1u)];
-            return cmul(hi, lo);
+            for (int i = tid; i < C * E; i += PL::THREADS) {
+                const int c = i / E, r = i % E;
+                const unsigned k1 = (unsigned)(tile * C + c);
+                steps[i] = twiddle_at(a, (unsigned)P * (unsigned)r * k1);   // P r k1 < N
+            }
+            tw_base = twiddle_at(a, (unsigned)t * (unsigned)line);          // t k1 < N
+            tw_step = steps;
+        }
+    }
+    // inter-pass twiddle of element t + P r (1 outside the row pass); the
+    // LDS steps must be visible (barrier after twiddle_setup)
+    __device__ __forceinline__ V twiddle(const KArgs<V>& a, int r) const {
+        if constexpr (PL::KIND == kRowPass) {
+            return cmul(tw_base, tw_step[slot * E + r]);
         } else {
             return V{(R)1, (R)0};
         }
@@ -403,7 +427,11 @@ template <class V, class PL, int FT> struct Smem {
     using R = typename RealOf<V>::type;
     static constexpr int NRED = 6;
     static constexpr int RED = FT ? 2 * (PL::TILE ? PL::C : 1) * PL::WAVES * NRED : 1;
-    static constexpr int BYTES = PL::LDS_DATA * (int)sizeof(V) + RED * (int)sizeof(R);
+    // row pass: the C x E inter-pass twiddle steps of the workgroup's rows
+    static constexpr int TWS = PL::KIND == kRowPass ? PL::C * PL::E : 0;
+    static constexpr int TWS_OFF = PL::LDS_DATA * (int)sizeof(V);
+    static constexpr int RED_OFF = TWS_OFF + TWS * (int)sizeof(V);
+    static constexpr int BYTES = RED_OFF + RED * (int)sizeof(R);
 };
 
 // Buffers that other workgroups of the same launch read back (the persistent
@@ -453,23 +481,24 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
     constexpr int E = PL::E, P = PL::P, M = PL::M, Ns = PL::Ns;
     constexpr bool BLOCK = PL::MULTI_WAVE;
     V* lds = reinterpret_cast<V*>(smem);
-    R* red = reinterpret_cast<R*>(smem + PL::LDS_DATA * sizeof(V));
+    R* red = reinterpret_cast<R*>(smem + Smem<V, PL, FT>::RED_OFF);
 
     // An opaque copy of the lane index: a persistent caller runs this body in
     // a loop, and nothing derived from the lane may be hoisted out of it.
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
     Geo<V, PL, IND> g(a, block, nblocks, tid);
+    if constexpr (PL::KIND == kRowPass) {
+        g.twiddle_setup(a, reinterpret_cast<V*>(smem + Smem<V, PL, FT>::TWS_OFF));
+        lds_sync<PL::MULTI_WAVE>();
+    }
     const auto li = g.lidx();
     constexpr bool KEEP_XS = FT == 3;   // in place: inputs are gone after the store
     const int t = g.t;
 
-    // this lane's share of the left vector e^T W: always the same positions
-    V aw[FT ? E : 1];
-    if constexpr (FT != 0) {
-#pragma unroll
-        for (int r = 0; r < E; ++r) aw[r] = a.left[t + P * r];
-    }
+    // This lane's share of the left vector e^T W (always the same positions)
+    // is loaded with each transaction's inputs and dies at the encoding, so it
+    // holds no registers through the butterflies; repeats hit the cache.
 
     V reg[E];
     V xs[KEEP_XS ? E : 1];
@@ -511,11 +540,11 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
                 const V z = reg[r];   // raw loaded value
                 V tw = V{(R)1, (R)0};
                 if constexpr (PL::KIND == kRowPass) {
-                    tw = g.twiddle(a, t + P * r);
+                    tw = g.twiddle(a, r);
                     reg[r] = cmul(z, tw);
                 }
                 if constexpr (FT != 0) {
-                    V av = aw[r];
+                    V av = a.left[t + P * r];
                     if constexpr (PL::KIND == kRowPass) av = cmul(av, tw);
                     p = cadd(p, cmul(av, z));
                     nu += z.x * z.x + z.y * z.y;
@@ -637,8 +666,8 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
                     for (int r = 0; r < E; ++r) {
                         V xv = ld_x<COH>(x, g.in_off(a, sb, t + P * r));
                         if (kc.conj_in) xv.y = -xv.y;
-                        V av = aw[r];
-                        if constexpr (PL::KIND == kRowPass) av = cmul(av, g.twiddle(a, t + P * r));
+                        V av = a.left[t + P * r];
+                        if constexpr (PL::KIND == kRowPass) av = cmul(av, g.twiddle(a, r));
                         p = cadd(p, cmul(av, xv));
                         V yv = ld_y<COH>(y, g.out_off(a, sb, t + P * r));
                         if (kc.conj_out) yv.y = -yv.y;
@@ -685,7 +714,7 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
                             acc = cadd(acc, xv);
                         }
                     }
-                    if constexpr (PL::KIND == kRowPass) acc = cmul(acc, g.twiddle(a, t + P * r));
+                    if constexpr (PL::KIND == kRowPass) acc = cmul(acc, g.twiddle(a, r));
                     reg[r] = acc;
                 }
                 slot_fft<V, E, P, BLOCK, decltype(li), 1, Rs...>(reg, a.tw, t, lds, li);   // W x_s
