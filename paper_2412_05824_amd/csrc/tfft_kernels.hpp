@@ -314,12 +314,20 @@ template <class V, class PL, bool IND> struct Geo {
         else if constexpr (PL::KIND == kColPass) return out_base(a, s) + (long long)k * a.N2 + line;
         else return out_base(a, s) + line + (long long)a.N1 * k;
     }
-    // is output element k of this slot the injected one (this kernel's numbering)?
-    __device__ __forceinline__ bool inj_hit(const KArgs<V>& a, const KCall<typename RealOf<V>::type>& kc,
-                                            int k) const {
-        if constexpr (PL::KIND == kSingle) return k == kc.inj_elem;
-        else if constexpr (PL::KIND == kColPass) return (long long)k * a.N2 + line == kc.inj_elem;
-        else return line + (long long)a.N1 * k == kc.inj_elem;
+    // which of this lane's output elements t + P r is the injected one (this
+    // kernel's numbering): r, or -1 (test hook; one division per transaction
+    // instead of a 64-bit compare per element)
+    __device__ __forceinline__ int inj_r(const KArgs<V>& a, const KCall<typename RealOf<V>::type>& kc) const {
+        long long k = -1;   // index of the target in this slot's numbering
+        if constexpr (PL::KIND == kSingle) {
+            k = kc.inj_elem;
+        } else if constexpr (PL::KIND == kColPass) {
+            if (kc.inj_elem % a.N2 == line) k = kc.inj_elem / a.N2;
+        } else {
+            if (kc.inj_elem % a.N1 == line) k = kc.inj_elem / a.N1;
+        }
+        if (k < t || k >= Ns || (k - t) % P != 0) return -1;
+        return (int)((k - t) / P);
     }
     __device__ __forceinline__ auto lidx() const {
         if constexpr (PL::KIND == kSingle) return LdsPad<PL::B>{lds_off};
@@ -429,8 +437,16 @@ template <class V, class PL, int FT> struct Smem {
     static constexpr int RED = FT ? 2 * (PL::TILE ? PL::C : 1) * PL::WAVES * NRED : 1;
     // row pass: the C x E inter-pass twiddle steps of the workgroup's rows
     static constexpr int TWS = PL::KIND == kRowPass ? PL::C * PL::E : 0;
+    // ABFT: the left vector e^T W staged once per workgroup where several
+    // signals share it and it is small (column tiles; single-pass groups of
+    // up to 2048 points); row passes keep reading the cached table, which
+    // costs them no registers and saves the staging
+    static constexpr bool AW_LDS =
+        FT != 0 && (PL::KIND == kColPass || (PL::KIND == kSingle && PL::SLOTS >= 2 && PL::Ns <= 2048));
+    static constexpr int AW = AW_LDS ? PL::Ns : 0;
     static constexpr int TWS_OFF = PL::LDS_DATA * (int)sizeof(V);
-    static constexpr int RED_OFF = TWS_OFF + TWS * (int)sizeof(V);
+    static constexpr int AW_OFF = TWS_OFF + TWS * (int)sizeof(V);
+    static constexpr int RED_OFF = AW_OFF + AW * (int)sizeof(V);
     static constexpr int BYTES = RED_OFF + RED * (int)sizeof(R);
 };
 
@@ -488,10 +504,18 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
     Geo<V, PL, IND> g(a, block, nblocks, tid);
-    if constexpr (PL::KIND == kRowPass) {
-        g.twiddle_setup(a, reinterpret_cast<V*>(smem + Smem<V, PL, FT>::TWS_OFF));
-        lds_sync<PL::MULTI_WAVE>();
+    // The left vector is read where each element is encoded: from LDS where
+    // one copy serves several lines or signals of the workgroup (and LDS
+    // reads need no address registers), from the cached table otherwise.
+    const V* left = a.left;
+    if constexpr (Smem<V, PL, FT>::AW_LDS) {
+        V* awl = reinterpret_cast<V*>(smem + Smem<V, PL, FT>::AW_OFF);
+        for (int i = tid; i < Ns; i += PL::THREADS) awl[i] = a.left[i];
+        left = awl;
     }
+    if constexpr (PL::KIND == kRowPass)
+        g.twiddle_setup(a, reinterpret_cast<V*>(smem + Smem<V, PL, FT>::TWS_OFF));
+    if constexpr (PL::KIND == kRowPass || Smem<V, PL, FT>::AW_LDS) lds_sync<PL::MULTI_WAVE>();
     const auto li = g.lidx();
     constexpr bool KEEP_XS = FT == 3;   // in place: inputs are gone after the store
     const int t = g.t;
@@ -544,7 +568,7 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
                     reg[r] = cmul(z, tw);
                 }
                 if constexpr (FT != 0) {
-                    V av = a.left[t + P * r];
+                    V av = left[t + P * r];
                     if constexpr (PL::KIND == kRowPass) av = cmul(av, tw);
                     p = cadd(p, cmul(av, z));
                     nu += z.x * z.x + z.y * z.y;
@@ -560,9 +584,10 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
         slot_fft<V, E, P, BLOCK, decltype(li), 1, Rs...>(reg, a.tw, t, lds, li);
 
         if (kc.inj_signal >= 0 && valid && g.gid(a, s) == kc.inj_signal) {   // test hook: one bit flip
+            const int rh = g.inj_r(a, kc);
 #pragma unroll
             for (int r = 0; r < E; ++r) {
-                if (g.inj_hit(a, kc, t + P * r)) {
+                if (r == rh) {
                     if (kc.inj_part == 0) reg[r].x = flip_bit(reg[r].x, kc.inj_bit);
                     else reg[r].y = flip_bit(reg[r].y, kc.inj_bit);
                 }
@@ -666,7 +691,7 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
                     for (int r = 0; r < E; ++r) {
                         V xv = ld_x<COH>(x, g.in_off(a, sb, t + P * r));
                         if (kc.conj_in) xv.y = -xv.y;
-                        V av = a.left[t + P * r];
+                        V av = left[t + P * r];
                         if constexpr (PL::KIND == kRowPass) av = cmul(av, g.twiddle(a, r));
                         p = cadd(p, cmul(av, xv));
                         V yv = ld_y<COH>(y, g.out_off(a, sb, t + P * r));
