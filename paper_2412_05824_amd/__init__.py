@@ -10,3 +10,4 @@ from .fft import (fft_c2c, prepare, supported, inject_arm, inject_disarm,  # noq
                   ragged_supported, ragged_set_schedule, RAGGED_PERSISTENT, RAGGED_PER_SIZE, routes, set_route,
                   get_route, set_chunk, load_tuning)
 from .autograd import FFT, fft  # noqa: F401,E402
+from . import _lib  # noqa: E402,F401
