@@ -173,23 +173,31 @@ int tfft_set_chunk(long long N, int precision, long long chunk_bytes);
 
 /* Routes.  A length runs either as one single-pass kernel or as a column
  * pass of length n1 followed by a row pass of length N/n1 (the multi-pass
- * decomposition of Sec. 3.1).  tfft_routes writes up to cap candidate routes
- * for (N, precision, ft_mode) into n1_out (1 = single pass, n1 > 1 = that
- * split) and returns how many exist.  tfft_set_route fixes the route of
- * (N, precision) (0 = default policy: single pass when built, else the most
- * balanced split), TFFT_EUNSUPPORTED if that route is not built.
- * tfft_get_route reports the route tfft_c2c would take now. */
-int tfft_routes(long long N, int precision, int ft_mode, long long* n1_out, int cap);
-int tfft_set_route(long long N, int precision, long long split_n1);
-int tfft_get_route(long long N, int precision, int ft_mode, long long* n1);
+ * decomposition of Sec. 3.1), each from one of the compiled plan variants
+ * of that length (tile width).  A route is coded as
+ *     code = n1 | va << 32 | vb << 40
+ * with n1 = 1 for a single pass of plan variant va, or n1 > 1 for a column
+ * pass of variant va and a row pass of variant vb; code 0 is the default
+ * policy (single pass when built, else the most balanced split, variant 0).
+ * tfft_routes writes up to cap codes built for (N, precision, ft_mode) and
+ * returns how many exist.  tfft_set_route fixes the route of (N, precision)
+ * in every ABFT mode (TFFT_EUNSUPPORTED if not built).  tfft_get_route
+ * reports the route tfft_c2c would take now in ft_mode (never code 0).
+ * tfft_set_tuning / tfft_set_chunk also apply to every mode; the tuning
+ * table may set each mode apart. */
+int tfft_routes(long long N, int precision, int ft_mode, long long* codes, int cap);
+int tfft_set_route(long long N, int precision, long long code);
+int tfft_get_route(long long N, int precision, int ft_mode, long long* code);
 
 /* Load a tuning table (JSON, as written by the autotuner):
- *   {"entries": [{"precision": "fp32" | "fp64", "N": n, "split_n1": s,
+ *   {"entries": [{"precision": "fp32" | "fp64", "N": n, "ft_mode": f,
+ *                 "split_n1": s, "variant_a": va, "variant_b": vb,
  *                 "T": t, "kappa": k, "chunk_bytes": b, ...}, ...]}
- * Each entry sets the fields it names for (N, precision); other keys are
- * ignored.  All entries are checked before any is applied.  Returns the
- * number of entries applied, or TFFT_EINVAL (unreadable file, malformed
- * JSON or value out of range) / TFFT_EUNSUPPORTED (a route not built). */
+ * Each entry sets the fields it names for (N, precision) in ABFT mode f, or
+ * in every mode when ft_mode is absent; other keys are ignored.  All
+ * entries are checked before any is applied.  Returns the number of entries
+ * applied, or TFFT_EINVAL (unreadable file, malformed JSON or value out of
+ * range) / TFFT_EUNSUPPORTED (a route not built). */
 int tfft_load_tuning(const char* path);
 
 /* Calibration of the detection threshold (Sec. 5.3 ROC protocol): while on,

@@ -2,17 +2,18 @@
 write the fastest into a JSON tuning table that the library loads
 (tfft_load_tuning).
 
-Per (precision, N) it sweeps:
+Per (precision, N) and ABFT mode (correct, off) it sweeps:
   * the route: single pass (when built) or each column/row split n1 x N/n1
-    (the multi-pass decomposition of Sec. 3.1);
+    (the multi-pass decomposition of Sec. 3.1), over the compiled plan
+    variants (tile widths) of each pass;
   * T, the transactions per checksum group (Sec. 4.3), limited by the
     accuracy bound below;
   * for two-pass routes, the chunk of signals whose intermediate lives in
     the workspace.
-Each candidate runs with ABFT correction on a 1 GiB seeded batch; it must
-count no detection on fault-free data and agree with the default
-configuration's output to within twice the precision's tolerance (two
-correct transforms differ by at most the sum of their errors).
+Each candidate runs on a 1 GiB seeded batch; it must count no detection on
+fault-free data and agree with the default configuration's output to
+within twice the precision's tolerance (two correct transforms differ by at
+most the sum of their errors).
 
 Accuracy bound on T: a flip just below the detection threshold changes one
 signal by about kappa * u * sqrt(T * log2 Ns) of its norm (Ns the longest
@@ -56,7 +57,7 @@ def _time(fn, torch, reps: int, warmup: int) -> float:
     return a.elapsed_time(b) / reps
 
 
-def tune(precisions, logs, reps=5, warmup=2, total_bytes=1 << 30, log=print):
+def tune(precisions, logs, modes=(2, 0), reps=5, warmup=2, total_bytes=1 << 30, log=print):
     import numpy as np
     import torch
 
@@ -81,41 +82,45 @@ def tune(precisions, logs, reps=5, warmup=2, total_bytes=1 << 30, log=print):
             xv, yv, rv = x.view(-1, N), y.view(-1, N), ref.view(-1, N)
             T0, k0 = tf.get_tuning(N, dtype)
             tf.set_route(N, dtype, 0)
-            tf.fft_c2c(xv, ft_mode=tf.FT_CORRECT, out=rv, counts=counts)
+            tf.fft_c2c(xv, ft_mode=tf.FT_OFF, out=rv)
             torch.cuda.synchronize()
             ref_norm = torch.linalg.vector_norm(rv).item()
-            best = None
-            for n1 in tf.routes(N, dtype, tf.FT_CORRECT):
-                longest = N if n1 == 1 else max(n1, N // n1)
-                tmax = max_T(prec, longest, KAPPA[prec])
-                chunks = [None] if n1 == 1 else [c << 20 for c in CHUNKS_MIB]
-                for T in [t for t in T_CHOICES if t <= tmax]:
-                    for chunk in chunks:
-                        tf.set_route(N, dtype, n1)
-                        tf.set_tuning(N, dtype, T, KAPPA[prec])
-                        if chunk:
-                            tf.set_chunk(N, dtype, chunk)
-                        counts.zero_()
-                        ms = _time(lambda: tf.fft_c2c(xv, ft_mode=tf.FT_CORRECT, out=yv, counts=counts),
-                                   torch, reps, warmup)
-                        det = tf.counts_dict(counts)["detected"]
-                        err = torch.linalg.vector_norm(yv - rv).item() / ref_norm
-                        ok = det == 0 and err <= 2 * TOL[prec]
-                        gbs = 2 * total * esize / (ms * 1e-3) / 1e9
-                        log(f"{prec} N={N} n1={n1} T={T} chunk={chunk} {ms:.4f} ms {gbs:.1f} GB/s "
-                            f"err={err:.2e} det={det}{'' if ok else ' REJECTED'}")
-                        if ok and (best is None or ms < best["ms"]):
-                            best = {"precision": prec, "N": N, "split_n1": n1, "T": T,
-                                    "kappa": KAPPA[prec], "ms": round(ms, 5), "gbs": round(gbs, 1)}
+            for ft in modes:
+                best = None
+                for code in tf.routes(N, dtype, ft):
+                    n1, va, vb = tf.route_parts(code)
+                    longest = N if n1 == 1 else max(n1, N // n1)
+                    # without ABFT, T only sets the signals per workgroup
+                    tmax = max_T(prec, longest, KAPPA[prec]) if ft else 4
+                    chunks = [None] if n1 == 1 else [c << 20 for c in CHUNKS_MIB]
+                    for T in [t for t in T_CHOICES if t <= tmax]:
+                        for chunk in chunks:
+                            tf.set_route(N, dtype, code)
+                            tf.set_tuning(N, dtype, T, KAPPA[prec])
                             if chunk:
-                                best["chunk_bytes"] = chunk
-            # back to the defaults before the next length
-            tf.set_route(N, dtype, 0)
-            tf.set_tuning(N, dtype, T0, k0)
-            tf.set_chunk(N, dtype, 128 << 20)
-            if best:
-                entries.append(best)
-                log(f"best {prec} N={N}: {best}")
+                                tf.set_chunk(N, dtype, chunk)
+                            counts.zero_()
+                            ms = _time(lambda: tf.fft_c2c(xv, ft_mode=ft, out=yv, counts=counts),
+                                       torch, reps, warmup)
+                            det = tf.counts_dict(counts)["detected"]
+                            err = torch.linalg.vector_norm(yv - rv).item() / ref_norm
+                            ok = det == 0 and err <= 2 * TOL[prec]
+                            gbs = 2 * total * esize / (ms * 1e-3) / 1e9
+                            log(f"{prec} N={N} ft={ft} n1={n1} v={va}/{vb} T={T} chunk={chunk} {ms:.4f} ms "
+                                f"{gbs:.1f} GB/s err={err:.2e} det={det}{'' if ok else ' REJECTED'}")
+                            if ok and (best is None or ms < best["ms"]):
+                                best = {"precision": prec, "N": N, "ft_mode": ft, "split_n1": n1,
+                                        "variant_a": va, "variant_b": vb, "T": T, "kappa": KAPPA[prec],
+                                        "ms": round(ms, 5), "gbs": round(gbs, 1)}
+                                if chunk:
+                                    best["chunk_bytes"] = chunk
+                if best:
+                    entries.append(best)
+                    log(f"best {prec} N={N} ft={ft}: {best}")
+                # back to the defaults before the next mode / length
+                tf.set_route(N, dtype, 0)
+                tf.set_tuning(N, dtype, T0, k0)
+                tf.set_chunk(N, dtype, 128 << 20)
         del x, y, ref
         torch.cuda.empty_cache()
     return entries
@@ -139,7 +144,7 @@ def main(argv=None):
                    log=lambda s: print(s, flush=True))
     doc = {"format": "tfft-tuning-1",
            "device": torch.cuda.get_device_name(0),
-           "workload": "1 GiB seeded batch per length, forward, ABFT correct",
+           "workload": "1 GiB seeded batch per length, forward, ABFT correct and off",
            "seconds": round(time.time() - t0, 1),
            "entries": entries}
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)

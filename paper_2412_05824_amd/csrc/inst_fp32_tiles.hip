@@ -18,6 +18,7 @@ template <int KIND> static void add_kind(std::vector<KernelEntry>& out) {
 void register_fp32_tiles(std::vector<KernelEntry>& out) {
     add_kind<kColPass>(out);
     add_kind<kRowPass>(out);
+    register_fp32_tiles_narrow(out);
 }
 
 }  // namespace tfft

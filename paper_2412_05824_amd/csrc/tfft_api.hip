@@ -71,18 +71,17 @@ struct Tuning {
     int T;
     double kappa;
     long long chunk_bytes;
-    long long split_n1;   // route: 0 default (single pass if built, else balanced split),
-                          // 1 single pass, > 1 column pass of this length then row pass
+    long long route;      // route code (see route_for): 0 the default policy
 };
 
 std::mutex g_mu;
 std::vector<KernelEntry>* g_entries = nullptr;
-std::map<std::tuple<int, int, int, int>, const KernelEntry*> g_by_key;   // (prec, kind, Ns, ft)
+std::map<std::tuple<int, int, int, int, int>, const KernelEntry*> g_by_key;   // (prec, kind, Ns, ft, variant)
 std::map<std::pair<int, int>, const KernelEntry*> g_ragged_by_key;      // (ragged plan id, ft)
 std::map<std::tuple<int, int, int, long long>, SubTables> g_sub;         // (prec, Ns, device, radices)
 std::map<std::tuple<int, long long, int>, PassTwiddle> g_pass;           // (prec, N, device)
 std::map<int, Workspace> g_ws;                                           // device
-std::map<std::pair<int, long long>, Tuning> g_tuning;
+std::map<std::tuple<int, long long, int>, Tuning> g_tuning;   // (prec, N, ft mode 0..2)
 
 struct Inject {
     bool armed = false;
@@ -114,13 +113,13 @@ void ensure_registry() {
     register_fp32_ragged_tiles(*g_entries);
     for (const KernelEntry& e : *g_entries) {
         if (e.ragged_id >= 0) g_ragged_by_key[std::make_pair(e.ragged_id, e.ft)] = &e;
-        else g_by_key[std::make_tuple(e.precision, e.kind, e.Ns, e.ft)] = &e;
+        else g_by_key[std::make_tuple(e.precision, e.kind, e.Ns, e.ft, e.variant)] = &e;
     }
 }
 
-const KernelEntry* find_entry(int precision, int kind, long long Ns, int ft) {
-    if (Ns > (1 << 30)) return nullptr;
-    auto it = g_by_key.find(std::make_tuple(precision, kind, (int)Ns, ft));
+const KernelEntry* find_entry(int precision, int kind, long long Ns, int ft, int variant = 0) {
+    if (Ns > (1 << 30) || variant < 0) return nullptr;
+    auto it = g_by_key.find(std::make_tuple(precision, kind, (int)Ns, ft, variant));
     return it == g_by_key.end() ? nullptr : it->second;
 }
 
@@ -133,26 +132,40 @@ struct Route {
     long long N1 = 0, N2 = 0;
 };
 
+// Route codes: n1 | va << 32 | vb << 40.  n1 = 1: single pass, plan variant
+// va; n1 > 1: column pass of n1 points (variant va), then row pass of N/n1
+// (variant vb); code 0: the default policy (single pass when built, else
+// the most balanced split, variants 0).
+constexpr long long route_code(long long n1, int va, int vb) {
+    return n1 | ((long long)va << 32) | ((long long)vb << 40);
+}
+inline long long route_n1(long long code) { return code & 0xffffffffLL; }
+inline int route_va(long long code) { return (int)((code >> 32) & 0xff); }
+inline int route_vb(long long code) { return (int)((code >> 40) & 0xff); }
+
 // a two-pass split N = n1 * n2 with compiled column and row kernels whose
 // tiles divide the other length
-bool split_ok(int precision, long long N, int ft, long long n1) {
+bool split_ok(int precision, long long N, int ft, long long n1, int va = 0, int vb = 0) {
     if (n1 < 2 || N % n1) return false;
     const long long n2 = N / n1;
-    const KernelEntry* c = find_entry(precision, kColPass, n1, ft);
-    const KernelEntry* w = find_entry(precision, kRowPass, n2, ft);
+    const KernelEntry* c = find_entry(precision, kColPass, n1, ft, va);
+    const KernelEntry* w = find_entry(precision, kRowPass, n2, ft, vb);
     return c && w && n2 % c->slots_per_block == 0 && n1 % w->slots_per_block == 0;
 }
 
-bool route_for(int precision, long long N, int ft, Route* r, long long split = 0) {
+bool route_for(int precision, long long N, int ft, Route* r, long long code = 0) {
     *r = Route{};
-    if (split <= 1) {
-        if ((r->single = find_entry(precision, kSingle, N, ft))) return true;
-        if (split == 1) return false;
+    if (code < 0 || (code >> 48) != 0) return false;
+    const long long n1c = route_n1(code);
+    const int va = route_va(code), vb = route_vb(code);
+    if (code == 0 || n1c == 1) {
+        if ((r->single = find_entry(precision, kSingle, N, ft, va))) return true;
+        if (code != 0) return false;
     }
     long long n1 = 0;
-    if (split > 1) {
-        if (!split_ok(precision, N, ft, split)) return false;
-        n1 = split;
+    if (code != 0) {
+        if (!split_ok(precision, N, ft, n1c, va, vb)) return false;
+        n1 = n1c;
     } else {
         // balanced split N = N1 * N2 with N1 <= N2
         for (long long c = 2; c * c <= N; c <<= 1)
@@ -161,8 +174,8 @@ bool route_for(int precision, long long N, int ft, Route* r, long long split = 0
     }
     r->N1 = n1;
     r->N2 = N / n1;
-    r->col = find_entry(precision, kColPass, r->N1, ft);
-    r->row = find_entry(precision, kRowPass, r->N2, ft);
+    r->col = find_entry(precision, kColPass, r->N1, ft, code ? va : 0);
+    r->row = find_entry(precision, kRowPass, r->N2, ft, code ? vb : 0);
     return true;
 }
 
@@ -173,7 +186,7 @@ Tuning default_tuning(int precision, long long N) {
     // under the 2e-6 relative tolerance; fp64 has ample margin.
     Tuning t{};
     t.chunk_bytes = 128ll << 20;
-    t.split_n1 = 0;
+    t.route = 0;
     if (precision == TFFT_FP32) {
         t.kappa = 8.0;
         t.T = N <= 128 ? 2 : 1;
@@ -184,9 +197,25 @@ Tuning default_tuning(int precision, long long N) {
     return t;
 }
 
-Tuning get_tuning(int precision, long long N) {
-    auto it = g_tuning.find(std::make_pair(precision, N));
+// tuning of (precision, N) for an ABFT mode (the in-place correcting
+// variant shares the correcting mode's entry)
+Tuning get_tuning(int precision, long long N, int ft = TFFT_FT_CORRECT) {
+    if (ft > TFFT_FT_CORRECT) ft = TFFT_FT_CORRECT;
+    auto it = g_tuning.find(std::make_tuple(precision, N, ft));
+    // detection without an entry of its own follows the correcting mode
+    // (same kernels up to the correction path)
+    if (it == g_tuning.end() && ft == TFFT_FT_DETECT)
+        it = g_tuning.find(std::make_tuple(precision, N, (int)TFFT_FT_CORRECT));
     return it == g_tuning.end() ? default_tuning(precision, N) : it->second;
+}
+
+// apply fn to the tuning of (precision, N) in every ABFT mode
+template <class F> void update_tuning(int precision, long long N, F fn) {
+    for (int ft = 0; ft <= TFFT_FT_CORRECT; ++ft) {
+        Tuning tu = get_tuning(precision, N, ft);
+        fn(tu);
+        g_tuning[std::make_tuple(precision, N, ft)] = tu;
+    }
 }
 
 template <class R> void put(std::vector<R>& v, long double re, long double im) {
@@ -856,8 +885,10 @@ int ragged_exec(tfft_ragged_plan_s* P, const void* x, void* y, int dir, int unit
 
 // ---------------------------------------------------------------------------
 // Tuning table file (JSON): {"entries": [{"precision": "fp32" | "fp64" | 0 | 1,
-// "N": n, "split_n1": s, "T": t, "kappa": k, "chunk_bytes": b, ...}, ...]}.
-// Unknown keys are ignored; missing ones keep their current value.
+// "N": n, "ft_mode": f, "split_n1": s, "variant_a": va, "variant_b": vb,
+// "T": t, "kappa": k, "chunk_bytes": b, ...}, ...]}.  An entry without
+// ft_mode applies to every ABFT mode.  Unknown keys are ignored; missing
+// ones keep their current value.
 // ---------------------------------------------------------------------------
 struct JVal {
     enum Kind { kNull, kBool, kNum, kStr, kArr, kObj } kind = kNull;
@@ -1003,7 +1034,7 @@ int tfft_prepare(long long N, int precision, int ft_mode) {
     std::lock_guard<std::mutex> lk(g_mu);
     ensure_registry();
     Route r;
-    if (!route_for(precision, N, ft_mode, &r, get_tuning(precision, N).split_n1)) return TFFT_EUNSUPPORTED;
+    if (!route_for(precision, N, ft_mode, &r, get_tuning(precision, N, ft_mode).route)) return TFFT_EUNSUPPORTED;
     SubTables* st = nullptr;
     if (r.single) return get_sub(*r.single, true, &st);
     int rc = get_sub(*r.col, true, &st);
@@ -1016,50 +1047,64 @@ int tfft_prepare(long long N, int precision, int ft_mode) {
 int tfft_set_tuning(long long N, int precision, int T, double kappa) {
     if (N < 1 || check_precision(precision) != TFFT_OK || T < 0 || T > 32 || kappa < 0) return TFFT_EINVAL;
     std::lock_guard<std::mutex> lk(g_mu);
-    Tuning tu = get_tuning(precision, N);
-    if (T > 0) tu.T = T;
-    if (kappa > 0) tu.kappa = kappa;
-    g_tuning[std::make_pair(precision, N)] = tu;
+    update_tuning(precision, N, [&](Tuning& tu) {
+        if (T > 0) tu.T = T;
+        if (kappa > 0) tu.kappa = kappa;
+    });
     return TFFT_OK;
 }
 
-int tfft_routes(long long N, int precision, int ft_mode, long long* n1_out, int cap) {
+int tfft_routes(long long N, int precision, int ft_mode, long long* codes, int cap) {
     if (N < 1 || check_precision(precision) != TFFT_OK || ft_mode < 0 || ft_mode > 2 || cap < 0 ||
-        (cap > 0 && !n1_out))
+        (cap > 0 && !codes))
         return TFFT_EINVAL;
     std::lock_guard<std::mutex> lk(g_mu);
     ensure_registry();
     int n = 0;
     auto put_route = [&](long long v) {
-        if (n < cap) n1_out[n] = v;
+        if (n < cap) codes[n] = v;
         ++n;
     };
-    if (find_entry(precision, kSingle, N, ft_mode)) put_route(1);
+    for (int v = 0; v < 8; ++v)
+        if (find_entry(precision, kSingle, N, ft_mode, v)) put_route(route_code(1, v, 0));
     for (long long c = 2; c < N; c <<= 1)
-        if (split_ok(precision, N, ft_mode, c)) put_route(c);
+        for (int va = 0; va < 8; ++va)
+            for (int vb = 0; vb < 8; ++vb)
+                if (split_ok(precision, N, ft_mode, c, va, vb)) put_route(route_code(c, va, vb));
     return n;
 }
 
-int tfft_set_route(long long N, int precision, long long split_n1) {
-    if (N < 1 || check_precision(precision) != TFFT_OK || split_n1 < 0) return TFFT_EINVAL;
-    std::lock_guard<std::mutex> lk(g_mu);
-    ensure_registry();
+// route of (precision, N) in one ABFT mode (ft 0..2) or in all (ft < 0)
+int set_route_locked(long long N, int precision, int ft, long long code) {
     Route r;
-    if (split_n1 != 0 && !route_for(precision, N, TFFT_FT_OFF, &r, split_n1)) return TFFT_EUNSUPPORTED;
-    Tuning tu = get_tuning(precision, N);
-    tu.split_n1 = split_n1;
-    g_tuning[std::make_pair(precision, N)] = tu;
+    for (int f = 0; f <= TFFT_FT_CORRECT; ++f)
+        if ((ft < 0 || f == ft) && code != 0 && !route_for(precision, N, f, &r, code)) return TFFT_EUNSUPPORTED;
+    for (int f = 0; f <= TFFT_FT_CORRECT; ++f) {
+        if (ft >= 0 && f != ft) continue;
+        Tuning tu = get_tuning(precision, N, f);
+        tu.route = code;
+        g_tuning[std::make_tuple(precision, N, f)] = tu;
+    }
     return TFFT_OK;
 }
 
-int tfft_get_route(long long N, int precision, int ft_mode, long long* n1) {
-    if (!n1 || N < 1 || check_precision(precision) != TFFT_OK || ft_mode < 0 || ft_mode > 2)
+int tfft_set_route(long long N, int precision, long long code) {
+    if (N < 1 || check_precision(precision) != TFFT_OK || code < 0) return TFFT_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    ensure_registry();
+    return set_route_locked(N, precision, -1, code);
+}
+
+int tfft_get_route(long long N, int precision, int ft_mode, long long* code) {
+    if (!code || N < 1 || check_precision(precision) != TFFT_OK || ft_mode < 0 || ft_mode > 2)
         return TFFT_EINVAL;
     std::lock_guard<std::mutex> lk(g_mu);
     ensure_registry();
     Route r;
-    if (!route_for(precision, N, ft_mode, &r, get_tuning(precision, N).split_n1)) return TFFT_EUNSUPPORTED;
-    *n1 = r.single ? 1 : r.N1;
+    const long long c = get_tuning(precision, N, ft_mode).route;
+    if (!route_for(precision, N, ft_mode, &r, c)) return TFFT_EUNSUPPORTED;
+    if (r.single) *code = route_code(1, r.single->variant, 0);
+    else *code = route_code(r.N1, r.col->variant, r.row->variant);
     return TFFT_OK;
 }
 
@@ -1080,7 +1125,13 @@ int tfft_load_tuning(const char* path) {
     std::lock_guard<std::mutex> lk(g_mu);
     ensure_registry();
     // validate every entry before applying any
-    std::vector<std::pair<std::pair<int, long long>, Tuning>> pending;
+    std::vector<std::pair<std::tuple<int, long long, int>, Tuning>> pending;
+    auto current = [&](int prec, long long N, int ft) {
+        Tuning tu = get_tuning(prec, N, ft);
+        for (auto& q : pending)
+            if (q.first == std::make_tuple(prec, N, ft)) tu = q.second;
+        return tu;
+    };
     for (const JVal& e : entries->arr) {
         if (e.kind != JVal::kObj) return TFFT_EINVAL;
         const JVal* pv = e.get("precision");
@@ -1089,38 +1140,48 @@ int tfft_load_tuning(const char* path) {
         else if (pv && pv->kind == JVal::kNum) prec = (int)pv->num;
         long long N = 0;
         if (check_precision(prec) != TFFT_OK || !json_int(e.get("N"), &N) || N < 1) return TFFT_EINVAL;
-        Tuning tu = get_tuning(prec, N);
-        for (auto& q : pending)
-            if (q.first == std::make_pair(prec, N)) tu = q.second;
-        long long v = 0;
-        if (e.get("split_n1")) {
-            if (!json_int(e.get("split_n1"), &v) || v < 0) return TFFT_EINVAL;
-            Route r;
-            if (v != 0 && !route_for(prec, N, TFFT_FT_OFF, &r, v)) return TFFT_EUNSUPPORTED;
-            tu.split_n1 = v;
+        long long ftv = -1;   // absent: every mode
+        if (e.get("ft_mode") && (!json_int(e.get("ft_mode"), &ftv) || ftv < 0 || ftv > 2)) return TFFT_EINVAL;
+        for (int ft = 0; ft <= TFFT_FT_CORRECT; ++ft) {
+            if (ftv >= 0 && ft != ftv) continue;
+            Tuning tu = current(prec, N, ft);
+            long long v = 0;
+            if (e.get("split_n1")) {
+                long long va = 0, vb = 0;
+                if (!json_int(e.get("split_n1"), &v) || v < 0 || v > 0xffffffffLL) return TFFT_EINVAL;
+                if (e.get("variant_a") && (!json_int(e.get("variant_a"), &va) || va < 0 || va > 255)) return TFFT_EINVAL;
+                if (e.get("variant_b") && (!json_int(e.get("variant_b"), &vb) || vb < 0 || vb > 255)) return TFFT_EINVAL;
+                const long long code = v == 0 ? 0 : route_code(v, (int)va, (int)vb);
+                Route r;
+                if (code != 0 && !route_for(prec, N, ft, &r, code)) return TFFT_EUNSUPPORTED;
+                tu.route = code;
+            }
+            if (e.get("T")) {
+                if (!json_int(e.get("T"), &v) || v < 1 || v > 32) return TFFT_EINVAL;
+                tu.T = (int)v;
+            }
+            if (e.get("chunk_bytes")) {
+                if (!json_int(e.get("chunk_bytes"), &v) || v < 1) return TFFT_EINVAL;
+                tu.chunk_bytes = v;
+            }
+            if (const JVal* k = e.get("kappa")) {
+                if (k->kind != JVal::kNum || !(k->num > 0)) return TFFT_EINVAL;
+                tu.kappa = k->num;
+            }
+            bool found = false;
+            for (auto& q : pending)
+                if (q.first == std::make_tuple(prec, N, ft)) { q.second = tu; found = true; }
+            if (!found) pending.emplace_back(std::make_tuple(prec, N, ft), tu);
         }
-        if (e.get("T")) {
-            if (!json_int(e.get("T"), &v) || v < 1 || v > 32) return TFFT_EINVAL;
-            tu.T = (int)v;
-        }
-        if (e.get("chunk_bytes")) {
-            if (!json_int(e.get("chunk_bytes"), &v) || v < 1) return TFFT_EINVAL;
-            tu.chunk_bytes = v;
-        }
-        if (const JVal* k = e.get("kappa")) {
-            if (k->kind != JVal::kNum || !(k->num > 0)) return TFFT_EINVAL;
-            tu.kappa = k->num;
-        }
-        pending.emplace_back(std::make_pair(prec, N), tu);
     }
     for (auto& q : pending) g_tuning[q.first] = q.second;
-    return (int)pending.size();
+    return (int)entries->arr.size();
 }
 
 int tfft_get_tuning(long long N, int precision, int* T, double* kappa) {
     if (!T || !kappa || check_precision(precision) != TFFT_OK) return TFFT_EINVAL;
     std::lock_guard<std::mutex> lk(g_mu);
-    Tuning tu = get_tuning(precision, N);
+    Tuning tu = get_tuning(precision, N, TFFT_FT_CORRECT);
     *T = tu.T;
     *kappa = tu.kappa;
     return TFFT_OK;
@@ -1129,9 +1190,9 @@ int tfft_get_tuning(long long N, int precision, int* T, double* kappa) {
 int tfft_set_chunk(long long N, int precision, long long chunk_bytes) {
     if (N < 1 || check_precision(precision) != TFFT_OK || chunk_bytes < 0) return TFFT_EINVAL;
     std::lock_guard<std::mutex> lk(g_mu);
-    Tuning tu = get_tuning(precision, N);
-    if (chunk_bytes > 0) tu.chunk_bytes = chunk_bytes;
-    g_tuning[std::make_pair(precision, N)] = tu;
+    update_tuning(precision, N, [&](Tuning& tu) {
+        if (chunk_bytes > 0) tu.chunk_bytes = chunk_bytes;
+    });
     return TFFT_OK;
 }
 
@@ -1223,12 +1284,12 @@ int tfft_c2c(const void* x, void* y, long long N, long long batch, int dir, int 
 
     std::lock_guard<std::mutex> lk(g_mu);
     ensure_registry();
-    const Tuning tu = get_tuning(precision, N);
+    const Tuning tu = get_tuning(precision, N, ft_mode);
     Route rt;
-    if (!route_for(precision, N, ft_mode, &rt, tu.split_n1)) return TFFT_EUNSUPPORTED;
+    if (!route_for(precision, N, ft_mode, &rt, tu.route)) return TFFT_EUNSUPPORTED;
     if (rt.single && ft_mode == TFFT_FT_CORRECT && x == y) {
         // in place: the kernel variant that keeps the right-side input sum
-        rt.single = find_entry(precision, kSingle, N, 3);
+        rt.single = find_entry(precision, kSingle, N, 3, rt.single->variant);
         if (!rt.single) return TFFT_EUNSUPPORTED;
     }
     Inject inj = g_inj;

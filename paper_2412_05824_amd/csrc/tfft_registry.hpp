@@ -25,6 +25,7 @@ struct KernelEntry {
     int radices[kMaxStages];
     LaunchFn launch;
     int ragged_id;          // index in the ragged plan list (-1: regular plan)
+    int variant;            // plans of one (kind, Ns): 0 default, 1.. alternatives
 };
 
 template <class V, class PL, int FT, bool IND, int... Rs>
@@ -51,22 +52,29 @@ template <class V, class PL, int FT, bool IND, int... Rs> KernelEntry make_entry
     for (int i = 0; i < e.n_stages; ++i) e.radices[i] = rs[i];
     e.launch = &launch_fft<V, PL, FT, IND, Rs...>;
     e.ragged_id = -1;
+    e.variant = 0;
     return e;
 }
 
 // register the ABFT modes of one plan (in-place correction: single pass only;
 // the passes of a two-pass transform never overwrite their own inputs)
 template <class V, int KIND, int Ns, int E, int WC, int B, int... Rs>
-void add_plan(std::vector<KernelEntry>& out, int precision) {
+void add_plan(std::vector<KernelEntry>& out, int precision, int variant = 0) {
     using PL = Plan<KIND, Ns, E, WC, B, Rs...>;
-    out.push_back(make_entry<V, PL, 0, false, Rs...>(precision));
-    out.push_back(make_entry<V, PL, 1, false, Rs...>(precision));
-    out.push_back(make_entry<V, PL, 2, false, Rs...>(precision));
-    if constexpr (KIND == kSingle) out.push_back(make_entry<V, PL, 3, false, Rs...>(precision));
+    KernelEntry e[4] = {make_entry<V, PL, 0, false, Rs...>(precision),
+                        make_entry<V, PL, 1, false, Rs...>(precision),
+                        make_entry<V, PL, 2, false, Rs...>(precision), {}};
+    int n = 3;
+    if constexpr (KIND == kSingle) e[n++] = make_entry<V, PL, 3, false, Rs...>(precision);
+    for (int i = 0; i < n; ++i) {
+        e[i].variant = variant;
+        out.push_back(e[i]);
+    }
 }
 
 void register_fp32_single(std::vector<KernelEntry>& out);
 void register_fp32_tiles(std::vector<KernelEntry>& out);
+void register_fp32_tiles_narrow(std::vector<KernelEntry>& out);
 void register_fp64_single(std::vector<KernelEntry>& out);
 void register_fp64_tiles(std::vector<KernelEntry>& out);
 

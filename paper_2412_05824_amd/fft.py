@@ -198,8 +198,19 @@ def fft_c2c_ragged(packed: torch.Tensor, sizes, dir: int = -1, ft_mode: int = 2,
 
 
 # ---- routes and the tuning table ----
+def route_code(n1: int, variant_a: int = 0, variant_b: int = 0) -> int:
+    """Route code: n1 = 1 single pass (plan variant_a), n1 > 1 column pass of n1
+    points (variant_a) then row pass of N/n1 (variant_b)."""
+    return int(n1) | (int(variant_a) << 32) | (int(variant_b) << 40)
+
+
+def route_parts(code: int):
+    """(n1, variant_a, variant_b) of a route code."""
+    return code & 0xFFFFFFFF, (code >> 32) & 0xFF, (code >> 40) & 0xFF
+
+
 def routes(N: int, dtype=torch.complex64, ft_mode: int = 2) -> list:
-    """Candidate routes of length N: 1 = single pass, n1 > 1 = column pass n1, row pass N/n1."""
+    """Route codes built for length N (see route_code)."""
     import ctypes
     lib = _lib.load()
     n = lib.tfft_routes(N, _precision(dtype), ft_mode, None, 0)
@@ -209,8 +220,9 @@ def routes(N: int, dtype=torch.complex64, ft_mode: int = 2) -> list:
     return [int(buf[i]) for i in range(n)]
 
 
-def set_route(N: int, dtype, split_n1: int) -> None:
-    _lib.check(_lib.load().tfft_set_route(N, _precision(dtype), split_n1), f"tfft_set_route(N={N})")
+def set_route(N: int, dtype, code: int) -> None:
+    """Fix the route of length N in every ABFT mode (0: the default policy)."""
+    _lib.check(_lib.load().tfft_set_route(N, _precision(dtype), code), f"tfft_set_route(N={N})")
 
 
 def get_route(N: int, dtype=torch.complex64, ft_mode: int = 2) -> int:

@@ -103,7 +103,8 @@ def test_ragged_invalid_arguments_rejected_on_host():
 
 def test_routes_and_forced_split():
     """Multi-pass decomposition choices (Sec. 3.1): the default route of a
-    length, the candidate list, and forcing a split."""
+    length, the candidate list (codes n1 | va << 32 | vb << 40), and forcing
+    a route."""
     lib = _lib.load()
     FP32 = _lib.FP32
 
@@ -118,22 +119,32 @@ def test_routes_and_forced_split():
         assert lib.tfft_get_route(n, prec, 2, ctypes.byref(v)) == _lib.TFFT_OK
         return v.value
 
+    n1 = lambda c: c & 0xFFFFFFFF
     r4096 = routes(4096)
     assert r4096[0] == 1 and len(r4096) > 1          # single pass, and splits
+    assert lib.tfft_set_route(1 << 20, FP32, 0) == _lib.TFFT_OK   # the default policy, not the table's
+    assert lib.tfft_set_route(4096, FP32, 0) == _lib.TFFT_OK
     assert route(4096) == 1
     big = routes(1 << 20)
-    assert 1 not in big and all((1 << 20) % n1 == 0 for n1 in big)
+    assert all(n1(c) > 1 and (1 << 20) % n1(c) == 0 for c in big)
+    assert any(c >> 32 for c in big)                   # tile-width variants exist
     default = route(1 << 20)
-    assert default in big and default * default <= (1 << 20)
+    assert default in big and n1(default) ** 2 <= (1 << 20) and default >> 32 == 0
     try:
-        alt = [n1 for n1 in r4096 if n1 > 1][0]
+        alt = [c for c in r4096 if n1(c) > 1][0]
         assert lib.tfft_set_route(4096, FP32, alt) == _lib.TFFT_OK
         assert route(4096) == alt
         assert lib.tfft_set_route(4096, FP32, 3) == _lib.TFFT_EUNSUPPORTED
         assert lib.tfft_set_route(1 << 20, FP32, 1) == _lib.TFFT_EUNSUPPORTED
+        assert lib.tfft_set_route(4096, FP32, 1 | (7 << 32)) == _lib.TFFT_EUNSUPPORTED
+        wide = [c for c in big if c >> 32][0]
+        assert lib.tfft_set_route(1 << 20, FP32, wide) == _lib.TFFT_OK
+        assert route(1 << 20) == wide
     finally:
         assert lib.tfft_set_route(4096, FP32, 0) == _lib.TFFT_OK
-    assert route(4096) == 1
+        assert lib.tfft_set_route(1 << 20, FP32, 0) == _lib.TFFT_OK
+        if os.path.exists(_lib.TUNING_PATH):   # back to the package's table
+            assert lib.tfft_load_tuning(_lib.TUNING_PATH.encode()) >= 0
 
 
 def test_load_tuning_table(tmp_path):
@@ -144,9 +155,17 @@ def test_load_tuning_table(tmp_path):
     good.write_text(json.dumps({"format": "x", "entries": [
         {"precision": "fp32", "N": 2048, "T": 1, "kappa": 9.5, "split_n1": 0, "gbs": 1.0},
         {"precision": "fp64", "N": 1024, "T": 4, "chunk_bytes": 1 << 26},
+        {"precision": "fp32", "N": 1 << 20, "ft_mode": 0, "split_n1": 512, "variant_a": 1, "variant_b": 1},
     ]}))
+    route = ctypes.c_longlong()
+    before = ctypes.c_longlong()
+    assert lib.tfft_get_route(1 << 20, _lib.FP32, 2, ctypes.byref(before)) == 0
     try:
-        assert lib.tfft_load_tuning(str(good).encode()) == 2
+        assert lib.tfft_load_tuning(str(good).encode()) == 3
+        assert lib.tfft_get_route(1 << 20, _lib.FP32, 0, ctypes.byref(route)) == 0
+        assert route.value == 512 | (1 << 32) | (1 << 40)
+        assert lib.tfft_get_route(1 << 20, _lib.FP32, 2, ctypes.byref(route)) == 0
+        assert route.value == before.value              # the other modes keep their route
         assert lib.tfft_get_tuning(2048, _lib.FP32, ctypes.byref(T), ctypes.byref(k)) == 0
         assert (T.value, k.value) == (1, 9.5)
         assert lib.tfft_get_tuning(1024, _lib.FP64, ctypes.byref(T), ctypes.byref(k)) == 0
@@ -166,3 +185,6 @@ def test_load_tuning_table(tmp_path):
         lib.tfft_set_tuning(2048, _lib.FP32, 1, 8.0)
         lib.tfft_set_tuning(1024, _lib.FP64, 8, 16.0)
         lib.tfft_set_chunk(1024, _lib.FP64, 128 << 20)
+        lib.tfft_set_route(1 << 20, _lib.FP32, 0)
+        if os.path.exists(_lib.TUNING_PATH):
+            assert lib.tfft_load_tuning(_lib.TUNING_PATH.encode()) >= 0

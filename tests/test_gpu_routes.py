@@ -50,14 +50,15 @@ def test_every_route_matches_oracle(dev, dtype, N):
     assert routes, N
     T0, k0 = tf.get_tuning(N, dtype)
     try:
-        for n1 in routes:
-            tf.set_route(N, dtype, n1)
-            assert tf.get_route(N, dtype) == n1
+        for code in routes:
+            n1 = tf.route_parts(code)[0]
+            tf.set_route(N, dtype, code)
+            assert tf.get_route(N, dtype) == code
             # two chunks at least on the two-pass routes, with a ragged last one
             if n1 > 1:
                 tf.set_chunk(N, dtype, max(N * (16 if dtype == torch.complex128 else 8) * 3, 1 << 20))
             batch = max(5, (1 << 21) // N) + 1
-            _check(dev, dtype, N, batch, seed=N + n1)
+            _check(dev, dtype, N, batch, seed=N + n1 + (code >> 32))
     finally:
         tf.set_route(N, dtype, 0)
         tf.set_tuning(N, dtype, T0, k0)
