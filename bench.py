@@ -41,6 +41,7 @@ def kernel_fingerprint() -> str:
     m = hashlib.sha256()
     pkg = os.path.join(ROOT, "paper_2412_05824_amd")
     for f in ("csrc/tfft_device.hpp", "csrc/tfft_kernels.hpp", "csrc/inst_fp32_single.hip",
+              "csrc/inst_fp32_single_e8.hip",
               "csrc/inst_fp32_tiles.hip", "csrc/inst_fp32_tiles_narrow.hip", "tuning/mi355x.json"):
         path = os.path.join(pkg, f)
         if os.path.exists(path):

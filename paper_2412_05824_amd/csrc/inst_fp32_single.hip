@@ -1,6 +1,6 @@
 // Single-pass fp32 kernels: E = 16 elements per lane, radix-16 stages after
-// one smaller leading radix, 4 waves per workgroup for sub-wave slots, XOR
-// swizzle over 16-element (128-byte) LDS rows.
+// one smaller leading radix, 4 waves per workgroup for sub-wave slots, one
+// LDS pad element per 16 (128-byte rows).
 #include "tfft_registry.hpp"
 
 namespace tfft {
@@ -14,6 +14,7 @@ void register_fp32_single(std::vector<KernelEntry>& out) {
     add_plan<float2, kSingle, 2048, 16, 4, 4, 8, 16, 16>(out, 0);
     add_plan<float2, kSingle, 4096, 16, 4, 4, 16, 16, 16>(out, 0);
     add_plan<float2, kSingle, 8192, 16, 4, 4, 2, 16, 16, 16>(out, 0);
+    register_fp32_single_e8(out);
 }
 
 }  // namespace tfft

@@ -42,7 +42,7 @@ def _check(dev, dtype, N, batch, seed):
         assert e <= TOL[dtype], (N, int(pick[i]), e)
 
 
-@pytest.mark.parametrize("dtype,N", [(torch.complex64, 1 << 12), (torch.complex64, 1 << 14),
+@pytest.mark.parametrize("dtype,N", [(torch.complex64, 1 << 12), (torch.complex64, 1 << 13), (torch.complex64, 1 << 14),
                                      (torch.complex64, 1 << 17), (torch.complex64, 1 << 20),
                                      (torch.complex128, 1 << 11), (torch.complex128, 1 << 16)])
 def test_every_route_matches_oracle(dev, dtype, N):
