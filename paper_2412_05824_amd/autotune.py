@@ -2,14 +2,16 @@
 write the fastest into a JSON tuning table that the library loads
 (tfft_load_tuning).
 
-Per (precision, N) and ABFT mode (correct, off) it sweeps:
+Per (precision, N) it sweeps, with ABFT correction on:
   * the route: single pass (when built) or each column/row split n1 x N/n1
     (the multi-pass decomposition of Sec. 3.1), over the compiled plan
-    variants (tile widths) of each pass;
+    variants (tile width, elements per lane) of each pass;
   * T, the transactions per checksum group (Sec. 4.3), limited by the
     accuracy bound below;
   * for two-pass routes, the chunk of signals whose intermediate lives in
-    the workspace.
+    the workspace;
+then, without ABFT, T and the chunk again on the same route (a shared plan
+keeps outputs bit-identical whether ABFT is on or off).
 Each candidate runs on a 1 GiB seeded batch; it must count no detection on
 fault-free data and agree with the default configuration's output to
 within twice the precision's tolerance (two correct transforms differ by at
@@ -85,9 +87,14 @@ def tune(precisions, logs, modes=(2, 0), reps=5, warmup=2, total_bytes=1 << 30, 
             tf.fft_c2c(xv, ft_mode=tf.FT_OFF, out=rv)
             torch.cuda.synchronize()
             ref_norm = torch.linalg.vector_norm(rv).item()
+            best_code = None
             for ft in modes:
                 best = None
-                for code in tf.routes(N, dtype, ft):
+                # every mode runs the plan chosen for the first (correcting)
+                # mode, so switching ABFT on or off never changes an output
+                # bit; the other modes tune only T and the chunk
+                codes = tf.routes(N, dtype, ft) if best_code is None else [best_code]
+                for code in codes:
                     n1, va, vb = tf.route_parts(code)
                     longest = N if n1 == 1 else max(n1, N // n1)
                     # without ABFT, T only sets the signals per workgroup
@@ -117,6 +124,8 @@ def tune(precisions, logs, modes=(2, 0), reps=5, warmup=2, total_bytes=1 << 30, 
                 if best:
                     entries.append(best)
                     log(f"best {prec} N={N} ft={ft}: {best}")
+                    if best_code is None:
+                        best_code = tf.route_code(best["split_n1"], best["variant_a"], best["variant_b"])
                 # back to the defaults before the next mode / length
                 tf.set_route(N, dtype, 0)
                 tf.set_tuning(N, dtype, T0, k0)

@@ -515,7 +515,10 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
     }
     if constexpr (PL::KIND == kRowPass)
         g.twiddle_setup(a, reinterpret_cast<V*>(smem + Smem<V, PL, FT>::TWS_OFF));
-    if constexpr (PL::KIND == kRowPass || Smem<V, PL, FT>::AW_LDS) lds_sync<PL::MULTI_WAVE>();
+    // these tables are written by some waves and read by all: a workgroup
+    // barrier whenever the workgroup has more than one wave (sub-wave slots
+    // otherwise only synchronise within their wave)
+    if constexpr (PL::KIND == kRowPass || Smem<V, PL, FT>::AW_LDS) lds_sync<(PL::THREADS > kWave)>();
     const auto li = g.lidx();
     constexpr bool KEEP_XS = FT == 3;   // in place: inputs are gone after the store
     const int t = g.t;
