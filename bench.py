@@ -287,8 +287,21 @@ def main():
 
 
 def ragged_compare(tf, synth, np, torch, dev, args):
-    """Time the ragged workload in its three forms; returns a dict for the JSON line."""
-    sizes = [int(n) for n in synth.ragged_sizes(args.ragged_signals, seed=5)]
+    """Time the ragged workload in its three forms; returns a dict for the JSON
+    line, with a second, small-signal batch (lengths 64..3072) as context."""
+    out = ragged_one(tf, synth, np, torch, dev, args,
+                     [int(n) for n in synth.ragged_sizes(args.ragged_signals, seed=5)],
+                     "lengths uniform over 2^k and 3*2^k, 6<=k<=16 (seed 5)")
+    small_menu = [n for n in synth.RAGGED_SIZES if n <= 3072]
+    out["small_signals"] = ragged_one(
+        tf, synth, np, torch, dev, args,
+        [int(n) for n in synth.ragged_sizes(2000, seed=6, menu=small_menu)],
+        "lengths uniform over 2^k and 3*2^k, 6<=k<=10 (seed 6)")
+    return out
+
+
+def ragged_one(tf, synth, np, torch, dev, args, sizes, desc):
+    """One ragged batch in its three forms."""
     total = int(sum(sizes))
     x = torch.from_numpy(synth.signals(1, total, seed=2005).reshape(-1)).to(dev)
     y = torch.empty_like(x)

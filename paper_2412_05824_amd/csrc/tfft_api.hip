@@ -585,9 +585,20 @@ int ragged_build(tfft_ragged_plan_s* P, const long long* sizes, long long count)
     // blocks per work item: about g_ragged_item elements, so that the queue
     // and descriptor traffic of an item is small next to its data; tile runs
     // stay inside one group of signals
-    auto per_item = [](const KernelEntry& e, int T, int tiles) {
+    // ... but at least about four items per resident workgroup, so that a
+    // small batch still spreads over the whole GPU
+    hipDeviceProp_t prop{};
+    hipError_t perr = hipGetDeviceProperties(&prop, P->device);
+    if (perr != hipSuccess) return hip_fail(perr);
+    P->cus = prop.multiProcessorCount;
+    long long work = 0;   // element passes of the whole batch
+    for (Len& L : lens) work += (long long)L.ids.size() * L.N * (L.rt.single ? 1 : 2);
+    const long long resident =
+        std::max(1ll, (long long)ragged_kernel(TFFT_FT_CORRECT, P->waves).blocks_per_cu * P->cus);
+    const long long item_elems = std::max(1ll, std::min(g_ragged_item, work / (4 * resident)));
+    auto per_item = [item_elems](const KernelEntry& e, int T, int tiles) {
         const long long per_block = (long long)e.slots_per_block * T * e.Ns;
-        long long k = g_ragged_item / per_block;
+        long long k = item_elems / per_block;
         if (k < 1) k = 1;
         if (tiles > 0) {
             if (k > tiles) k = tiles;
@@ -813,10 +824,6 @@ int ragged_build(tfft_ragged_plan_s* P, const long long* sizes, long long count)
     err = hipMemcpy(P->buf, host.data(), bytes, hipMemcpyHostToDevice);
     if (err != hipSuccess) return hip_fail(err);
 
-    hipDeviceProp_t prop{};
-    err = hipGetDeviceProperties(&prop, P->device);
-    if (err != hipSuccess) return hip_fail(err);
-    P->cus = prop.multiProcessorCount;
     return TFFT_OK;
 }
 
