@@ -12,6 +12,10 @@ Printed as ONE JSON line, with:
   * roofline: the kernel that takes most of the step, HBM-bound, achieved
     GB/s from HIP events on the launch stream against 8 TB/s;
   * cpu_baseline: the fp64 CPU oracle on a bounded sample of the same sweep;
+  * fp64_sweep: complex128 forward and inverse, N = 2^6..2^20, batch 2^26/N,
+    standard-normal inputs, ABFT off and correct, seeded single-bit flips;
+  * autograd: loss = sum(w * |FFT(x)|^2) on x complex64 [16384, 4096], one
+    forward + backward (ABFT-protected adjoint) per step;
   * ragged: 10,000 signals with lengths drawn uniformly from {2^k, 3*2^k :
     6 <= k <= 16} (seeded), ABFT on, as one persistent launch replayed from a
     captured graph against one launch per length and pass (eager and
@@ -60,6 +64,8 @@ def parse():
     p.add_argument("--no-extra", action="store_true", help="skip the off/injection sweep")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--no-ragged", action="store_true", help="skip the ragged-batch comparison")
+    p.add_argument("--no-fp64", action="store_true", help="skip the fp64 forward+inverse sweep")
+    p.add_argument("--no-autograd", action="store_true", help="skip the autograd step")
     p.add_argument("--ragged-only", action="store_true",
                    help="only run the ragged-batch comparison (for profiling its kernels)")
     p.add_argument("--ragged-signals", type=int, default=10000)
@@ -211,6 +217,9 @@ def main():
     if not args.no_ragged:
         ragged = ragged_compare(tf, synth, np, torch, dev, args)
 
+    fp64 = None if args.no_fp64 else fp64_sweep(tf, torch, dev, args)
+    grad = None if args.no_autograd else autograd_step(tf, torch, dev, args)
+
     # ---- roofline of the kernel that takes most of the step ----
     dom = max(kernels, key=lambda k: k["total_ms"])
     dom_name = f"{dom['precision']} {dom['kind']} Ns={dom['Ns']} ft={dom['ft']}"
@@ -282,8 +291,106 @@ def main():
         "clean_counts": c_clean,
         "sweep": {str(k): v for k, v in sweep.items()},
         "ragged": ragged,
+        "fp64_sweep": fp64,
+        "autograd": grad,
     }
     print(json.dumps(out), flush=True)
+
+
+def fp64_sweep(tf, torch, dev, args):
+    """complex128 forward+inverse sweep with ABFT off / correct and seeded
+    flips; inputs standard normal, generated on the device from a seed."""
+    import numpy as np
+    total = 1 << 26                              # 1 GiB of complex128
+    g = torch.Generator(device=dev)
+    g.manual_seed(3000)
+    x = torch.randn(total, 2, dtype=torch.float64, device=dev, generator=g).view(torch.complex128).view(-1)
+    y = torch.empty_like(x)
+    counts = tf.new_counts(dev)
+    rng = np.random.default_rng(3001)
+    reps = max(3, args.steps // 2)
+    out = {}
+    for lg in range(6, 21):
+        N = 1 << lg
+        if not tf.supported(N, torch.complex128):
+            continue
+        xv, yv = x.view(-1, N), y.view(-1, N)
+        ms = {}
+        for ft in (tf.FT_OFF, tf.FT_CORRECT):
+            def step():
+                tf.fft_c2c(xv, dir=tf.FORWARD, ft_mode=ft, out=yv, counts=counts)
+                tf.fft_c2c(yv, dir=tf.INVERSE, ft_mode=ft, out=yv, counts=counts)
+            for _ in range(max(1, args.warmup)):
+                step()
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(reps):
+                step()
+            b.record()
+            torch.cuda.synchronize()
+            ms[ft] = a.elapsed_time(b) / reps
+        # seeded flips: one in a forward and one in an inverse launch
+        counts.zero_()
+        flips = []
+        for d in (tf.FORWARD, tf.INVERSE):
+            sig, elem = int(rng.integers(0, total // N)), int(rng.integers(0, N))
+            part, bit = int(rng.integers(0, 2)), int(rng.integers(0, 63))
+            tf.inject_arm(sig, elem, part, bit, dtype=torch.complex128)
+            tf.fft_c2c(xv, dir=d, ft_mode=tf.FT_CORRECT, out=yv, counts=counts)
+            flips.append((sig, elem, part, bit))
+        torch.cuda.synchronize()
+        c = tf.counts_dict(counts)
+        bytes_step = 2 * 2 * total * 16              # forward + inverse, read + write
+        out[str(N)] = {"ft_gbs": round(bytes_step / (ms[2] * 1e-3) / 1e9, 1),
+                       "off_gbs": round(bytes_step / (ms[0] * 1e-3) / 1e9, 1),
+                       "ft_overhead_pct": round(100.0 * (ms[2] / ms[0] - 1.0), 1),
+                       "flips": flips,
+                       "counts": {k: c[k] for k in ("detected", "corrected", "rebuilt", "uncorrectable")}}
+    del x, y
+    torch.cuda.empty_cache()
+    return {"workload": "complex128 forward+inverse, N=2^6..2^20, batch=2^26/N (1 GiB), inputs N(0,1) "
+                        "from a device generator (seed 3000), ABFT correct vs off, 2 seeded flips per N",
+            "per_n": out}
+
+
+def autograd_step(tf, torch, dev, args):
+    """loss = sum(w * |FFT(x)|^2), x complex64 [16384, 4096]: forward and the
+    ABFT-protected adjoint; ms per step and algorithmic GB/s of the two FFTs."""
+    B, N = 16384, 4096
+    g = torch.Generator(device=dev)
+    g.manual_seed(4000)
+    x = (torch.rand(B, N, 2, device=dev, generator=g) * 2 - 1).view(torch.complex64).view(B, N)
+    x.requires_grad_(True)
+    w = torch.rand(B, N, device=dev, generator=g)
+    reps = max(3, args.steps // 2)
+
+    def step():
+        x.grad = None
+        y = tf.fft(x, ft_mode=tf.FT_CORRECT)
+        loss = (w * (y.real * y.real + y.imag * y.imag)).sum()
+        loss.backward()
+        return loss
+
+    for _ in range(max(1, args.warmup)):
+        step()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        step()
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    fft_bytes = 2 * 2 * B * N * 8                  # forward + adjoint, read + write
+    out = {"workload": "loss = sum(w*|FFT(x)|^2), x complex64 [16384, 4096], w U[0,1), ABFT correct",
+           "ms_per_step": round(ms, 4),
+           "fft_gbs_in_step": round(fft_bytes / (ms * 1e-3) / 1e9, 1)}
+    del x, w
+    torch.cuda.empty_cache()
+    return out
 
 
 def ragged_compare(tf, synth, np, torch, dev, args):
