@@ -301,3 +301,27 @@ def test_no_false_alarm_at_scale(dev, N):
         c = tf.counts_dict(counts)
         assert c["detected"] == 0 and c["uncorrectable"] == 0, (N, ft, c)
     del x, y
+
+
+@pytest.mark.parametrize("N", [64, 1 << 16])
+def test_batch_beyond_2_31_elements(dev, N):
+    """A batch of 2^31 + 2^20 complex64 elements (16 GiB per buffer): element
+    offsets past 2^31 must not wrap.  Signals on both sides of the 2^31
+    boundary and the last one are checked against the oracle."""
+    total = (1 << 31) + (1 << 20)
+    batch = total // N
+    g = torch.Generator(device=dev)
+    g.manual_seed(N + 31)
+    x = (torch.rand(batch, N, 2, device=dev, generator=g) * 2 - 1).view(torch.complex64).view(batch, N)
+    y, counts = tf.fft_c2c(x, ft_mode=tf.FT_CORRECT)
+    torch.cuda.synchronize()
+    assert tf.counts_dict(counts)["detected"] == 0
+    edge = (1 << 31) // N
+    pick = [0, edge - 1, edge, edge + 1, batch - 1]
+    xs = x[pick].cpu().numpy()
+    ref = oracle.fft(xs)
+    got = y[pick].cpu().numpy()
+    for i, s in enumerate(pick):
+        assert oracle.rel_l2(got[i], ref[i]) <= 2e-6, (N, s)
+    del x, y
+    torch.cuda.empty_cache()
