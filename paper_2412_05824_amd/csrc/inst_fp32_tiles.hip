@@ -19,6 +19,7 @@ void register_fp32_tiles(std::vector<KernelEntry>& out) {
     add_kind<kColPass>(out);
     add_kind<kRowPass>(out);
     register_fp32_tiles_narrow(out);
+    register_fp32_tiles_e8(out);
 }
 
 }  // namespace tfft
