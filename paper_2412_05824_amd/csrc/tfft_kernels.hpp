@@ -121,7 +121,19 @@ template <int KIND_, int Ns_, int E_, int WC_, int B_, int... Rs> struct Plan {
     static_assert(!TILE || THREADS % kWave == 0, "tile workgroups are whole waves");
     static_assert(!TILE || (kWave % C == 0), "tile width divides a wave");
     static_assert(TILE || (P > kWave ? P % kWave == 0 : kWave % P == 0), "slot must tile waves");
+    static_assert(TILE || Ns % (1 << B_) == 0, "slot regions start on a padding block");
 };
+
+// Conditional negation without a branch: XOR with a wave-uniform sign mask
+// (a branch on the flag would make the loads of the values complete first).
+__device__ __forceinline__ float xor_sign(float v, unsigned long long m) {
+    return __uint_as_float(__float_as_uint(v) ^ (unsigned)(m >> 32));
+}
+__device__ __forceinline__ double xor_sign(double v, unsigned long long m) {
+    return __longlong_as_double(__double_as_longlong(v) ^ (long long)m);
+}
+// the sign bit of a double, whose high word is that of a float
+__device__ __forceinline__ unsigned long long sign_mask(int on) { return on ? 0x8000000000000000ull : 0ull; }
 
 // Bit flip of one component (fault injection, Sec. 5.3 protocol).
 __device__ __forceinline__ float flip_bit(float v, int bit) {
@@ -134,13 +146,28 @@ __device__ __forceinline__ double flip_bit(double v, int bit) {
 // ---------------------------------------------------------------------------
 // LDS index maps.
 // ---------------------------------------------------------------------------
+constexpr bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// step(d) is the index distance from position m to m + d when no block
+// boundary of the map falls between them other than those d itself crosses;
+// SPLIT<L, R> says that this holds for the positions base + j L (j < R) of
+// every Stockham butterfly and for t + P r (t < P, P = L) of every lane, so
+// that one index per butterfly (or lane) plus immediate offsets addresses
+// them all.
 template <int B> struct LdsPad {   // one signal per region, one pad element per 2^B
-    int off;
+    int off;                       // region start, a multiple of 2^B
     __device__ __forceinline__ int operator()(int m) const { return pad_idx<B>(off + m); }
+    static __device__ __forceinline__ constexpr int step(int d) { return d + (d >> B); }
+    // Powers of two L, R: a butterfly's positions lie in one aligned block of
+    // L R positions plus an offset k < L, so base mod 2^B and j L mod 2^B
+    // never add up past 2^B (and likewise t + P r with t < P).
+    template <int L, int R> static constexpr bool SPLIT = pow2(L) && pow2(R);
 };
 template <int C> struct LdsCol {    // tile [m][c]: C sub-signals interleaved
     int c;
     __device__ __forceinline__ int operator()(int m) const { return m * C + c; }
+    static __device__ __forceinline__ constexpr int step(int d) { return d * C; }
+    template <int L, int R> static constexpr bool SPLIT = true;
 };
 
 // ---------------------------------------------------------------------------
@@ -153,8 +180,10 @@ __device__ __forceinline__ void stockham_stage(V (&reg)[E], const V* __restrict_
     constexpr int NB = E / R;
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
-        const int beta = t + i * P;
-        const int k = beta % L;
+        // unsigned: t is never negative, and L is a power of two on most
+        // stages, where % and / are then a mask and a shift
+        const unsigned beta = (unsigned)t + (unsigned)(i * P);
+        const int k = (int)(beta % (unsigned)L);
         V v[R];
 #pragma unroll
         for (int j = 0; j < R; ++j) v[j] = reg[i + j * NB];
@@ -168,9 +197,15 @@ __device__ __forceinline__ void stockham_stage(V (&reg)[E], const V* __restrict_
 #pragma unroll
             for (int j = 0; j < R; ++j) reg[i + j * NB] = v[j];
         } else {
-            const int base = (beta / L) * (L * R) + k;
+            const int base = (int)(beta / (unsigned)L) * (L * R) + k;
+            if constexpr (LI::template SPLIT<L, R>) {
+                V* const at = lds + li(base);
 #pragma unroll
-            for (int j = 0; j < R; ++j) lds[li(base + j * L)] = v[j];
+                for (int j = 0; j < R; ++j) at[LI::step(j * L)] = v[j];
+            } else {
+#pragma unroll
+                for (int j = 0; j < R; ++j) lds[li(base + j * L)] = v[j];
+            }
         }
     }
 }
@@ -185,8 +220,14 @@ __device__ __forceinline__ void slot_fft(V (&reg)[E], const V* __restrict__ tw, 
     stockham_stage<V, E, P, R, L, LAST>(reg, tw, t, lds, li);
     if constexpr (!LAST) {
         lds_sync<BLOCK>();
+        if constexpr (LI::template SPLIT<P, 1>) {
+            const V* const at = lds + li(t);
 #pragma unroll
-        for (int r = 0; r < E; ++r) reg[r] = lds[li(t + P * r)];
+            for (int r = 0; r < E; ++r) reg[r] = at[LI::step(P * r)];
+        } else {
+#pragma unroll
+            for (int r = 0; r < E; ++r) reg[r] = lds[li(t + P * r)];
+        }
         lds_sync<BLOCK>();
         slot_fft<V, E, P, BLOCK, LI, L * R, Rest...>(reg, tw + L * R, t, lds, li);
     }
@@ -226,7 +267,7 @@ template <class V, int E, int P, int M> __device__ __forceinline__ V encode_out(
     for (int r = 0; r < E; ++r) bucket[(P * r) % M] = cadd(bucket[(P * r) % M], v[r]);
     V acc = bucket[0];
 #pragma unroll
-    for (int m = 1; m < M; ++m) acc = cadd(acc, cmul(bucket[m], wM<V, M>(m)));
+    for (int m = 1; m < M; ++m) acc = cmac(acc, bucket[m], wM<V, M>(m));
     return acc;
 }
 
@@ -250,6 +291,9 @@ template <class V, class PL, bool IND> struct Geo {
     int par = 0;         // which half of the reduction scratch the next reduce uses
     int tid;             // lane in the workgroup
     int tile = 0;        // tiles: tile index within the signal group
+    long long sig_u0;    // wave-uniform signal of transaction 0 (slot 0 of the wave)
+    unsigned lane_in;    // this lane's element offset within a transaction's input
+    unsigned lane_out;   // and within its output
     V tw_base{(R)1, (R)0};       // row pass: w_N^{t k1} of this lane
     const V* tw_step = nullptr;  // row pass: LDS table w_N^{P r k1} of the tile's rows
 
@@ -263,14 +307,20 @@ template <class V, class PL, bool IND> struct Geo {
                 lds_off = 0;
                 sig0 = block * a.T;
                 sig_step = 1;
+                sig_u0 = sig0;
+                lane_in = (unsigned)t;
             } else {
                 const int sigma = lane / P;
                 t = lane % P;
                 slot = wave * PL::SPW + sigma;
                 lds_off = slot * Ns;
-                sig0 = (block * PL::WAVES + wave) * a.T * PL::SPW + sigma;
+                const long long wave_u = __builtin_amdgcn_readfirstlane(wave);
+                sig_u0 = (block * PL::WAVES + wave_u) * a.T * PL::SPW;
+                sig0 = sig_u0 + sigma;
                 sig_step = PL::SPW;
+                lane_in = (unsigned)sigma * (unsigned)a.N + (unsigned)t;
             }
+            lane_out = lane_in;
             line = 0;
         } else {
             t = tid / C;
@@ -288,7 +338,40 @@ template <class V, class PL, bool IND> struct Geo {
             line = (int)(tl * C + slot);
             sig0 = grp * a.T;
             sig_step = 1;
+            sig_u0 = sig0;
+            if constexpr (PL::KIND == kColPass) {
+                lane_in = (unsigned)t * (unsigned)a.N2 + (unsigned)slot;
+                lane_out = lane_in;
+            } else {
+                lane_in = (unsigned)slot * (unsigned)a.N2 + (unsigned)t;
+                lane_out = (unsigned)slot + (unsigned)a.N1 * (unsigned)t;
+            }
         }
+    }
+    // Transaction b's elements t + P r sit at a wave-uniform element offset
+    // (in_uni / out_uni) plus r times a uniform stride (in_step / out_step)
+    // plus this lane's 32-bit offset (lane_in / lane_out): loads and stores
+    // then take a scalar base and one vector offset shared by all E elements.
+    // Lane offsets stay below 2^32 bytes: at most a tile's span of a signal.
+    __device__ __forceinline__ long long in_uni(const KArgs<V>& a, int b) const {
+        const long long su = sig_u0 + (long long)b * sig_step;
+        if constexpr (PL::KIND == kSingle) return su * a.N;
+        else if constexpr (PL::KIND == kColPass) return su * a.N + (long long)tile * C;
+        else return su * a.N + (long long)tile * C * a.N2;
+    }
+    __device__ __forceinline__ long long out_uni(const KArgs<V>& a, int b) const {
+        const long long su = sig_u0 + (long long)b * sig_step;
+        if constexpr (PL::KIND == kSingle) return su * a.N;
+        else return su * a.N + (long long)tile * C;
+    }
+    __device__ __forceinline__ long long in_step(const KArgs<V>& a) const {
+        if constexpr (PL::KIND == kColPass) return (long long)P * a.N2;
+        else return P;
+    }
+    __device__ __forceinline__ long long out_step(const KArgs<V>& a) const {
+        if constexpr (PL::KIND == kSingle) return P;
+        else if constexpr (PL::KIND == kColPass) return (long long)P * a.N2;
+        else return (long long)P * a.N1;
     }
     __device__ __forceinline__ long long sig(int b) const { return sig0 + (long long)b * sig_step; }
     // element offsets of input element m / output element k of signal s
@@ -487,6 +570,35 @@ template <int COH, class V> __device__ __forceinline__ void st_y(V* y, long long
     if constexpr ((COH & 1) != 0) st_coh(y + i, v);
     else y[i] = v;
 }
+// Raw buffer access: a wave-uniform descriptor (base address in scalar
+// registers), one 32-bit vector offset shared by all elements of a lane and
+// a 32-bit scalar offset per element.  A flat pointer would need a 64-bit
+// vector address per element, since the element strides exceed the 4 KiB
+// immediate offset range.  Descriptor word 3: 32-bit data format (raw
+// accesses on this architecture must not use the invalid format); the
+// record count is the maximum, so no access is range-clamped.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, -1, 0x00020000);
+}
+template <class V> __device__ __forceinline__ V buf_load(__amdgpu_buffer_rsrc_t rs, unsigned voff, unsigned soff) {
+    V v;
+    if constexpr (sizeof(V) == 8) {
+        const auto q = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)voff, (int)soff, 0);
+        __builtin_memcpy(&v, &q, 8);
+    } else {
+        static_assert(sizeof(V) == 16, "complex float or double");
+        const auto q = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)voff, (int)soff, 0);
+        __builtin_memcpy(&v, &q, 16);
+    }
+    return v;
+}
+template <class V> __device__ __forceinline__ void buf_store(const V& v, __amdgpu_buffer_rsrc_t rs, unsigned voff,
+                                                             unsigned soff) {
+    static_assert(sizeof(V) == 8, "8-byte elements only");
+    unsigned __attribute__((ext_vector_type(2))) q;
+    __builtin_memcpy(&q, &v, 8);
+    __builtin_amdgcn_raw_buffer_store_b64(q, rs, (int)voff, (int)soff, 0);
+}
 
 // One workgroup's share of a transform: block `block` of `nblocks`.
 template <class V, class PL, int FT, bool IND, int COH, int... Rs>
@@ -507,7 +619,18 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
     // The left vector is read where each element is encoded: from LDS where
     // one copy serves several lines or signals of the workgroup (and LDS
     // reads need no address registers), from the cached table otherwise.
+    // Signals addressed directly (not through the ragged tables, and not
+    // shared with other workgroups of the launch) move through raw buffers.
+    constexpr bool kBufIO = !IND && COH == 0;
+    // Stores of 16-byte elements stay flat.  A buffer store of more than 8
+    // bytes reads its data registers after issue, and with a register as
+    // scalar offset the compiler lets the next instruction overwrite them
+    // (seen as complex-double outputs corrupted in groups of four lanes,
+    // with clean checksums: the registers held the right values); two
+    // 8-byte stores instead cost more than the flat store saves.
+    constexpr bool kBufStore = kBufIO && sizeof(V) == 8;
     const V* left = a.left;
+    const auto left_rs = buf_rsrc(a.left);
     if constexpr (Smem<V, PL, FT>::AW_LDS) {
         V* awl = reinterpret_cast<V*>(smem + Smem<V, PL, FT>::AW_OFF);
         for (int i = tid; i < Ns; i += PL::THREADS) awl[i] = a.left[i];
@@ -548,16 +671,39 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
         asm volatile("" : "+v"(t));
         auto li = g.lidx();
         asm volatile("" : "+v"(li));
-        if (valid) {
+        // this lane's share of e^T W: single-pass plans request it before
+        // the inputs, so that the two loads overlap (they meet in the
+        // encode); tiles read it there, which keeps the row pass (where it
+        // also meets the inter-pass twiddle) within fewer registers
+        auto left_at = [&](int r) -> V {
+            if constexpr (Smem<V, PL, FT>::AW_LDS || !kBufIO) return left[t + P * r];
+            else return buf_load<V>(left_rs, (unsigned)t * (unsigned)sizeof(V), (unsigned)(P * r * (int)sizeof(V)));
+        };
+        constexpr bool kAwEarly = FT != 0 && PL::KIND == kSingle;
+        V aw[kAwEarly ? E : 1];
+        if constexpr (kAwEarly) {
 #pragma unroll
-            for (int r = 0; r < E; ++r) reg[r] = ld_x<COH>(x, g.in_off(a, s, t + P * r));
+            for (int r = 0; r < E; ++r) aw[r] = left_at(r);
+        }
+        if (valid) {
+            if constexpr (kBufIO) {
+                const auto rs = buf_rsrc(x + g.in_uni(a, b));
+                const unsigned st = (unsigned)(g.in_step(a) * (long long)sizeof(V));
+                const unsigned lo = g.lane_in * (unsigned)sizeof(V);
+#pragma unroll
+                for (int r = 0; r < E; ++r) reg[r] = buf_load<V>(rs, lo, st * (unsigned)r);
+            } else {
+#pragma unroll
+                for (int r = 0; r < E; ++r) reg[r] = ld_x<COH>(x, g.in_off(a, s, t + P * r));
+            }
         } else {
 #pragma unroll
             for (int r = 0; r < E; ++r) reg[r] = V{0, 0};
         }
-        if (kc.conj_in) {
+        {
+            const unsigned long long cm = sign_mask(kc.conj_in);
 #pragma unroll
-            for (int r = 0; r < E; ++r) reg[r].y = -reg[r].y;
+            for (int r = 0; r < E; ++r) reg[r].y = xor_sign(reg[r].y, cm);
         }
         {
             const R wb = (R)(b + 1);
@@ -571,16 +717,18 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
                     reg[r] = cmul(z, tw);
                 }
                 if constexpr (FT != 0) {
-                    V av = left[t + P * r];
+                    V av;
+                    if constexpr (kAwEarly) av = aw[r];
+                    else av = left_at(r);
                     if constexpr (PL::KIND == kRowPass) av = cmul(av, tw);
-                    p = cadd(p, cmul(av, z));
-                    nu += z.x * z.x + z.y * z.y;
+                    p = cmac(p, av, z);
+                    nu = fmad(z.x, z.x, fmad(z.y, z.y, nu));
                     if constexpr (KEEP_XS) xs[r] = cadd(xs[r], z);
                 }
             }
             if constexpr (FT != 0) {
                 ps = cadd(ps, p);
-                pw = V{pw.x + wb * p.x, pw.y + wb * p.y};
+                pw = V{fmad(wb, p.x, pw.x), fmad(wb, p.y, pw.y)};
             }
         }
 
@@ -601,16 +749,23 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
             const V q = encode_out<V, E, P, M>(reg);
             const R wb = (R)(b + 1);
             qs = cadd(qs, q);
-            qw = V{qw.x + wb * q.x, qw.y + wb * q.y};
+            qw = V{fmad(wb, q.x, qw.x), fmad(wb, q.y, qw.y)};
             if (!cfin(q.x, q.y, a.cap)) nfmask |= 1u << b;
         }
 
         if (valid) {
+            const auto rs = buf_rsrc(y + g.out_uni(a, b));
+            const unsigned st = (unsigned)(g.out_step(a) * (long long)sizeof(V));
+            const unsigned lo = g.lane_out * (unsigned)sizeof(V);
+            // conjugation folded into the scale of the imaginary part
+            // (-a * s and a * -s round alike)
+            const R sy = kc.conj_out ? -kc.scale : kc.scale;
 #pragma unroll
             for (int r = 0; r < E; ++r) {
-                V v = reg[r];
-                if (kc.conj_out) v.y = -v.y;
-                st_y<COH>(y, g.out_off(a, s, t + P * r), V{v.x * kc.scale, v.y * kc.scale});
+                const V v = reg[r];
+                const V o = V{v.x * kc.scale, v.y * sy};
+                if constexpr (kBufStore) buf_store<V>(o, rs, lo, st * (unsigned)r);
+                else st_y<COH>(y, g.out_off(a, s, t + P * r), o);
             }
         }
     }

@@ -34,6 +34,9 @@ def _check(dev, dtype, N, batch, seed):
     y, counts = tf.fft_c2c(x, ft_mode=tf.FT_CORRECT)
     torch.cuda.synchronize()
     assert tf.counts_dict(counts)["detected"] == 0
+    # every element: the checksums must not disturb what the plan stores
+    y0, _ = tf.fft_c2c(x, ft_mode=tf.FT_OFF)
+    assert torch.equal(y, y0), (N, "ABFT and plain outputs differ")
     pick = synth.sample_indices(batch, 6, seed=seed + 1)
     ref = oracle.fft(x_host[pick], threads=8)
     got = y.cpu().numpy()[pick]
