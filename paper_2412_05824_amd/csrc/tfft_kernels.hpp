@@ -679,7 +679,7 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
             if constexpr (Smem<V, PL, FT>::AW_LDS || !kBufIO) return left[t + P * r];
             else return buf_load<V>(left_rs, (unsigned)t * (unsigned)sizeof(V), (unsigned)(P * r * (int)sizeof(V)));
         };
-        constexpr bool kAwEarly = FT != 0 && PL::KIND == kSingle;
+        constexpr bool kAwEarly = FT != 0 && PL::KIND == kSingle && kBufIO;
         V aw[kAwEarly ? E : 1];
         if constexpr (kAwEarly) {
 #pragma unroll
@@ -700,10 +700,15 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
 #pragma unroll
             for (int r = 0; r < E; ++r) reg[r] = V{0, 0};
         }
-        {
+        if constexpr (kBufIO) {
             const unsigned long long cm = sign_mask(kc.conj_in);
 #pragma unroll
             for (int r = 0; r < E; ++r) reg[r].y = xor_sign(reg[r].y, cm);
+        } else if (kc.conj_in) {
+            // the persistent kernel holds every plan in one function: a
+            // branch here costs it fewer registers than the mask
+#pragma unroll
+            for (int r = 0; r < E; ++r) reg[r].y = -reg[r].y;
         }
         {
             const R wb = (R)(b + 1);
@@ -771,6 +776,9 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
     }
 
     if constexpr (FT != 0) {
+        // The group close decides and corrects; its arithmetic never reaches
+        // a fault-free output, so the compiler may fuse freely here.
+#pragma clang fp contract(fast)
         // ---- group close: reduce the checksum differences over the slot ----
         const V lanef = wM<V, M>(t % M);   // e_{t + P r} = w_M^t w_M^{P r}
         const V dd0 = csub(cmul(lanef, qs), ps);   // this lane's share of D0
