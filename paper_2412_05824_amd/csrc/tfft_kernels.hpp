@@ -86,6 +86,8 @@ template <class V> struct KArgs : KCall<typename RealOf<V>::type> {
     R cap;                // magnitude cap: larger outputs mark their signal corrupted
     int x_intact;         // 1: inputs can be re-read on the error path
     int tiles;            // workgroups per signal group (tile geometries)
+    long long nblk;       // workgroups' worth of work of the launch (resident
+                          // kernels loop over it; others launch that many)
     // Indirection (ragged batches, kernels built with IND): element offset of
     // local signal s in x and in y, and its global index for counters and
     // injection.  Without IND, signal s starts at s * N and its global index
@@ -513,8 +515,21 @@ template <class V, class PL, bool IND> struct Geo {
 // path), 3 correct in place (the right-side input sum X e stays in registers
 // through the group, because the outputs overwrite the inputs).
 // ---------------------------------------------------------------------------
+// Resident checking kernels: single-pass plans whose workgroup holds one
+// signal per transaction read all Ns entries of e^T W per signal, as many
+// bytes again as the signal itself.  Their workgroups stay resident instead,
+// stage e^T W in LDS once and loop over signal groups (directly addressed
+// launches only; the ragged kernel has its own persistent loop).  The loop
+// costs the kernel 12-26 more registers, which loses an occupancy step on
+// some plans: residency is kept where it measured faster (complex float:
+// 8 elements per lane, or 8192 points and up; complex double: 4096 points
+// and up).
+template <class V, class PL, int FT, bool IND> constexpr bool kResident =
+    FT != 0 && !IND && PL::KIND == kSingle && PL::SLOTS == 1 &&
+    (sizeof(V) == 8 ? (PL::E == 8 || PL::Ns >= 8192) : PL::Ns >= 4096);
+
 // LDS of one workgroup of a plan: exchange buffer, then reduction scratch
-template <class V, class PL, int FT> struct Smem {
+template <class V, class PL, int FT, bool IND = false> struct Smem {
     using R = typename RealOf<V>::type;
     static constexpr int NRED = 6;
     static constexpr int RED = FT ? 2 * (PL::TILE ? PL::C : 1) * PL::WAVES * NRED : 1;
@@ -525,7 +540,8 @@ template <class V, class PL, int FT> struct Smem {
     // up to 2048 points); row passes keep reading the cached table, which
     // costs them no registers and saves the staging
     static constexpr bool AW_LDS =
-        FT != 0 && (PL::KIND == kColPass || (PL::KIND == kSingle && PL::SLOTS >= 2 && PL::Ns <= 2048));
+        FT != 0 && (PL::KIND == kColPass || (PL::KIND == kSingle && PL::SLOTS >= 2 && PL::Ns <= 2048) ||
+                    kResident<V, PL, FT, IND>);
     static constexpr int AW = AW_LDS ? PL::Ns : 0;
     static constexpr int TWS_OFF = PL::LDS_DATA * (int)sizeof(V);
     static constexpr int AW_OFF = TWS_OFF + TWS * (int)sizeof(V);
@@ -609,7 +625,7 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
     constexpr int E = PL::E, P = PL::P, M = PL::M, Ns = PL::Ns;
     constexpr bool BLOCK = PL::MULTI_WAVE;
     V* lds = reinterpret_cast<V*>(smem);
-    R* red = reinterpret_cast<R*>(smem + Smem<V, PL, FT>::RED_OFF);
+    R* red = reinterpret_cast<R*>(smem + Smem<V, PL, FT, IND>::RED_OFF);
 
     // An opaque copy of the lane index: a persistent caller runs this body in
     // a loop, and nothing derived from the lane may be hoisted out of it.
@@ -631,17 +647,20 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
     constexpr bool kBufStore = kBufIO && sizeof(V) == 8;
     const V* left = a.left;
     const auto left_rs = buf_rsrc(a.left);
-    if constexpr (Smem<V, PL, FT>::AW_LDS) {
-        V* awl = reinterpret_cast<V*>(smem + Smem<V, PL, FT>::AW_OFF);
-        for (int i = tid; i < Ns; i += PL::THREADS) awl[i] = a.left[i];
+    if constexpr (Smem<V, PL, FT, IND>::AW_LDS) {
+        V* awl = reinterpret_cast<V*>(smem + Smem<V, PL, FT, IND>::AW_OFF);
+        if constexpr (!kResident<V, PL, FT, IND>) {   // resident kernels staged it once
+            for (int i = tid; i < Ns; i += PL::THREADS) awl[i] = a.left[i];
+        }
         left = awl;
     }
     if constexpr (PL::KIND == kRowPass)
-        g.twiddle_setup(a, reinterpret_cast<V*>(smem + Smem<V, PL, FT>::TWS_OFF));
+        g.twiddle_setup(a, reinterpret_cast<V*>(smem + Smem<V, PL, FT, IND>::TWS_OFF));
     // these tables are written by some waves and read by all: a workgroup
     // barrier whenever the workgroup has more than one wave (sub-wave slots
     // otherwise only synchronise within their wave)
-    if constexpr (PL::KIND == kRowPass || Smem<V, PL, FT>::AW_LDS) lds_sync<(PL::THREADS > kWave)>();
+    if constexpr (PL::KIND == kRowPass || (Smem<V, PL, FT, IND>::AW_LDS && !kResident<V, PL, FT, IND>))
+        lds_sync<(PL::THREADS > kWave)>();
     const auto li = g.lidx();
     constexpr bool KEEP_XS = FT == 3;   // in place: inputs are gone after the store
     const int t = g.t;
@@ -676,7 +695,7 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
         // encode); tiles read it there, which keeps the row pass (where it
         // also meets the inter-pass twiddle) within fewer registers
         auto left_at = [&](int r) -> V {
-            if constexpr (Smem<V, PL, FT>::AW_LDS || !kBufIO) return left[t + P * r];
+            if constexpr (Smem<V, PL, FT, IND>::AW_LDS || !kBufIO) return left[t + P * r];
             else return buf_load<V>(left_rs, (unsigned)t * (unsigned)sizeof(V), (unsigned)(P * r * (int)sizeof(V)));
         };
         constexpr bool kAwEarly = FT != 0 && PL::KIND == kSingle && kBufIO;
@@ -992,8 +1011,18 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
 template <class V, class PL, int FT, bool IND, int... Rs>
 __global__ __launch_bounds__(PL::THREADS) void k_fft(const V* __restrict__ x, V* __restrict__ y,
                                                      KArgs<V> a) {
-    __shared__ __align__(16) char smem[Smem<V, PL, FT>::BYTES];
-    fft_body<V, PL, FT, IND, 0, Rs...>(x, y, a, a, blockIdx.x, gridDim.x, smem);
+    __shared__ __align__(16) char smem[Smem<V, PL, FT, IND>::BYTES];
+    if constexpr (kResident<V, PL, FT, IND>) {
+        // e^T W into LDS once; every exchange and reduction of the first
+        // group passes a workgroup barrier before it is read
+        V* awl = reinterpret_cast<V*>(smem + Smem<V, PL, FT, IND>::AW_OFF);
+        for (int i = threadIdx.x; i < PL::Ns; i += PL::THREADS) awl[i] = a.left[i];
+        __syncthreads();
+        for (long long g = blockIdx.x; g < a.nblk; g += gridDim.x)
+            fft_body<V, PL, FT, IND, 0, Rs...>(x, y, a, a, g, a.nblk, smem);
+    } else {
+        fft_body<V, PL, FT, IND, 0, Rs...>(x, y, a, a, blockIdx.x, gridDim.x, smem);
+    }
 }
 
 }  // namespace tfft

@@ -20,7 +20,7 @@ template <int FT> constexpr int ragged_plan_smem() {
     int m = 0;
 #define TFFT_SMEM_MAX(id, kind, Ns, E, WC, B, ...)                                                   \
     {                                                                                                \
-        constexpr int b = Smem<float2, TFFT_PLAN_T(id, kind, Ns, E, WC, B, __VA_ARGS__), FT>::BYTES; \
+        constexpr int b = Smem<float2, TFFT_PLAN_T(id, kind, Ns, E, WC, B, __VA_ARGS__), FT, true>::BYTES; \
         m = m > b ? m : b;                                                                           \
     }
     TFFT_RAGGED_PLANS(TFFT_SMEM_MAX)

@@ -28,10 +28,29 @@ struct KernelEntry {
     int variant;            // plans of one (kind, Ns): 0 default, 1.. alternatives
 };
 
+// grid: workgroups' worth of work.  Resident kernels launch at most as many
+// workgroups as the device holds at once and loop over the rest.
 template <class V, class PL, int FT, bool IND, int... Rs>
 hipError_t launch_fft(const void* x, void* y, const void* ka, long long grid, hipStream_t s) {
-    const KArgs<V>& a = *static_cast<const KArgs<V>*>(ka);
-    hipLaunchKernelGGL((k_fft<V, PL, FT, IND, Rs...>), dim3((unsigned)grid), dim3(PL::THREADS), 0, s,
+    KArgs<V> a = *static_cast<const KArgs<V>*>(ka);
+    a.nblk = grid;
+    long long g = grid;
+    if constexpr (kResident<V, PL, FT, IND>) {
+        static const int per_cu = [] {
+            int n = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fft<V, PL, FT, IND, Rs...>, PL::THREADS, 0) !=
+                    hipSuccess || n < 1)
+                n = 1;
+            return n;
+        }();
+        int dev = 0, cus = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        const long long cap = (long long)per_cu * (cus > 0 ? cus : 1);
+        if (g > cap) g = cap;
+    }
+    hipLaunchKernelGGL((k_fft<V, PL, FT, IND, Rs...>), dim3((unsigned)g), dim3(PL::THREADS), 0, s,
                        static_cast<const V*>(x), static_cast<V*>(y), a);
     return hipGetLastError();
 }

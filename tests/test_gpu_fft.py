@@ -161,6 +161,43 @@ def test_injected_flip_detected_located_corrected(dev, N, dtype):
         assert np.array_equal(yh[others], yc[others]), msg
 
 
+@pytest.mark.parametrize("dtype,N,variant", [(torch.complex64, 8192, 0), (torch.complex64, 2048, 1),
+                                             (torch.complex128, 4096, 0)], ids=["fp32-8192", "fp32-2048e8", "fp64-4096"])
+def test_resident_loop_late_group(dev, dtype, N, variant):
+    """Single-pass checking kernels with one signal per workgroup stay
+    resident and loop over the groups; a batch several times the resident
+    workgroups, with a flip in a group of a late iteration, must be detected,
+    located and corrected like any other, and every other signal must match
+    the plain kernel bit for bit."""
+    batch = 2600
+    sig, elem, part = batch - 7, N // 3, 0
+    bit = 30 if dtype == torch.complex64 else 62
+    tf.set_route(N, dtype, tf.route_code(1, variant, 0))
+    try:
+        x = synth.signals(batch, N, seed=4100 + N, dtype=NPDT[dtype])
+        xd = torch.from_numpy(x).to(dev)
+        y0, _ = tf.fft_c2c(xd, ft_mode=tf.FT_OFF)
+        y2, c2 = tf.fft_c2c(xd, ft_mode=tf.FT_CORRECT)
+        assert tf.counts_dict(c2)["detected"] == 0
+        assert torch.equal(y2, y0)
+        tf.inject_arm(sig, elem, part, bit, dtype=dtype)
+        y, counts = tf.fft_c2c(xd, ft_mode=tf.FT_CORRECT)
+        c = tf.counts_dict(counts)
+        assert c["detected"] == 1 and c["uncorrectable"] == 0, c
+        assert c["corrected"] + c["rebuilt"] == 1 and c["last_signal"] == sig, c
+        pick = [0, 1, batch // 2, sig, batch - 1]
+        ref = oracle.fft(x[pick], threads=8)
+        got = y.cpu().numpy()
+        for i, s in enumerate(pick):
+            assert oracle.rel_l2(got[s], ref[i]) <= 2 * TOL[dtype], (N, s)
+        others = torch.ones(batch, dtype=torch.bool, device=dev)
+        others[sig] = False
+        assert torch.equal(y[others], y0[others])
+    finally:
+        tf.set_route(N, dtype, 0)
+        _restore_tuning()
+
+
 @pytest.mark.parametrize("dtype", DTYPES, ids=["fp32", "fp64"])
 def test_exponent_flips_always_detected(dev, dtype):
     # the top exponent bits change a value by orders of magnitude (or make it
