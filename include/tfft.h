@@ -219,6 +219,15 @@ int tfft_calibration(int on);
 int tfft_profile(int on);
 int tfft_profile_read(char* buf, long long buflen);
 
+/* Restrict the per-launch timing above to the launches of one kernel:
+ * precision (TFFT_FP32 / TFFT_FP64), kind (0 single, 1 colpass, 2 rowpass,
+ * 3 ragged persistent), sub-length Ns and ABFT mode ft; -1 in a field
+ * matches any value (all -1, the default, times every launch).  Events cost
+ * the stream a few microseconds per launch, so a benchmark that times one
+ * kernel live brackets only that kernel's launches.  Returns TFFT_EINVAL
+ * for a value out of range. */
+int tfft_profile_only(int precision, int kind, int Ns, int ft);
+
 const char* tfft_strerror(int status);
 int tfft_last_hip_error(void);
 

@@ -99,7 +99,14 @@ struct LaunchRec {
     double bytes;
 };
 bool g_prof = false;
+int g_prof_sel[4] = {-1, -1, -1, -1};   // precision, kind, Ns, ft of the timed kernel; -1: any
 std::vector<LaunchRec> g_prof_log;
+bool prof_selected(const KernelEntry& e) {
+    const int v[4] = {e.precision, e.kind, e.Ns, e.ft};
+    for (int i = 0; i < 4; ++i)
+        if (g_prof_sel[i] >= 0 && g_prof_sel[i] != v[i]) return false;
+    return true;
+}
 std::string g_prof_text;   // aggregated, not yet read
 
 void ensure_registry() {
@@ -374,7 +381,7 @@ template <class V> int run(const KernelEntry& e, const void* x, void* y, const K
     if (grid <= 0) return TFFT_OK;
     if (grid > 0x7fffffffLL) return TFFT_EUNSUPPORTED;
     LaunchRec rec{};
-    const bool prof = g_prof && !capturing(stream);
+    const bool prof = g_prof && !capturing(stream) && prof_selected(e);
     if (prof) {
         rec.e = &e;
         rec.bytes = 2.0 * (double)a.batch * (double)a.N * (double)sizeof(V);
@@ -847,13 +854,13 @@ int ragged_exec(tfft_ragged_plan_s* P, const void* x, void* y, int dir, int unit
         long long grid = (long long)k.blocks_per_cu * P->cus;
         if (grid > P->n_items) grid = P->n_items;
         LaunchRec rec{};
-        const bool prof = g_prof && !capturing(stream);
+        KernelEntry& pe = g_ragged_prof_entry[ft];
+        pe.precision = TFFT_FP32;
+        pe.kind = 3;
+        pe.Ns = 0;
+        pe.ft = ft;
+        const bool prof = g_prof && !capturing(stream) && prof_selected(pe);
         if (prof) {
-            KernelEntry& pe = g_ragged_prof_entry[ft];
-            pe.precision = TFFT_FP32;
-            pe.kind = 3;
-            pe.Ns = 0;
-            pe.ft = ft;
             rec.e = &pe;
             rec.bytes = 2.0 * (double)P->total * (double)sizeof(float2);
             if (hipEventCreate(&rec.start) != hipSuccess || hipEventCreate(&rec.stop) != hipSuccess)
@@ -1206,6 +1213,17 @@ int tfft_set_chunk(long long N, int precision, long long chunk_bytes) {
 int tfft_profile(int on) {
     std::lock_guard<std::mutex> lk(g_mu);
     g_prof = on != 0;
+    return TFFT_OK;
+}
+
+int tfft_profile_only(int precision, int kind, int Ns, int ft) {
+    if (precision < -1 || precision > TFFT_FP64 || kind < -1 || kind > 3 || Ns < -1 || ft < -1 || ft > 3)
+        return TFFT_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_prof_sel[0] = precision;
+    g_prof_sel[1] = kind;
+    g_prof_sel[2] = Ns;
+    g_prof_sel[3] = ft;
     return TFFT_OK;
 }
 
