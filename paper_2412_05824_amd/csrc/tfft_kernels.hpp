@@ -28,16 +28,25 @@
 //     k1 + N1*k2 (the reorganised last-stage store of Sec. 5.1.2, coalesced
 //     over the C rows).
 //
+// Addressing: a transaction's elements sit at a wave-uniform base plus r
+// times a uniform stride plus a 32-bit lane offset, so directly addressed
+// launches load (and store 8-byte elements) through raw buffer descriptors:
+// one vector offset per lane, the strides in scalar registers.
+//
 // Two-side ABFT (Sec. 4.1-4.3), per slot and group of T transactions, e_k =
 // w_M^k (M = 3, or 5 when 3 | Ns) and a = e^T W of the sub-length:
-//   per transaction b: p_b = a^T x_b (input; each lane keeps its E entries of
-//   a in registers, since it encodes the same positions every time), q_b = e^T y_b
-//   (output, M bucket sums), x_s += x_b (right-side checksum X e, kept in
-//   registers: the inputs "compressed" into registers);
+//   per transaction b: p_b = a^T x_b (input; each lane reads its E entries
+//   of a with the inputs, from LDS where the workgroup stages a, else from
+//   the cached table), q_b = e^T y_b (output, M bucket sums);
 //   group close: D0 = sum q_b - sum p_b detects, D1 = sum (b+1)(q_b - p_b)
 //   locates (location encoding), c = W x_s - Y e corrects the located
-//   signal (delayed batched correction).  Y e is summed from the group's
-//   stored outputs on the error path only.
+//   signal (delayed batched correction).  The right-side sums x_s = X e and
+//   Y e are formed on the error path only, from the group's intact inputs
+//   and stored outputs (in place, where the inputs are overwritten, x_s is
+//   accumulated in registers during the group instead).
+// Single-pass checking kernels with one signal per workgroup can run
+// resident: as many workgroups as the device holds, e^T W staged in LDS
+// once, a loop over the signal groups (kResident).
 // In the row pass the left vector becomes a_n * w_N^{n k1} applied to the raw
 // loaded values and x_s sums the raw values, so the inter-pass twiddle
 // multiply is covered as well; all transactions of a row-pass group share
