@@ -259,7 +259,7 @@ def main():
     if not args.no_cpu:
         import oracle
         threads = min(16, os.cpu_count() or 1)
-        per_n_elems = 1 << 24
+        per_n_elems = 1 << 26
         t_total = 0.0
         bytes_total = 0
         done = []
