@@ -21,7 +21,7 @@ tf = pytest.importorskip("paper_2412_05824_amd")
 TOL = {torch.complex64: 2e-6, torch.complex128: 1e-13}
 NPDT = {torch.complex64: np.complex64, torch.complex128: np.complex128}
 PREC = {torch.complex64: "fp32", torch.complex128: "fp64"}
-SIZES = [64, 128, 256, 512, 1024, 2048, 4096, 8192]
+SIZES = [64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384]
 # lengths served by a column pass and a row pass (N = N1 * N2)
 TWO_PASS = {torch.complex64: [1 << 14, 1 << 15, 1 << 17, 1 << 20],
             torch.complex128: [1 << 13, 1 << 14, 1 << 16]}
