@@ -81,7 +81,10 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        # signals are independent: several GPUs would each run this
+        # benchmark on their share of the batch, with no exchange
+        print(json.dumps({"error": "the benchmark runs on one GPU: --gpus must be 1 "
+                                   "(signals shard across GPUs with no communication)",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 
