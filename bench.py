@@ -43,7 +43,7 @@ TOTAL_ELEMS = 1 << 27          # 1 GiB of complex64 per buffer
 
 def kernel_fingerprint() -> str:
     """Hash of the kernel sources and the tuning table (which sets the bytes
-    per launch), to match stored counter readings to this build."""
+    per launch), to match stored counter readings to the library being timed."""
     import hashlib
     m = hashlib.sha256()
     pkg = os.path.join(ROOT, "paper_2412_05824_amd")
@@ -251,7 +251,7 @@ def main():
     traffic = None
     tpath = os.path.join(ROOT, "profiles", "traffic.json")
     if os.path.exists(tpath):
-        # counters taken on other kernel sources do not describe this build
+        # counters taken on other kernel sources do not describe this library
         tj = json.load(open(tpath))
         if tj.get("kernel_source_sha256_16") == kernel_fingerprint():
             rec = tj.get("kernels", {}).get(dom_name)

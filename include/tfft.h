@@ -39,7 +39,7 @@ extern "C" {
 typedef enum {
     TFFT_OK = 0,
     TFFT_EINVAL = -1,       /* null pointer, N < 1, batch < 0, unknown enum value */
-    TFFT_EUNSUPPORTED = -2, /* size or mode without a kernel in this build */
+    TFFT_EUNSUPPORTED = -2, /* size or mode without a compiled kernel */
     TFFT_EALIGN = -3,       /* x or y not aligned to the element size */
     TFFT_EHIP = -4,         /* HIP runtime error, see tfft_last_hip_error() */
     TFFT_ENOMEM = -5,       /* table allocation failed */
@@ -70,7 +70,7 @@ typedef struct {
  *             TFFT_FT_CORRECT (two-side check, location and correction).
  *   scale     multiplies every output; 0 selects 1 (forward) or 1/N (inverse).
  *   counts    device tfft_ft_counts, required unless ft_mode is TFFT_FT_OFF.
- * N must be 2^k or 3*2^k within the sizes this build supports
+ * N must be 2^k or 3*2^k within the sizes the library supports
  * (tfft_supported()).  batch = 0 is a no-op. */
 int tfft_c2c(const void* x, void* y, long long N, long long batch, int dir, int precision,
              int ft_mode, double scale, tfft_ft_counts* counts, void* hip_stream);
@@ -146,7 +146,7 @@ int tfft_ragged_set_schedule(long long window_elems, long long item_elems, int w
 int tfft_c2c_ragged(tfft_ragged_plan plan, const void* x, void* y, int dir, int unit_scale,
                     int mode, int ft_mode, tfft_ft_counts* counts, void* hip_stream);
 
-/* 1 if N (and precision) has a kernel in this build, else 0. */
+/* 1 if N (and precision) has a compiled kernel, else 0. */
 int tfft_supported(long long N, int precision);
 
 /* Test hook (Sec. 5.3 injection protocol): arm a single-bit flip for the NEXT

@@ -7,7 +7,7 @@ weights e_3 = (1, 2, ...); delayed batched correction) and Sec. 4.3
 (multi-transaction groups, location weight = the signal's index in the group).
 All arithmetic here is fp64 numpy plus the oracle FFT of this package.
 
-Readings taken where the paper is silent (each one is listed in the design doc):
+Readings taken where the paper is silent:
   * encoding vector e_k = w_M^k, w_M = exp(-2 pi i / M), M = 3 (Wang's vector),
     switched to M = 5 when 3 | N (then w_3 makes e^T W vanish almost everywhere);
   * left vector a = e^T W = W e (W is symmetric), closed form
