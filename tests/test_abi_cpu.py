@@ -195,3 +195,29 @@ def test_load_tuning_table(tmp_path):
         lib.tfft_set_route(1 << 20, _lib.FP32, 0)
         if os.path.exists(_lib.TUNING_PATH):
             assert lib.tfft_load_tuning(_lib.TUNING_PATH.encode()) >= 0
+
+
+def test_shipped_tuning_table_is_complete_and_consistent():
+    """The package's tuning table covers every length of the benchmark sweeps
+    in both the correcting and the plain mode, gives both modes the same route
+    (so switching ABFT on or off never changes an output bit), keeps T within
+    the autotuner's accuracy bound, and is accepted by the library."""
+    import math
+    from paper_2412_05824_amd import autotune
+    doc = json.load(open(_lib.TUNING_PATH))
+    entries = {(e["precision"], e["N"], e.get("ft_mode", 2)): e for e in doc["entries"]}
+    for prec, hi in (("fp32", 22), ("fp64", 20)):
+        for lg in range(6, hi + 1):
+            N = 1 << lg
+            on, off = entries[(prec, N, 2)], entries[(prec, N, 0)]
+            route = lambda e: (e.get("split_n1", 1), e.get("variant_a", 0), e.get("variant_b", 0))
+            assert route(on) == route(off), (prec, N)
+            n1 = on.get("split_n1", 1)
+            longest = N if n1 <= 1 else max(n1, N // n1)
+            assert 1 <= on["T"] <= autotune.max_T(prec, longest, on["kappa"]), (prec, N, on["T"])
+            assert math.isfinite(on["kappa"]) and on["kappa"] > 0
+    lib = _lib.load()
+    try:
+        assert lib.tfft_load_tuning(_lib.TUNING_PATH.encode()) == len(doc["entries"])
+    finally:
+        lib.tfft_load_tuning(_lib.TUNING_PATH.encode())
