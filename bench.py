@@ -58,6 +58,17 @@ def kernel_fingerprint() -> str:
     return m.hexdigest()[:16]
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -92,7 +103,7 @@ def main():
     import torch
 
     import paper_2412_05824_amd as tf
-    from paper_2412_05824_amd import synth
+    import synth
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -201,37 +212,13 @@ def main():
         off_ms = {}
         time_sweep(tf.FT_OFF, max(3, args.steps // 2), 1, per_kernel=off_ms)
         rng = np.random.default_rng(2024)
-        inj_ms = {}
         for N in sizes:
-            counts.zero_()
-            batch = TOTAL_ELEMS // N
-            n_launch = 100
-            hit = int(rng.integers(0, n_launch))
-            flips = []
-            a = torch.cuda.Event(enable_timing=True)
-            b = torch.cuda.Event(enable_timing=True)
-            a.record(stream)
-            for i in range(n_launch):
-                if i == hit:
-                    sig = int(rng.integers(0, batch))
-                    elem = int(rng.integers(0, N))
-                    part = int(rng.integers(0, 2))
-                    bit = int(rng.integers(0, 31))
-                    tf.inject_arm(sig, elem, part, bit, dtype=torch.complex64)
-                    flips.append((sig, elem, part, bit))
-                launch(N, tf.FT_CORRECT)
-            b.record(stream)
-            torch.cuda.synchronize()
-            inj_ms[N] = a.elapsed_time(b) / n_launch
-            cd = tf.counts_dict(counts)
             sweep[N].update({
                 "off_ms": off_ms[N],
                 "off_gbs": 2 * TOTAL_ELEMS * 8 / (off_ms[N] * 1e-3) / 1e9,
                 "ft_overhead_pct": 100.0 * (per_kernel_ms[N] / off_ms[N] - 1.0),
-                "inj_ms": inj_ms[N],
-                "inj_overhead_pct": 100.0 * (inj_ms[N] / per_kernel_ms[N] - 1.0),
-                "inj_flips": flips,
-                "inj_counts": {k: cd[k] for k in ("detected", "corrected", "rebuilt", "uncorrectable")},
+                **injection_run(tf, torch, np, stream, counts, launch, y, N, TOTAL_ELEMS // N,
+                                per_kernel_ms[N], rng, torch.complex64),
             })
 
     # ---- ragged batch: one persistent launch vs one launch per length ----
@@ -261,7 +248,10 @@ def main():
     cpu = None
     if not args.no_cpu:
         import oracle
-        threads = min(16, os.cpu_count() or 1)
+        # the host cores this process may run on, at most the 16-core share a
+        # one-GPU job has on the benchmark hosts
+        avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+        threads = max(1, min(16, avail))
         per_n_elems = 1 << 26
         t_total = 0.0
         bytes_total = 0
@@ -279,7 +269,7 @@ def main():
             if t_total > budget:
                 break
         cpu = {"value": bytes_total / t_total / 1e9, "unit": "GB/s", "cores": threads,
-               "kind": "oracle",
+               "kind": "oracle", "nproc": os.cpu_count(), "affinity": avail, "cpu_model": cpu_model(),
                "sample": f"{per_n_elems} elements per N for N in {done[0]}..{done[-1]} "
                          f"({len(done)} sizes, {t_total:.1f}s, fp64 recursive radix-2 FFT)"}
 
@@ -320,6 +310,69 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def flip_value(v: complex, part: int, bit: int, real_dtype) -> complex:
+    """v with one bit of its real (part 0) or imaginary part flipped, as
+    stored in binary32 / binary64 (the injected fault, seen from the host)."""
+    import numpy as np
+    a = np.array([v.real, v.imag], dtype=real_dtype)
+    u = a.view(np.uint32 if real_dtype == np.float32 else np.uint64)
+    u[part] ^= (1 << bit)
+    return complex(float(a[0]), float(a[1]))
+
+
+def injection_run(tf, torch, np, stream, counts, launch, y, N, batch, ft_ms, rng, dtype,
+                  n_launch=100, direction=None):
+    """n_launch ABFT launches timed like the ABFT sweep (HIP events around
+    each launch), one of them (seeded) with a single-bit flip in a random
+    output element.  Reports the mean launch time and its overhead over the
+    sweep's, the counts, and the flip: its size relative to the hit signal's
+    norm, whether it is significant (an uncorrected flip of that size would
+    take the signal past the acceptance tolerance) and the hit signal's
+    relative distance, after correction, to its fault-free output."""
+    fp32 = dtype == torch.complex64
+    tol = 2e-6 if fp32 else 1e-13
+    nbits = 31 if fp32 else 63
+    counts.zero_()
+    hit = int(rng.integers(0, n_launch))
+    sig, elem = int(rng.integers(0, batch)), int(rng.integers(0, N))
+    part, bit = int(rng.integers(0, 2)), int(rng.integers(0, nbits))
+    yv = y.view(-1, N)
+    kept = torch.empty(N, dtype=dtype, device=y.device)
+    evs = []
+    for i in range(n_launch):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        if i == hit:
+            tf.inject_arm(sig, elem, part, bit, dtype=dtype)
+        a.record(stream)
+        launch(N, tf.FT_CORRECT)
+        b.record(stream)
+        evs.append((a, b))
+        if i == hit:
+            kept.copy_(yv[sig])   # the corrected signal, before later launches overwrite it
+    torch.cuda.synchronize()
+    inj_ms = sum(a.elapsed_time(b) for a, b in evs) / n_launch
+    cd = tf.counts_dict(counts)
+    launch(N, tf.FT_OFF)                      # fault-free output of the same input
+    torch.cuda.synchronize()
+    clean = yv[sig].to(torch.complex128)
+    norm = torch.linalg.vector_norm(clean).item()
+    yc = complex(clean[elem].item())
+    delta = abs(flip_value(yc, part, bit, np.float32 if fp32 else np.float64) - yc)
+    delta_rel = delta / norm if norm > 0 else float("inf")
+    after = torch.linalg.vector_norm(kept.to(torch.complex128) - clean).item() / norm
+    return {
+        "inj_ms": inj_ms,
+        "inj_overhead_pct": 100.0 * (inj_ms / ft_ms - 1.0),
+        "inj_flip": {"launch": hit, "signal": sig, "element": elem, "part": part, "bit": bit,
+                     "delta_rel": delta_rel if math.isfinite(delta_rel) else "inf",
+                     "significant": not (delta_rel <= tol),
+                     "hit_signal_rel_after": after,
+                     "hit_signal_within_tol": after <= tol},
+        "inj_counts": {k: cd[k] for k in ("detected", "corrected", "rebuilt", "uncorrectable")},
+    }
+
+
 def fp64_sweep(tf, torch, dev, args):
     """complex128 forward+inverse sweep with ABFT off / correct and seeded
     flips; inputs standard normal, generated on the device from a seed."""
@@ -354,7 +407,10 @@ def fp64_sweep(tf, torch, dev, args):
             b.record()
             torch.cuda.synchronize()
             ms[ft] = a.elapsed_time(b) / reps
-        # seeded flips: one in a forward and one in an inverse launch
+        # the fault-free runs above must not have counted anything
+        clean = tf.counts_dict(counts)
+        # seeded flips: one in a forward and one in an inverse launch; the hit
+        # signal, after correction, against its fault-free output
         counts.zero_()
         flips = []
         for d in (tf.FORWARD, tf.INVERSE):
@@ -362,13 +418,24 @@ def fp64_sweep(tf, torch, dev, args):
             part, bit = int(rng.integers(0, 2)), int(rng.integers(0, 63))
             tf.inject_arm(sig, elem, part, bit, dtype=torch.complex128)
             tf.fft_c2c(xv, dir=d, ft_mode=tf.FT_CORRECT, out=yv, counts=counts)
-            flips.append((sig, elem, part, bit))
+            kept = yv[sig].clone()
+            tf.fft_c2c(xv, dir=d, ft_mode=tf.FT_OFF, out=yv)
+            ref = yv[sig]
+            norm = torch.linalg.vector_norm(ref).item()
+            yc = complex(ref[elem].item())
+            delta_rel = abs(flip_value(yc, part, bit, np.float64) - yc) / norm
+            after = torch.linalg.vector_norm(kept - ref).item() / norm
+            flips.append({"dir": d, "signal": sig, "element": elem, "part": part, "bit": bit,
+                          "delta_rel": delta_rel if math.isfinite(delta_rel) else "inf",
+                          "significant": not (delta_rel <= 1e-13),
+                          "hit_signal_rel_after": after, "hit_signal_within_tol": after <= 1e-13})
         torch.cuda.synchronize()
         c = tf.counts_dict(counts)
         bytes_step = 2 * 2 * total * 16              # forward + inverse, read + write
         out[str(N)] = {"ft_gbs": round(bytes_step / (ms[2] * 1e-3) / 1e9, 1),
                        "off_gbs": round(bytes_step / (ms[0] * 1e-3) / 1e9, 1),
                        "ft_overhead_pct": round(100.0 * (ms[2] / ms[0] - 1.0), 1),
+                       "clean_detected": clean["detected"],
                        "flips": flips,
                        "counts": {k: c[k] for k in ("detected", "corrected", "rebuilt", "uncorrectable")}}
     del x, y
@@ -421,12 +488,13 @@ def ragged_compare(tf, synth, np, torch, dev, args):
     line, with a second, small-signal batch (lengths 64..3072) as context."""
     out = ragged_one(tf, synth, np, torch, dev, args,
                      [int(n) for n in synth.ragged_sizes(args.ragged_signals, seed=5)],
-                     "lengths uniform over 2^k and 3*2^k, 6<=k<=16 (seed 5)")
+                     f"{args.ragged_signals} fp32 signals, lengths uniform over 2^k and 3*2^k, "
+                     f"6<=k<=16 (seed 5)")
     small_menu = [n for n in synth.RAGGED_SIZES if n <= 3072]
     out["small_signals"] = ragged_one(
         tf, synth, np, torch, dev, args,
         [int(n) for n in synth.ragged_sizes(2000, seed=6, menu=small_menu)],
-        "lengths uniform over 2^k and 3*2^k, 6<=k<=10 (seed 6)")
+        "2000 fp32 signals, lengths uniform over 2^k and 3*2^k, 6<=k<=10 (seed 6)")
     return out
 
 
@@ -477,8 +545,7 @@ def ragged_one(tf, synth, np, torch, dev, args, sizes, desc):
     bytes_alg = 2.0 * total * 8
     best_per_size = min(res["per_size_eager_ms"], res["per_size_graph_ms"])
     out = {
-        "workload": f"{len(sizes)} fp32 signals, lengths uniform over 2^k and 3*2^k, 6<=k<=16 "
-                    f"(seed 5), {total} elements, forward, ABFT correct",
+        "workload": f"{desc}, {total} elements, forward, ABFT correct",
         "elements": total,
         "work_items": info["items"],
         "persistent_grid": info["grid"],
@@ -489,7 +556,7 @@ def ragged_one(tf, synth, np, torch, dev, args, sizes, desc):
         "speedup_vs_per_size_eager": round(res["per_size_eager_ms"] / res["persistent_graph_ms"], 3),
         "speedup_vs_best_per_size": round(best_per_size / res["persistent_graph_ms"], 3),
         "detected": c["detected"],
-        "queue_err": info["queue_err"],
+        "err_launches": info["err_launches"],
     }
     plan.close()
     del x, y

@@ -50,15 +50,20 @@ enum { TFFT_FORWARD = -1, TFFT_INVERSE = +1 };       /* sign of the exponent */
 enum { TFFT_FP32 = 0, TFFT_FP64 = 1 };
 enum { TFFT_FT_OFF = 0, TFFT_FT_DETECT = 1, TFFT_FT_CORRECT = 2 };
 
-/* Device-resident counters, accumulated by every ABFT call (the caller zeroes
- * them).  detected: groups whose checksums disagreed (or held a non-finite /
- * oversized output); corrected: fixed by adding W(Xe)-Ye; rebuilt: fixed by
- * recomputing the located signal as W(Xe) minus the group's other outputs;
- * uncorrectable: detected but not located or not verified (for example two
- * faults in one group); last_signal: global index of the most recently
- * located signal. */
+/* Device-resident counters, accumulated by every call that is given them
+ * (the caller zeroes them).  detected: faulty signals found (a checksum
+ * disagreement, or a non-finite / oversized output); corrected: fixed by
+ * adding W(Xe)-Ye; rebuilt: fixed by recomputing the located signal as W(Xe)
+ * minus the group's other outputs; uncorrectable: detected but not located or
+ * not verified (for example two faults in one group under group-level
+ * detection); last_signal: global index of the most recently located signal;
+ * calib: see tfft_calibration; sched_errors: persistent ragged launches in
+ * which a wait gave up (their outputs are not to be trusted); fallback:
+ * detections whose location came from re-encoding every signal of the group
+ * because the location code D1/D0 was not an index. */
 typedef struct {
-    unsigned long long detected, corrected, rebuilt, uncorrectable, last_signal, reserved[3];
+    unsigned long long detected, corrected, rebuilt, uncorrectable, last_signal;
+    unsigned long long calib, sched_errors, fallback;
 } tfft_ft_counts;
 
 /* Batched 1-D C2C transform of `batch` signals of length N.
@@ -75,9 +80,19 @@ typedef struct {
 int tfft_c2c(const void* x, void* y, long long N, long long batch, int dir, int precision,
              int ft_mode, double scale, tfft_ft_counts* counts, void* hip_stream);
 
-/* Build (and cache) tables and plans for length N.  Host call, allocates.
- * Call before capturing tfft_c2c into a graph. */
-int tfft_prepare(long long N, int precision, int ft_mode);
+/* Build (and cache) the tables of length N for ABFT mode ft_mode and, when
+ * batch > 0 and N runs as two passes, reserve the two-pass workspace that
+ * tfft_c2c of up to `batch` signals on hip_stream will use.  Host call,
+ * allocates, must not be made while hip_stream is being captured.  Call it
+ * before capturing tfft_c2c into a graph: a captured call that finds its
+ * tables or its workspace missing returns TFFT_ECAPTURE.
+ * Workspace: one per (device, stream), owned by the library, grown when a
+ * larger call needs it and never freed while the library is loaded, so a
+ * graph captured earlier keeps a valid buffer; calls on one stream share it
+ * (stream order serialises them), calls on different streams do not.
+ * TFFT_EINVAL for N < 1, batch < 0 or an unknown enum; TFFT_EUNSUPPORTED for
+ * a length without a compiled route; TFFT_ENOMEM when allocation fails. */
+int tfft_prepare(long long N, long long batch, int precision, int ft_mode, void* hip_stream);
 
 /* ---- Ragged batches: signals of mixed lengths in one call ----
  * The transform of each signal is that of tfft_c2c (Sec. 2.2), with the same
@@ -114,9 +129,10 @@ int tfft_ragged_plan_destroy(tfft_ragged_plan plan);
 /* Up to n values: [0] signals, [1] total elements, [2] work items,
  * [3] classes (lengths x passes), [4] workspace elements, [5] persistent
  * grid, [6] workspace batches and [7] window (elements per half; 0 when the
- * workspace is flat); [8] the queue's error bits and [9] its next-item
- * counter (read from the device with a synchronising copy when n > 8; both
- * 0 between launches). */
+ * workspace is flat); [8] persistent launches of this plan in which a wait
+ * gave up (sticky; each such launch also adds 1 to counts->sched_errors) and
+ * [9] the queue's next-item counter (0 between launches); [8] and [9] are
+ * read from the device with a synchronising copy when n > 8. */
 int tfft_ragged_plan_info(tfft_ragged_plan plan, long long* info, int n);
 
 /* Schedule of plans created from now on.  window_elems > 0: the persistent
@@ -130,6 +146,14 @@ int tfft_ragged_plan_info(tfft_ragged_plan plan, long long* info, int n);
  * spill; measured faster); 0 lets the compiler size their registers (two
  * workgroups per CU).  Per-size launches are unaffected. */
 int tfft_ragged_set_schedule(long long window_elems, long long item_elems, int waves);
+
+/* Test hook for the persistent launch's bounded waits: every row-pass (and
+ * windowed column-pass) wait gives up after max_polls polls (0 restores the
+ * default of 2^20) and needs `extra` more finished items than exist, so with
+ * extra > 0 each wait reaches its bound: the launch still drains, reports the
+ * failure (counts->sched_errors, plan info [8]) and resets its counters so
+ * the next launch is correct.  Applies to launches made from now on. */
+int tfft_ragged_test_wait(unsigned max_polls, unsigned extra);
 
 /* Execute a plan.
  *   x, y        device buffers of total elements (complex64); x == y only
@@ -201,7 +225,7 @@ int tfft_get_route(long long N, int precision, int ft_mode, long long* code);
 int tfft_load_tuning(const char* path);
 
 /* Calibration of the detection threshold (Sec. 5.3 ROC protocol): while on,
- * every ABFT call also records in counts->reserved[0] the largest ratio
+ * every ABFT call also records in counts->calib the largest ratio
  * |D0| / tau over its fault-free groups, as the bits of an IEEE double
  * (atomic max; the caller zeroes it).  D0 is the left-side checksum
  * difference and tau the threshold.  Off by default; costs one atomic per

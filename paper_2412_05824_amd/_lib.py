@@ -36,12 +36,13 @@ _D = ctypes.c_double
 SIGNATURES = {
     "tfft_c2c": ([_VP, _VP, _LL, _LL, _I, _I, _I, _D, _VP, _VP], _I),
     "tfft_c2c_ragged": ([_VP, _VP, _VP, _I, _I, _I, _I, _VP, _VP], _I),
-    "tfft_prepare": ([_LL, _I, _I], _I),
+    "tfft_prepare": ([_LL, _LL, _I, _I, _VP], _I),
     "tfft_ragged_supported": ([_LL, _I], _I),
     "tfft_ragged_plan_create": ([ctypes.POINTER(_VP), ctypes.POINTER(_LL), _LL, _I], _I),
     "tfft_ragged_plan_destroy": ([_VP], _I),
     "tfft_ragged_plan_info": ([_VP, ctypes.POINTER(_LL), _I], _I),
     "tfft_ragged_set_schedule": ([_LL, _LL, _I], _I),
+    "tfft_ragged_test_wait": ([ctypes.c_uint, ctypes.c_uint], _I),
     "tfft_supported": ([_LL, _I], _I),
     "tfft_inject_arm": ([_LL, _LL, _I, _I, _I], _I),
     "tfft_inject_disarm": ([], _I),

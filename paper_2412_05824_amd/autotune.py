@@ -64,7 +64,6 @@ def tune(precisions, logs, modes=(2, 0), reps=5, warmup=2, total_bytes=1 << 30, 
     import torch
 
     import paper_2412_05824_amd as tf
-    from paper_2412_05824_amd import synth
 
     dev = torch.device("cuda:0")
     entries = []
@@ -73,7 +72,11 @@ def tune(precisions, logs, modes=(2, 0), reps=5, warmup=2, total_bytes=1 << 30, 
         npdt = np.complex64 if prec == "fp32" else np.complex128
         esize = 8 if prec == "fp32" else 16
         total = total_bytes // esize
-        x = torch.from_numpy(synth.signals(1, total, seed=4000, dtype=npdt).reshape(-1)).to(dev)
+        # re, im i.i.d. U[-1, 1) from a seeded device generator
+        g = torch.Generator(device=dev)
+        g.manual_seed(4000)
+        rdt = torch.float32 if prec == "fp32" else torch.float64
+        x = (torch.rand(total, 2, dtype=rdt, device=dev, generator=g) * 2 - 1).view(dtype).view(-1)
         y = torch.empty_like(x)
         ref = torch.empty_like(x)
         counts = tf.new_counts(dev)

@@ -23,6 +23,7 @@
 
 #include "tfft.h"
 #include "tfft_ragged.hpp"
+#include "tfft_workspace.hpp"
 
 using namespace tfft;
 
@@ -65,7 +66,6 @@ void cis_neg(long long num, long long den, long double* re, long double* im) {
 
 struct SubTables { void* tw = nullptr; void* left = nullptr; };
 struct PassTwiddle { void* hi = nullptr; void* lo = nullptr; int bits = 0; };
-struct Workspace { void* ptr = nullptr; size_t bytes = 0; };
 
 struct Tuning {
     int T;
@@ -80,7 +80,14 @@ std::map<std::tuple<int, int, int, int, int>, const KernelEntry*> g_by_key;   //
 std::map<std::pair<int, int>, const KernelEntry*> g_ragged_by_key;      // (ragged plan id, ft)
 std::map<std::tuple<int, int, int, long long>, SubTables> g_sub;         // (prec, Ns, device, radices)
 std::map<std::tuple<int, long long, int>, PassTwiddle> g_pass;           // (prec, N, device)
-std::map<int, Workspace> g_ws;                                           // device
+struct DeviceAlloc {
+    bool operator()(void** p, size_t bytes) const {
+        hipError_t e = hipMalloc(p, bytes);
+        if (e != hipSuccess) { g_last_hip = (int)e; *p = nullptr; return false; }
+        return true;
+    }
+};
+WorkspacePool<DeviceAlloc> g_ws{DeviceAlloc{}};                          // (device, stream)
 std::map<std::tuple<int, long long, int>, Tuning> g_tuning;   // (prec, N, ft mode 0..2)
 
 struct Inject {
@@ -337,21 +344,21 @@ int get_pass(int precision, long long N, bool may_alloc, PassTwiddle** out) {
     return TFFT_OK;
 }
 
-int get_workspace(size_t bytes, bool may_alloc, void** out) {
-    Workspace& w = g_ws[current_device()];
-    if (w.bytes >= bytes) { *out = w.ptr; return TFFT_OK; }
-    if (!may_alloc) return TFFT_ECAPTURE;
-    if (w.ptr) {
-        hipError_t e = hipDeviceSynchronize();   // no kernel may still use the old buffer
-        if (e != hipSuccess) return hip_fail(e);
-        (void)hipFree(w.ptr);
-        w = Workspace{};
+int get_workspace(size_t bytes, hipStream_t stream, bool may_alloc, void** out) {
+    switch (g_ws.get(current_device(), stream, bytes, may_alloc, out)) {
+        case WsResult::kOk: return TFFT_OK;
+        case WsResult::kWouldAllocate: return TFFT_ECAPTURE;
+        default: return TFFT_ENOMEM;
     }
-    hipError_t e = hipMalloc(&w.ptr, bytes);
-    if (e != hipSuccess) { g_last_hip = (int)e; w = Workspace{}; return TFFT_ENOMEM; }
-    w.bytes = bytes;
-    *out = w.ptr;
-    return TFFT_OK;
+}
+
+// signals per chunk of a two-pass transform: the tuned chunk in whole
+// signals, at least one, at most the batch
+long long chunk_signals(long long N, long long batch, size_t elem_bytes, const Tuning& tu) {
+    long long chunk = tu.chunk_bytes / (long long)((size_t)N * elem_bytes);
+    if (chunk < 1) chunk = 1;
+    if (chunk > batch) chunk = batch;
+    return chunk;
 }
 
 template <class V> struct Launch {
@@ -428,11 +435,9 @@ int transform(const Route& rt, const void* x, void* y, long long N, long long ba
     if (rc == TFFT_OK) rc = get_pass(precision, N, may_alloc, &pt);
     if (rc != TFFT_OK) return rc;
     const size_t sig_bytes = (size_t)N * sizeof(V);
-    long long chunk = tu.chunk_bytes / (long long)sig_bytes;
-    if (chunk < 1) chunk = 1;
-    if (chunk > batch) chunk = batch;
+    const long long chunk = chunk_signals(N, batch, sizeof(V), tu);
     void* ws = nullptr;
-    rc = get_workspace((size_t)chunk * sig_bytes, may_alloc, &ws);
+    rc = get_workspace((size_t)chunk * sig_bytes, stream, may_alloc, &ws);
     if (rc != TFFT_OK) return rc;
 
     KArgs<V> A{}, B{};
@@ -523,6 +528,8 @@ KernelEntry g_ragged_prof_entry[3];   // labels of the persistent launches in th
 long long g_ragged_window = 0;        // workspace window of new plans (elements, 0: flat)
 long long g_ragged_item = 32768;      // elements per work item of new plans
 int g_ragged_waves = 3;               // persistent kernel register budget of new plans
+unsigned g_ragged_max_polls = 0;      // test hook: bound of one wait (0: the default)
+unsigned g_ragged_wait_extra = 0;     // test hook: added to what every wait needs
 
 RaggedKernel ragged_kernel(int ft, int waves) {
     static RaggedKernel k[3][2];
@@ -819,6 +826,7 @@ int ragged_build(tfft_ragged_plan_s* P, const long long* sizes, long long count)
     desc.cnt_b = reinterpret_cast<unsigned*>(base + o_cb);
     desc.cnt_r = reinterpret_cast<unsigned*>(base + o_cr);
     desc.n_batches = (long long)batches.size();
+    desc.n_groups = groups_tot;
     desc.ws = static_cast<float2*>(P->ws);
     P->d_desc = reinterpret_cast<RaggedDesc*>(base + o_desc);
     P->d_queue = desc.q;
@@ -847,6 +855,8 @@ int ragged_exec(tfft_ragged_plan_s* P, const void* x, void* y, int dir, int unit
     c.conj = dir == TFFT_INVERSE ? 1 : 0;
     c.unit_scale = unit_scale ? 1 : 0;
     c.stats = g_stats ? 1 : 0;
+    c.max_polls = g_ragged_max_polls ? g_ragged_max_polls : kMaxPolls;
+    c.wait_extra = g_ragged_wait_extra;
     if (P->n_items == 0) return TFFT_OK;
     if (mode == TFFT_RAGGED_PERSISTENT) {
         const RaggedKernel k = ragged_kernel(ft, P->waves);
@@ -1043,18 +1053,30 @@ int tfft_supported(long long N, int precision) {
     return route_for(precision, N, 0, &r) ? 1 : 0;
 }
 
-int tfft_prepare(long long N, int precision, int ft_mode) {
-    if (N < 1 || check_precision(precision) != TFFT_OK || ft_mode < 0 || ft_mode > 2) return TFFT_EINVAL;
+int tfft_prepare(long long N, long long batch, int precision, int ft_mode, void* hip_stream) {
+    if (N < 1 || batch < 0 || check_precision(precision) != TFFT_OK || ft_mode < 0 || ft_mode > 2)
+        return TFFT_EINVAL;
     std::lock_guard<std::mutex> lk(g_mu);
     ensure_registry();
+    const Tuning tu = get_tuning(precision, N, ft_mode);
     Route r;
-    if (!route_for(precision, N, ft_mode, &r, get_tuning(precision, N, ft_mode).route)) return TFFT_EUNSUPPORTED;
+    if (!route_for(precision, N, ft_mode, &r, tu.route)) return TFFT_EUNSUPPORTED;
     SubTables* st = nullptr;
-    if (r.single) return get_sub(*r.single, true, &st);
+    if (r.single) {
+        int rc = get_sub(*r.single, true, &st);
+        // the in-place correcting kernel shares the tables of its plan
+        return rc;
+    }
     int rc = get_sub(*r.col, true, &st);
     if (rc == TFFT_OK) rc = get_sub(*r.row, true, &st);
     PassTwiddle* pt = nullptr;
     if (rc == TFFT_OK) rc = get_pass(precision, N, true, &pt);
+    if (rc == TFFT_OK && batch > 0) {
+        const size_t S = precision == TFFT_FP32 ? 8 : 16;
+        void* ws = nullptr;
+        rc = get_workspace((size_t)chunk_signals(N, batch, S, tu) * (size_t)N * S,
+                           static_cast<hipStream_t>(hip_stream), true, &ws);
+    }
     return rc;
 }
 
@@ -1384,7 +1406,7 @@ int tfft_ragged_plan_info(tfft_ragged_plan plan, long long* info, int n) {
         RQueue q{};
         hipError_t err = hipMemcpy(&q, plan->d_queue, sizeof(q), hipMemcpyDeviceToHost);
         if (err != hipSuccess) return hip_fail(err);
-        v[8] = (long long)q.err;
+        v[8] = (long long)q.err_launches;
         v[9] = (long long)q.next;
     }
     for (int i = 0; i < n && i < 10; ++i) info[i] = v[i];
@@ -1397,6 +1419,13 @@ int tfft_ragged_set_schedule(long long window_elems, long long item_elems, int w
     g_ragged_window = window_elems;
     if (item_elems > 0) g_ragged_item = item_elems;
     g_ragged_waves = waves;
+    return TFFT_OK;
+}
+
+int tfft_ragged_test_wait(unsigned max_polls, unsigned extra) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_ragged_max_polls = max_polls;
+    g_ragged_wait_extra = extra;
     return TFFT_OK;
 }
 

@@ -58,7 +58,10 @@
 namespace tfft {
 
 struct FtCounts {   // mirrors tfft_ft_counts in the public header
-    unsigned long long detected, corrected, rebuilt, uncorrectable, last_signal, reserved[3];
+    unsigned long long detected, corrected, rebuilt, uncorrectable, last_signal;
+    unsigned long long calib;          // calibration: max |D0| / tau (bits of a double)
+    unsigned long long sched_errors;   // ragged launches whose waits gave up
+    unsigned long long fallback;       // detections located by re-encoding the group
 };
 
 enum Kind { kSingle = 0, kColPass = 1, kRowPass = 2 };
@@ -861,7 +864,7 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
         if (kc.stats && checked && nf == 0 && t == 0 && tau > (R)0) {
             // calibration: largest |D0| / tau seen (non-negative doubles order as integers)
             const double q = (double)d0 / (double)tau;
-            atomicMax(&kc.counts->reserved[0], (unsigned long long)__double_as_longlong(q));
+            atomicMax(&kc.counts->calib, (unsigned long long)__double_as_longlong(q));
         }
 
         // Location fallback on the error path: when D1/D0 is not an index (an

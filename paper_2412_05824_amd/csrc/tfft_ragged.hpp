@@ -16,6 +16,15 @@
 
 namespace tfft {
 
+// Default bound on the polls of one wait (a poll is a device-scope load plus
+// a short sleep, about a microsecond): far beyond any column pass, so it only
+// ends a wait whose counters are out of step.  It sets the error bit, and
+// every later wait of the launch gives up at once, so even a broken schedule
+// drains the queue in bounded time instead of hanging.  The last workgroup
+// out reports the error (counts->sched_errors and the plan's sticky count),
+// clears it and zeroes every counter, so the next launch starts in step.
+constexpr unsigned kMaxPolls = 1u << 20;
+
 constexpr int kRaggedThreads = 256;
 constexpr int kRaggedSlotBytes = 16;   // LDS slot for the item index, ahead of the plan's LDS
 
@@ -50,8 +59,8 @@ struct RItem {
 struct RQueue {
     unsigned long long next;   // next item to hand out
     unsigned long long done;   // workgroups that have left the loop
-    unsigned long long err;    // bit 0: a row-pass wait gave up (counters out of step)
-    unsigned long long pad;
+    unsigned long long err;    // bit 0: a wait of this launch gave up (cleared at its end)
+    unsigned long long err_launches;   // launches that ended with err set (sticky)
 };
 
 // Device-resident description of one ragged plan, written once by the host.
@@ -64,6 +73,7 @@ struct RaggedDesc {
     unsigned* cnt_b;           // per group: row-pass items past their wait
     unsigned* cnt_r;           // per batch: finished row-pass items (windowed workspace)
     long long n_batches;
+    long long n_groups;        // entries of cnt_a and cnt_b
     float2* ws;                // column-pass results of the two-pass signals
 };
 
@@ -78,6 +88,8 @@ struct RaggedCall {
     int conj;                  // 1: inverse direction
     int unit_scale;            // 1: scale 1 (else 1 forward, 1/N inverse)
     int stats;
+    unsigned max_polls;        // bound of one wait (polls)
+    unsigned wait_extra;       // test hook: added to what every wait needs (0)
     int pad;
 };
 

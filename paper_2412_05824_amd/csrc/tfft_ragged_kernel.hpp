@@ -70,12 +70,6 @@ __device__ __forceinline__ long long share_item(long long mine) {
     return uni(*slot);
 }
 
-// Upper bound on the polls of one row-pass wait (a poll is a device-scope
-// load plus a short sleep, about a microsecond): far beyond any column pass,
-// so it only ends a wait whose counters are out of step.  It sets the error
-// bit, and every later wait of the launch gives up at once, so even a broken
-// schedule drains the queue in bounded time instead of hanging.
-constexpr unsigned kMaxPolls = 1u << 20;
 
 // One work item.  Column passes write the workspace with coherent stores and
 // row passes read it with coherent loads, so handing results from one pass
@@ -83,10 +77,12 @@ constexpr unsigned kMaxPolls = 1u << 20;
 // pass waits for its stores to complete before it counts itself done, and a
 // row pass starts loading only after every count of its group is in.
 // Thread 0 waits until *ctr reaches need (bounded; see kMaxPolls).
-__device__ __forceinline__ void wait_count(const RaggedDesc& d, unsigned* ctr, unsigned need) {
+__device__ __forceinline__ void wait_count(const RaggedCall& c, const RaggedDesc& d, unsigned* ctr,
+                                           unsigned need) {
     unsigned polls = 0;
+    need += c.wait_extra;
     while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
-        if (++polls > kMaxPolls ||
+        if (++polls > c.max_polls ||
             __hip_atomic_load(&d.q->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0ull) {
             atomicOr(&d.q->err, 1ull);
             break;
@@ -107,14 +103,14 @@ __device__ __forceinline__ void ragged_step(const RaggedCall& c, const RaggedDes
     if constexpr (PL::KIND == kColPass) {
         // windowed workspace: the half this batch writes has been read out
         if (it.wait_batch >= 0) {
-            if (threadIdx.x == 0) wait_count(d, &d.cnt_r[it.wait_batch], (unsigned)it.wait_need);
+            if (threadIdx.x == 0) wait_count(c, d, &d.cnt_r[it.wait_batch], (unsigned)it.wait_need);
             __syncthreads();
         }
     }
     if constexpr (PL::KIND == kRowPass) {
         // every column-pass item of this group has finished
         if (threadIdx.x == 0) {
-            wait_count(d, &d.cnt_a[cnt], (unsigned)need);
+            wait_count(c, d, &d.cnt_a[cnt], (unsigned)need);
             // the last row-pass item of the group resets both counters for
             // the next launch; the others have all passed their wait
             if (atomicAdd(&d.cnt_b[cnt], 1u) == (unsigned)(cl->items_per_group - 1)) {
@@ -199,8 +195,24 @@ __device__ __forceinline__ void ragged_loop(const RaggedCall& c, const RaggedDes
                        ? 1
                        : 0);
     if (last) {
+        // every other workgroup has left the loop, so every item has finished
+        // and no counter changes any more
+        const unsigned long long err =
+            uni((long long)__hip_atomic_load(&d.q->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
         for (long long i = threadIdx.x; i < d.n_batches; i += kRaggedThreads) atomicExch(&d.cnt_r[i], 0u);
+        if (err != 0ull) {
+            // a wait gave up: the per-group counters may be out of step
+            for (long long i = threadIdx.x; i < d.n_groups; i += kRaggedThreads) {
+                atomicExch(&d.cnt_a[i], 0u);
+                atomicExch(&d.cnt_b[i], 0u);
+            }
+        }
         if (threadIdx.x == 0) {
+            if (err != 0ull) {
+                atomicAdd(&d.q->err_launches, 1ull);
+                if (c.counts) atomicAdd(&c.counts->sched_errors, 1ull);
+                atomicExch(&d.q->err, 0ull);
+            }
             atomicExch(&d.q->next, 0ull);
             atomicExch(&d.q->done, 0ull);
         }

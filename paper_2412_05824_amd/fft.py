@@ -5,7 +5,8 @@
 x is a [batch, N] complex64 (fp32) or complex128 (fp64) CUDA tensor.  The
 call runs on torch's current stream; counts is a device int64 tensor of 8
 entries laid out like tfft_ft_counts (detected, corrected, rebuilt,
-uncorrectable, last_signal, reserved...), accumulated, never synchronised.
+uncorrectable, last_signal, calib, sched_errors, fallback), accumulated,
+never synchronised.
 """
 from __future__ import annotations
 
@@ -13,7 +14,8 @@ import torch
 
 from . import _lib
 
-COUNT_FIELDS = ("detected", "corrected", "rebuilt", "uncorrectable", "last_signal")
+COUNT_FIELDS = ("detected", "corrected", "rebuilt", "uncorrectable", "last_signal", "calib",
+                "sched_errors", "fallback")
 
 
 def _precision(dtype) -> int:
@@ -61,8 +63,15 @@ def fft_c2c(x: torch.Tensor, dir: int = -1, ft_mode: int = 2, out: torch.Tensor 
     return out, counts
 
 
-def prepare(N: int, dtype=torch.complex64, ft_mode: int = 2) -> None:
-    _lib.check(_lib.load().tfft_prepare(N, _precision(dtype), ft_mode), f"tfft_prepare(N={N})")
+def prepare(N: int, dtype=torch.complex64, ft_mode: int = 2, batch: int = 0, device=None) -> None:
+    """Build the tables of length N and, for batch > 0, reserve the two-pass
+    workspace for up to `batch` signals on torch's current stream (call
+    before capturing fft_c2c into a graph)."""
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    with torch.cuda.device(dev):
+        st = _lib.load().tfft_prepare(N, int(batch), _precision(dtype), ft_mode,
+                                      _stream_ptr(dev) if batch > 0 else None)
+    _lib.check(st, f"tfft_prepare(N={N}, batch={batch})")
 
 
 def supported(N: int, dtype=torch.complex64) -> bool:
@@ -139,7 +148,7 @@ class RaggedPlan:
         with torch.cuda.device(self.device):
             _lib.check(_lib.load().tfft_ragged_plan_info(self._h, buf, n), "tfft_ragged_plan_info")
         keys = ("signals", "total", "items", "classes", "ws_elems", "grid", "batches", "window",
-                "queue_err", "queue_next")
+                "err_launches", "queue_next")
         return {k: int(buf[i]) for i, k in enumerate(keys[:n])}
 
     def __call__(self, x: torch.Tensor, out: torch.Tensor | None = None, dir: int = -1,

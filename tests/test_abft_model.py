@@ -13,7 +13,7 @@ import pytest
 
 import oracle
 from oracle import abft_model as am
-from paper_2412_05824_amd import synth
+import synth
 
 
 def brute_left(N, M, dir=-1):

@@ -55,8 +55,9 @@ def test_invalid_arguments_rejected_on_host():
     assert lib.tfft_inject_arm(0, 0, 0, 63, 1) == _lib.TFFT_OK
     assert lib.tfft_inject_disarm() == _lib.TFFT_OK
     assert lib.tfft_set_tuning(64, 0, 33, 0.0) == _lib.TFFT_EINVAL
-    assert lib.tfft_prepare(0, 0, 0) == _lib.TFFT_EINVAL
-    assert lib.tfft_prepare(100, 0, 0) == _lib.TFFT_EUNSUPPORTED
+    assert lib.tfft_prepare(0, 0, 0, 0, None) == _lib.TFFT_EINVAL
+    assert lib.tfft_prepare(256, -1, 0, 0, None) == _lib.TFFT_EINVAL
+    assert lib.tfft_prepare(100, 0, 0, 0, None) == _lib.TFFT_EUNSUPPORTED
     # launch-timing filter: fields in range or -1 (any)
     assert lib.tfft_profile_only(2, -1, -1, -1) == _lib.TFFT_EINVAL
     assert lib.tfft_profile_only(-1, 4, -1, -1) == _lib.TFFT_EINVAL

@@ -10,7 +10,7 @@ import torch
 
 import oracle
 from oracle import abft_model as am
-from paper_2412_05824_amd import synth
+import synth
 
 pytestmark = pytest.mark.gpu
 tf = pytest.importorskip("paper_2412_05824_amd")

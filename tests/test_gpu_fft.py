@@ -12,7 +12,7 @@ import torch
 
 import oracle
 from oracle import abft_model as am
-from paper_2412_05824_amd import synth
+import synth
 
 pytestmark = pytest.mark.gpu
 
@@ -60,7 +60,7 @@ def test_forward_parity_and_ft_bit_identity(dev, N, dtype):
         y0, _ = tf.fft_c2c(xd, dir=tf.FORWARD, ft_mode=tf.FT_OFF)
         y0h = y0.cpu().numpy()
         assert oracle.rel_l2(y0h, ref) <= TOL[dtype]
-        assert _per_signal_rel(y0h, ref).max() <= 2 * TOL[dtype]
+        assert _per_signal_rel(y0h, ref).max() <= TOL[dtype]
         for ft in (tf.FT_DETECT, tf.FT_CORRECT):
             y, counts = tf.fft_c2c(xd, dir=tf.FORWARD, ft_mode=ft)
             c = tf.counts_dict(counts)
@@ -73,7 +73,7 @@ def test_forward_parity_and_ft_bit_identity(dev, N, dtype):
     # and each mode's own tuned plan matches the oracle
     for ft in (tf.FT_OFF, tf.FT_CORRECT):
         y, _ = tf.fft_c2c(xd, dir=tf.FORWARD, ft_mode=ft)
-        assert _per_signal_rel(y.cpu().numpy(), ref).max() <= 2 * TOL[dtype], ft
+        assert _per_signal_rel(y.cpu().numpy(), ref).max() <= TOL[dtype], ft
 
 
 @pytest.mark.parametrize("dtype", DTYPES, ids=["fp32", "fp64"])
@@ -90,6 +90,7 @@ def test_inverse_parity_and_round_trip(dev, N, dtype):
             assert tf.counts_dict(counts)["detected"] == 0
     yf, _ = tf.fft_c2c(xd, dir=tf.FORWARD, ft_mode=tf.FT_CORRECT)
     xr, _ = tf.fft_c2c(yf, dir=tf.INVERSE, ft_mode=tf.FT_CORRECT)
+    # a round trip is two transforms: their errors add
     assert oracle.rel_l2(xr.cpu().numpy(), x) <= 2 * TOL[dtype]
 
 
@@ -146,15 +147,17 @@ def test_injected_flip_detected_located_corrected(dev, N, dtype):
         x, ref, yc, yh, c, delta = _inject_case(dev, dtype, N, batch, sig, elem, part, bit)
         per = _per_signal_rel(yh, ref)
         msg = f"N={N} bit={bit} sig={sig} elem={elem} part={part} delta={delta:.3e} counts={c}"
-        # every output, corrupted or not, ends within tolerance of the oracle
-        assert per.max() <= 2 * tol, msg + f" worst={per.max():.3e} at {per.argmax()}"
+        # every output, corrupted or not, ends within tolerance of the oracle,
+        # and the hit signal within tolerance of its fault-free output
+        assert per.max() <= tol, msg + f" worst={per.max():.3e} at {per.argmax()}"
+        assert oracle.rel_l2(yh[sig], yc[sig]) <= tol, msg
         if c["detected"]:
             assert c["detected"] == 1 and c["uncorrectable"] == 0, msg
             assert c["corrected"] + c["rebuilt"] == 1, msg
             assert c["last_signal"] == sig, msg
         else:
             # only flips far below the signal's norm may pass unnoticed
-            assert delta <= 2 * tol * np.linalg.norm(ref[sig]), msg
+            assert delta <= tol * np.linalg.norm(ref[sig]), msg
         # the uncorrupted signals are bit-identical to the clean run
         others = np.ones(batch, bool)
         others[sig] = False
@@ -189,7 +192,8 @@ def test_resident_loop_late_group(dev, dtype, N, variant):
         ref = oracle.fft(x[pick], threads=8)
         got = y.cpu().numpy()
         for i, s in enumerate(pick):
-            assert oracle.rel_l2(got[s], ref[i]) <= 2 * TOL[dtype], (N, s)
+            assert oracle.rel_l2(got[s], ref[i]) <= TOL[dtype], (N, s)
+        assert oracle.rel_l2(got[sig], y0[sig].cpu().numpy()) <= TOL[dtype]
         others = torch.ones(batch, dtype=torch.bool, device=dev)
         others[sig] = False
         assert torch.equal(y[others], y0[others])
@@ -211,7 +215,8 @@ def test_exponent_flips_always_detected(dev, dtype):
         msg = f"bit={bit} sig={sig} elem={elem} counts={c} delta={delta}"
         assert c["detected"] == 1 and c["corrected"] + c["rebuilt"] == 1, msg
         assert c["last_signal"] == sig, msg
-        assert oracle.rel_l2(yh[sig], ref[sig]) <= 2 * TOL[dtype], msg
+        assert oracle.rel_l2(yh[sig], ref[sig]) <= TOL[dtype], msg
+        assert oracle.rel_l2(yh[sig], yc[sig]) <= TOL[dtype], msg
 
 
 @pytest.mark.parametrize("T", [1, 2, 8])
@@ -265,7 +270,7 @@ def _two_pass_parity(dev, dtype):
         y0, _ = tf.fft_c2c(xd, dir=tf.FORWARD, ft_mode=tf.FT_OFF)
         y0h = y0.cpu().numpy()
         assert oracle.rel_l2(y0h, ref) <= TOL[dtype], N
-        assert _per_signal_rel(y0h, ref).max() <= 2 * TOL[dtype], N
+        assert _per_signal_rel(y0h, ref).max() <= TOL[dtype], N
         for ft in (tf.FT_DETECT, tf.FT_CORRECT):
             y, counts = tf.fft_c2c(xd, dir=tf.FORWARD, ft_mode=ft)
             c = tf.counts_dict(counts)
@@ -300,7 +305,8 @@ def test_two_pass_small_chunks(dev, dtype):
         y_inj, c2 = tf.fft_c2c(xd, ft_mode=tf.FT_CORRECT)
         cd = tf.counts_dict(c2)
         assert cd["detected"] == 1 and cd["last_signal"] == batch - 2, cd
-        assert oracle.rel_l2(y_inj.cpu().numpy()[batch - 2], oracle.fft(x[batch - 2])) <= 2 * TOL[dtype]
+        assert oracle.rel_l2(y_inj.cpu().numpy()[batch - 2], oracle.fft(x[batch - 2])) <= TOL[dtype]
+        assert oracle.rel_l2(y_inj[batch - 2].cpu().numpy(), y_full[batch - 2].cpu().numpy()) <= TOL[dtype]
     finally:
         _lib.load().tfft_set_chunk(N, prec, 128 << 20)
 
@@ -316,21 +322,26 @@ def test_two_pass_injection(dev, dtype):
         x, ref, yc, yh, c, delta = _inject_case(dev, dtype, N, batch, sig, elem, part, bit)
         per = _per_signal_rel(yh, ref)
         msg = f"N={N} bit={bit} sig={sig} elem={elem} counts={c} delta={delta:.3e}"
-        assert per.max() <= 2 * TOL[dtype], msg + f" worst={per.max():.3e}"
+        assert per.max() <= TOL[dtype], msg + f" worst={per.max():.3e}"
+        assert oracle.rel_l2(yh[sig], yc[sig]) <= TOL[dtype], msg
         if c["detected"]:
             assert c["corrected"] + c["rebuilt"] == 1 and c["last_signal"] == sig, msg
         else:
-            assert delta <= 2 * TOL[dtype] * np.linalg.norm(ref[sig]), msg
+            assert delta <= TOL[dtype] * np.linalg.norm(ref[sig]), msg
 
 
-@pytest.mark.parametrize("N", [64, 128, 256, 512, 1024, 2048, 4096, 8192, 1 << 14, 1 << 16])
-def test_no_false_alarm_at_scale(dev, N):
+@pytest.mark.parametrize("dtype,N", [(torch.complex64, n) for n in
+                                     [64, 128, 256, 512, 1024, 2048, 4096, 8192, 1 << 14, 1 << 16]] +
+                         [(torch.complex128, n) for n in [64, 256, 1024, 2048, 4096, 1 << 13, 1 << 16]],
+                         ids=lambda v: str(v).replace("torch.complex64", "fp32").replace("torch.complex128", "fp64"))
+def test_no_false_alarm_at_scale(dev, dtype, N):
     """Fault-free data count no detection also on batches of 2^26 elements
     (tens of thousands of workgroups, so races between waves of a workgroup
     would show), with the tuned route of each length."""
     g = torch.Generator(device=dev)
     g.manual_seed(N)
-    x = (torch.rand((1 << 26) // N, N, 2, device=dev, generator=g) * 2 - 1).view(torch.complex64)
+    rdt = torch.float32 if dtype == torch.complex64 else torch.float64
+    x = (torch.rand((1 << 26) // N, N, 2, dtype=rdt, device=dev, generator=g) * 2 - 1).view(dtype)
     x = x.view((1 << 26) // N, N)
     for ft in (tf.FT_DETECT, tf.FT_CORRECT):
         y, counts = tf.fft_c2c(x, ft_mode=ft)

@@ -13,7 +13,7 @@ import pytest
 import torch
 
 import oracle
-from paper_2412_05824_amd import synth
+import synth
 
 pytestmark = pytest.mark.gpu
 
@@ -117,7 +117,7 @@ def test_ragged_parity_and_modes(dev, ft, window, waves):
     worst = _check_signals(outs["persistent"], x_host, sizes, refs)
     print(f"ragged {len(sizes)} signals ft={ft}: worst rel L2 {worst:.3e}")
     st = plan.info(device_state=True)
-    assert st["queue_err"] == 0 and st["queue_next"] == 0
+    assert st["err_launches"] == 0 and st["queue_next"] == 0
 
 
 def test_ragged_abft_changes_no_bit(dev):
@@ -222,7 +222,7 @@ def test_ragged_graph_replay(dev, window, waves):
         assert np.array_equal(y.cpu().numpy().view(np.uint32), eager.cpu().numpy().view(np.uint32)), r
         assert tf.counts_dict(counts)["detected"] == 0
     st = plan.info(device_state=True)
-    assert st["queue_err"] == 0 and st["queue_next"] == 0
+    assert st["err_launches"] == 0 and st["queue_next"] == 0
     refs = _oracle_ragged(fresh, sizes, only=range(0, len(sizes), 7))
     _check_signals(y.cpu().numpy(), fresh, sizes, refs)
 
@@ -278,4 +278,37 @@ def test_ragged_full_workload(dev, window, waves):
         e = oracle.rel_l2(got, refs[i])
         assert e <= TOL, (i, sizes[i], e)
     st = plan.info(device_state=True)
-    assert st["queue_err"] == 0 and st["queue_next"] == 0
+    assert st["err_launches"] == 0 and st["queue_next"] == 0
+
+
+@pytest.mark.parametrize("window", [0, 1 << 21])
+def test_ragged_wait_bound_reported_then_clean(dev, window):
+    """The host forces every bounded wait of one persistent launch to give
+    up (each wait needs one more finished item than exist and polls at most
+    64 times): the launch still drains, counts one schedule error and leaves
+    its counters zeroed, so the next launch is bit-identical to the per-size
+    launches with no error.  Every kernel exits normally."""
+    from paper_2412_05824_amd import _lib
+    sizes = [1 << 14] * 6 + [3 << 14] * 3 + [1 << 16] * 3 + [256] * 40 + [1 << 17]
+    x = torch.from_numpy(_ragged_input(sizes, seed=301)).to(dev)
+    plan = _plan(sizes, dev, window, 3)
+    lib = _lib.load()
+    ref, _ = plan(x, ft_mode=tf.FT_CORRECT, mode="per_size")
+    counts = tf.new_counts(dev)
+    assert lib.tfft_ragged_test_wait(64, 1) == 0
+    try:
+        plan(x, ft_mode=tf.FT_CORRECT, counts=counts, mode="persistent")
+        torch.cuda.synchronize()
+    finally:
+        lib.tfft_ragged_test_wait(0, 0)
+    c = tf.counts_dict(counts)
+    assert c["sched_errors"] == 1, c
+    st = plan.info(device_state=True)
+    assert st["err_launches"] == 1 and st["queue_next"] == 0, st
+    counts2 = tf.new_counts(dev)
+    y2, _ = plan(x, ft_mode=tf.FT_CORRECT, counts=counts2, mode="persistent")
+    torch.cuda.synchronize()
+    c2 = tf.counts_dict(counts2)
+    assert c2["sched_errors"] == 0 and c2["detected"] == 0, c2
+    assert torch.equal(y2.view(torch.float32), ref.view(torch.float32))
+    assert plan.info(device_state=True)["err_launches"] == 1

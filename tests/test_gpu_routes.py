@@ -11,7 +11,7 @@ import pytest
 import torch
 
 import oracle
-from paper_2412_05824_amd import synth
+import synth
 
 pytestmark = pytest.mark.gpu
 

@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_2412_05824_amd import synth
+import synth
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "dft_small.txt")
 
