@@ -173,13 +173,38 @@ int tfft_c2c_ragged(tfft_ragged_plan plan, const void* x, void* y, int dir, int 
 /* 1 if N (and precision) has a compiled kernel, else 0. */
 int tfft_supported(long long N, int precision);
 
-/* Test hook (Sec. 5.3 injection protocol): arm a single-bit flip for the NEXT
- * tfft_c2c or tfft_c2c_ragged call only.  The flip hits output element
- * `element` of signal `signal` (for a ragged batch: the signal's index in the
- * list) (real part if part == 0, imaginary if 1), bit `bit` of its IEEE
- * representation, inside the kernel after the last butterfly and before the
- * output checksum, i.e. as a compute-unit fault.  Returns TFFT_EINVAL for a
- * bit outside the element's width. */
+/* Test hook (Sec. 5.3 injection protocol; Sec. 2.2 fault model, a fault in
+ * a compute unit that propagates through the later stages): arm a
+ * single-bit flip for the NEXT tfft_c2c or tfft_c2c_ragged call only.
+ *   signal     index of the signal in the call (ragged: index in the list).
+ *   element    position of the value hit, in the numbering of the chosen
+ *              pass: for a single-pass length, the position k < N in the
+ *              sequence the chosen stage produces (after the last stage:
+ *              output element k); for a two-pass length N = N1 * N2 (see
+ *              tfft_route_info), in the column pass k * N2 + n2 (column n2,
+ *              position k of its N1-point sequence; after the last stage the
+ *              intermediate value of row k), in the row pass n1 + N1 * k (row
+ *              n1, position k of its N2-point sequence; after the last stage
+ *              output element n1 + N1 * k).
+ *   part       0: real part, 1: imaginary part.
+ *   bit        bit of the IEEE binary32 (0..31) or binary64 (0..63) value.
+ *   precision  TFFT_FP32 or TFFT_FP64; must match the call.
+ *   pass       -1: the last pass; 0: the single pass or the column pass;
+ *              1: the row pass.
+ *   stage      -1: after the last radix stage (an output value of the pass,
+ *              before its checksum and store); s >= 0: after radix stage s,
+ *              on the value held between stage s and s + 1.
+ * The flip happens in registers inside the kernel.  The call returns
+ * TFFT_EINVAL when the injection does not fit it (signal, element, pass or
+ * stage out of range, other precision); arming returns TFFT_EINVAL for a
+ * field out of range. */
+typedef struct {
+    long long signal, element;
+    int part, bit, precision, pass, stage, reserved;
+} tfft_inject_desc;
+int tfft_inject_arm_desc(const tfft_inject_desc* desc);
+
+/* The same flip of an output value of the last pass (pass -1, stage -1). */
 int tfft_inject_arm(long long signal, long long element, int part, int bit, int precision);
 int tfft_inject_disarm(void);
 
@@ -210,6 +235,13 @@ int tfft_set_chunk(long long N, int precision, long long chunk_bytes);
  * tfft_set_tuning / tfft_set_chunk also apply to every mode; the tuning
  * table may set each mode apart. */
 int tfft_routes(long long N, int precision, int ft_mode, long long* codes, int cap);
+
+/* The route tfft_c2c takes now for (N, precision, ft_mode): up to n values
+ * [0] passes (1 or 2), [1] N1 (column-pass length; N for a single pass),
+ * [2] N2 (row-pass length; 1 for a single pass), [3] radix stages of pass 0,
+ * [4] radix stages of pass 1 (0 for a single pass), [5] transactions per
+ * checksum group T.  TFFT_EUNSUPPORTED for a length without a route. */
+int tfft_route_info(long long N, int precision, int ft_mode, long long* info, int n);
 int tfft_set_route(long long N, int precision, long long code);
 int tfft_get_route(long long N, int precision, int ft_mode, long long* code);
 

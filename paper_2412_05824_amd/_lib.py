@@ -45,6 +45,8 @@ SIGNATURES = {
     "tfft_ragged_test_wait": ([ctypes.c_uint, ctypes.c_uint], _I),
     "tfft_supported": ([_LL, _I], _I),
     "tfft_inject_arm": ([_LL, _LL, _I, _I, _I], _I),
+    "tfft_inject_arm_desc": ([_VP], _I),
+    "tfft_route_info": ([_LL, _I, _I, ctypes.POINTER(_LL), _I], _I),
     "tfft_inject_disarm": ([], _I),
     "tfft_set_tuning": ([_LL, _I, _I, _D], _I),
     "tfft_get_tuning": ([_LL, _I, ctypes.POINTER(_I), ctypes.POINTER(_D)], _I),
@@ -60,6 +62,12 @@ SIGNATURES = {
     "tfft_strerror": ([_I], ctypes.c_char_p),
     "tfft_last_hip_error": ([], _I),
 }
+
+
+class InjectDesc(ctypes.Structure):
+    """tfft_inject_desc of include/tfft.h."""
+    _fields_ = [("signal", _LL), ("element", _LL), ("part", _I), ("bit", _I),
+                ("precision", _I), ("pass_", _I), ("stage", _I), ("reserved", _I)]
 
 
 class TfftError(RuntimeError):

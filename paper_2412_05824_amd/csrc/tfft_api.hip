@@ -94,7 +94,32 @@ struct Inject {
     bool armed = false;
     long long signal = -1, element = 0;
     int part = 0, bit = 0, precision = 0;
+    int pass = -1;    // -1 last pass, 0 first (single or column pass), 1 row pass
+    int stage = -1;   // -1 after the last radix stage, else after stage `stage`
 } g_inj;
+
+// kernel-side injection fields of a launch that is pass `pass` (0 or 1) of a
+// route with `passes` passes, of a plan with `stages` radix stages
+template <class R> void arm_launch(KCall<R>& k, const Inject& inj, int pass, int passes, int stages) {
+    k.inj_signal = -1;
+    if (!inj.armed) return;
+    const int want = inj.pass < 0 ? passes - 1 : inj.pass;
+    if (want != pass) return;
+    k.inj_signal = inj.signal;
+    k.inj_elem = inj.element;
+    k.inj_part = inj.part;
+    k.inj_bit = inj.bit;
+    k.inj_stage = inj.stage < 0 ? stages - 1 : inj.stage;
+}
+
+// an armed injection fits a route: its pass exists and so does its stage
+bool inject_fits(const Inject& inj, const KernelEntry* first, const KernelEntry* second) {
+    if (!inj.armed) return true;
+    const int passes = second ? 2 : 1;
+    if (inj.pass >= passes || inj.pass < -1) return false;
+    const KernelEntry* e = (inj.pass == 0 || passes == 1) ? first : second;
+    return inj.stage < e->n_stages && inj.stage >= -1;
+}
 
 bool g_stats = false;   // calibration mode: kernels record max |D0| / tau
 
@@ -423,7 +448,7 @@ int transform(const Route& rt, const void* x, void* y, long long N, long long ba
         a.scale = (R)scale;
         a.sig_base = 0;
         a.x_intact = x != y ? 1 : 0;
-        if (inj.armed) { a.inj_signal = inj.signal; a.inj_elem = inj.element; a.inj_part = inj.part; a.inj_bit = inj.bit; }
+        arm_launch(a, inj, 0, 1, rt.single->n_stages);
         const long long per_block = (long long)rt.single->slots_per_block * tu.T;
         return run<V>(*rt.single, x, y, a, (batch + per_block - 1) / per_block, stream);
     }
@@ -463,13 +488,10 @@ int transform(const Route& rt, const void* x, void* y, long long N, long long ba
         const long long cnt = (batch - c0 < chunk) ? batch - c0 : chunk;
         A.batch = B.batch = cnt;
         A.sig_base = B.sig_base = c0;
-        B.inj_signal = -1;
-        if (inj.armed && inj.signal >= c0 && inj.signal < c0 + cnt) {
-            B.inj_signal = inj.signal;   // global index: the kernel compares sig_base + s
-            B.inj_elem = inj.element;
-            B.inj_part = inj.part;
-            B.inj_bit = inj.bit;
-        }
+        // global signal index: the kernels compare sig_base + s
+        arm_launch(A, inj, 0, 2, rt.col->n_stages);
+        arm_launch(B, inj, 1, 2, rt.row->n_stages);
+        if (!(inj.signal >= c0 && inj.signal < c0 + cnt)) A.inj_signal = B.inj_signal = -1;
         const long long groups = (cnt + tu.T - 1) / tu.T;
         rc = run<V>(*rt.col, xb + (size_t)c0 * sig_bytes, ws, A, groups * A.tiles, stream);
         if (rc != TFFT_OK) return rc;
@@ -852,6 +874,8 @@ int ragged_exec(tfft_ragged_plan_s* P, const void* x, void* y, int dir, int unit
     c.inj_elem = inj.element;
     c.inj_part = inj.part;
     c.inj_bit = inj.bit;
+    c.inj_pass = inj.pass;
+    c.inj_stage = inj.stage;
     c.conj = dir == TFFT_INVERSE ? 1 : 0;
     c.unit_scale = unit_scale ? 1 : 0;
     c.stats = g_stats ? 1 : 0;
@@ -894,10 +918,10 @@ int ragged_exec(tfft_ragged_plan_s* P, const void* x, void* y, int dir, int unit
         a.scale = (cl.final_pass && c.conj && !c.unit_scale) ? 1.0f / (float)a.N : 1.0f;
         a.counts = c.counts;
         a.stats = c.stats;
-        a.inj_signal = cl.final_pass ? c.inj_signal : -1;
-        a.inj_elem = c.inj_elem;
-        a.inj_part = c.inj_part;
-        a.inj_bit = c.inj_bit;
+        {
+            const int passes = (cl.src_ws || cl.dst_ws) ? 2 : 1;
+            arm_launch(a, inj, cl.src_ws ? 1 : 0, passes, e->n_stages);
+        }
         const void* src = cl.src_ws ? P->ws : x;
         void* dst = cl.dst_ws ? P->ws : y;
         int rc = run<float2>(*e, src, dst, a, cl.nblocks, stream);
@@ -1131,6 +1155,25 @@ int tfft_set_route(long long N, int precision, long long code) {
     return set_route_locked(N, precision, -1, code);
 }
 
+int tfft_route_info(long long N, int precision, int ft_mode, long long* info, int n) {
+    if (!info || n < 1 || N < 1 || check_precision(precision) != TFFT_OK || ft_mode < 0 || ft_mode > 2)
+        return TFFT_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    ensure_registry();
+    const Tuning tu = get_tuning(precision, N, ft_mode);
+    Route r;
+    if (!route_for(precision, N, ft_mode, &r, tu.route)) return TFFT_EUNSUPPORTED;
+    long long v[6];
+    if (r.single) {
+        v[0] = 1; v[1] = N; v[2] = 1; v[3] = r.single->n_stages; v[4] = 0;
+    } else {
+        v[0] = 2; v[1] = r.N1; v[2] = r.N2; v[3] = r.col->n_stages; v[4] = r.row->n_stages;
+    }
+    v[5] = tu.T;
+    for (int i = 0; i < n && i < 6; ++i) info[i] = v[i];
+    return TFFT_OK;
+}
+
 int tfft_get_route(long long N, int precision, int ft_mode, long long* code) {
     if (!code || N < 1 || check_precision(precision) != TFFT_OK || ft_mode < 0 || ft_mode > 2)
         return TFFT_EINVAL;
@@ -1288,19 +1331,35 @@ int tfft_calibration(int on) {
     return TFFT_OK;
 }
 
-int tfft_inject_arm(long long signal, long long element, int part, int bit, int precision) {
-    if (signal < 0 || element < 0 || (part != 0 && part != 1)) return TFFT_EINVAL;
-    if (check_precision(precision) != TFFT_OK) return TFFT_EINVAL;
-    const int width = precision == TFFT_FP32 ? 32 : 64;
-    if (bit < 0 || bit >= width) return TFFT_EINVAL;
+int tfft_inject_arm_desc(const tfft_inject_desc* d) {
+    if (!d) return TFFT_EINVAL;
+    if (d->signal < 0 || d->element < 0 || (d->part != 0 && d->part != 1)) return TFFT_EINVAL;
+    if (check_precision(d->precision) != TFFT_OK) return TFFT_EINVAL;
+    const int width = d->precision == TFFT_FP32 ? 32 : 64;
+    if (d->bit < 0 || d->bit >= width) return TFFT_EINVAL;
+    if (d->pass < -1 || d->pass > 1 || d->stage < -1) return TFFT_EINVAL;
     std::lock_guard<std::mutex> lk(g_mu);
     g_inj.armed = true;
-    g_inj.signal = signal;
-    g_inj.element = element;
-    g_inj.part = part;
-    g_inj.bit = bit;
-    g_inj.precision = precision;
+    g_inj.signal = d->signal;
+    g_inj.element = d->element;
+    g_inj.part = d->part;
+    g_inj.bit = d->bit;
+    g_inj.precision = d->precision;
+    g_inj.pass = d->pass;
+    g_inj.stage = d->stage;
     return TFFT_OK;
+}
+
+int tfft_inject_arm(long long signal, long long element, int part, int bit, int precision) {
+    tfft_inject_desc d{};
+    d.signal = signal;
+    d.element = element;
+    d.part = part;
+    d.bit = bit;
+    d.precision = precision;
+    d.pass = -1;
+    d.stage = -1;
+    return tfft_inject_arm_desc(&d);
 }
 
 int tfft_inject_disarm(void) {
@@ -1340,7 +1399,8 @@ int tfft_c2c(const void* x, void* y, long long N, long long batch, int dir, int 
         if (!rt.single) return TFFT_EUNSUPPORTED;
     }
     Inject inj = g_inj;
-    if (inj.armed && (inj.precision != precision || inj.signal >= batch || inj.element >= N))
+    if (inj.armed && (inj.precision != precision || inj.signal >= batch || inj.element >= N ||
+                      !inject_fits(inj, rt.single ? rt.single : rt.col, rt.single ? nullptr : rt.row)))
         return TFFT_EINVAL;
     const bool may_alloc = !capturing(stream);
     int rc;
@@ -1453,6 +1513,10 @@ int tfft_c2c_ragged(tfft_ragged_plan plan, const void* x, void* y, int dir, int 
     if (inj.armed) {
         if (inj.precision != plan->precision || inj.signal >= plan->count ||
             inj.element >= plan->sizes[(size_t)inj.signal])
+            return TFFT_EINVAL;
+        RRoute rr;
+        if (!ragged_route(plan->sizes[(size_t)inj.signal], &rr) ||
+            !inject_fits(inj, rr.single ? rr.single : rr.col, rr.single ? nullptr : rr.row))
             return TFFT_EINVAL;
     }
     int rc = ragged_exec(plan, x, y, dir, unit_scale, mode, ft_mode, counts, inj, stream);

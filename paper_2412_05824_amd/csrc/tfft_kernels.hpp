@@ -75,9 +75,10 @@ template <class R> struct KCall {
     int stats;            // 1: record max |D0| / tau over groups (calibration)
     FtCounts* counts;     // device counters (ABFT only)
     long long inj_signal; // signal to corrupt (-1: none)
-    long long inj_elem;   // element index in this kernel's output numbering
+    long long inj_elem;   // element index in this kernel's numbering (see Geo::inj_r)
     int inj_part;         // 0 real, 1 imaginary
     int inj_bit;          // bit to flip
+    int inj_stage;        // radix stage after which the value is hit (the last: the output)
 };
 
 // Arguments of one launch (a plain launch passes them as its kernel argument;
@@ -226,10 +227,15 @@ __device__ __forceinline__ void stockham_stage(V (&reg)[E], const V* __restrict_
 
 // All stages of one in-slot FFT.  reg holds elements t + P*r on entry and the
 // transform's outputs t + P*r on exit.  Stage s's table holds L_s * R_s
-// entries and the tables follow each other.
-template <class V, int E, int P, bool BLOCK, class LI, int L, int R, int... Rest>
+// entries and the tables follow each other.  hook(s, reg) runs after stage s
+// (S counts the stages), on the values t + P*r of the intermediate sequence
+// the stage produced (the fault-injection point; a no-op outside tests).
+struct NoHook {
+    template <class A> __device__ __forceinline__ void operator()(int, A&) const {}
+};
+template <class V, int E, int P, bool BLOCK, class LI, class H, int S, int L, int R, int... Rest>
 __device__ __forceinline__ void slot_fft(V (&reg)[E], const V* __restrict__ tw, int t,
-                                         V* __restrict__ lds, const LI& li) {
+                                         V* __restrict__ lds, const LI& li, H& hook) {
     constexpr bool LAST = sizeof...(Rest) == 0;
     stockham_stage<V, E, P, R, L, LAST>(reg, tw, t, lds, li);
     if constexpr (!LAST) {
@@ -243,7 +249,10 @@ __device__ __forceinline__ void slot_fft(V (&reg)[E], const V* __restrict__ tw, 
             for (int r = 0; r < E; ++r) reg[r] = lds[li(t + P * r)];
         }
         lds_sync<BLOCK>();
-        slot_fft<V, E, P, BLOCK, LI, L * R, Rest...>(reg, tw + L * R, t, lds, li);
+        hook(S, reg);
+        slot_fft<V, E, P, BLOCK, LI, H, S + 1, L * R, Rest...>(reg, tw + L * R, t, lds, li, hook);
+    } else {
+        hook(S, reg);
     }
 }
 
@@ -411,9 +420,11 @@ template <class V, class PL, bool IND> struct Geo {
         else if constexpr (PL::KIND == kColPass) return out_base(a, s) + (long long)k * a.N2 + line;
         else return out_base(a, s) + line + (long long)a.N1 * k;
     }
-    // which of this lane's output elements t + P r is the injected one (this
-    // kernel's numbering): r, or -1 (test hook; one division per transaction
-    // instead of a 64-bit compare per element)
+    // which of this lane's values t + P r is the injected one: r, or -1 (test
+    // hook).  inj_elem numbers a value of position k of a sub-sequence as k
+    // (single pass), k N2 + n2 (column n2 of a column pass) or n1 + N1 k
+    // (row n1 of a row pass), the layouts the passes store; k is the
+    // position in the sequence the chosen stage produces.
     __device__ __forceinline__ int inj_r(const KArgs<V>& a, const KCall<typename RealOf<V>::type>& kc) const {
         long long k = -1;   // index of the target in this slot's numbering
         if constexpr (PL::KIND == kSingle) {
@@ -768,18 +779,21 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
             }
         }
 
-        slot_fft<V, E, P, BLOCK, decltype(li), 1, Rs...>(reg, a.tw, t, lds, li);
-
-        if (kc.inj_signal >= 0 && valid && g.gid(a, s) == kc.inj_signal) {   // test hook: one bit flip
-            const int rh = g.inj_r(a, kc);
+        // test hook: one bit flip in the value of position inj_elem after
+        // radix stage inj_stage (a uniform branch on kernel arguments)
+        auto inject = [&](int stage, V (&rg)[E]) {
+            if (kc.inj_signal >= 0 && kc.inj_stage == stage && valid && g.gid(a, s) == kc.inj_signal) {
+                const int rh = g.inj_r(a, kc);
 #pragma unroll
-            for (int r = 0; r < E; ++r) {
-                if (r == rh) {
-                    if (kc.inj_part == 0) reg[r].x = flip_bit(reg[r].x, kc.inj_bit);
-                    else reg[r].y = flip_bit(reg[r].y, kc.inj_bit);
+                for (int r = 0; r < E; ++r) {
+                    if (r == rh) {
+                        if (kc.inj_part == 0) rg[r].x = flip_bit(rg[r].x, kc.inj_bit);
+                        else rg[r].y = flip_bit(rg[r].y, kc.inj_bit);
+                    }
                 }
             }
-        }
+        };
+        slot_fft<V, E, P, BLOCK, decltype(li), decltype(inject), 0, 1, Rs...>(reg, a.tw, t, lds, li, inject);
 
         if constexpr (FT != 0) {
             const V q = encode_out<V, E, P, M>(reg);
@@ -905,7 +919,11 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
                 const R m2 = d[0] * d[0] + d[1] * d[1];
                 if (vb && m2 > best) { best = m2; bbest = b; }
             }
-            if (action == 3 && nf == 0 && bbest >= 0) { bstar = bbest; action = 1; }
+            if (action == 3 && nf == 0 && bbest >= 0) {
+                bstar = bbest;
+                action = 1;
+                if (t == 0) atomicAdd(&kc.counts->fallback, 1ull);
+            }
         }
         const long long sstar = g.sig(bstar < 0 ? 0 : bstar);
 
@@ -939,7 +957,8 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
                     if constexpr (PL::KIND == kRowPass) acc = cmul(acc, g.twiddle(a, r));
                     reg[r] = acc;
                 }
-                slot_fft<V, E, P, BLOCK, decltype(li), 1, Rs...>(reg, a.tw, t, lds, li);   // W x_s
+                NoHook nohook;
+                slot_fft<V, E, P, BLOCK, decltype(li), NoHook, 0, 1, Rs...>(reg, a.tw, t, lds, li, nohook);   // W x_s
                 // c = W x_s - Y e, element by element, Y e summed from the
                 // group's stored outputs (internal domain); skip: leave out b*
                 auto corr_elem = [&](int r, int skip) -> V {

@@ -85,6 +85,8 @@ struct RaggedCall {
     long long inj_signal;      // global signal index (-1: none)
     long long inj_elem;
     int inj_part, inj_bit;
+    int inj_pass;              // -1 last pass, 0 single / column pass, 1 row pass
+    int inj_stage;             // -1 after the last radix stage
     int conj;                  // 1: inverse direction
     int unit_scale;            // 1: scale 1 (else 1 forward, 1/N inverse)
     int stats;

@@ -125,13 +125,20 @@ __device__ __forceinline__ void ragged_step(const RaggedCall& c, const RaggedDes
     // it does for kernel arguments); only the per-call part is built here
     const KArgs<float2>& ka = *(const KArgs<float2>*)&cl->args;
     const int final_pass = PL::KIND != kColPass;
-    KCall<float> kc;
+    KCall<float> kc{};
     kc.conj_in = PL::KIND == kRowPass ? 0 : c.conj;
     kc.conj_out = final_pass ? c.conj : 0;
     kc.scale = (final_pass && c.conj && !c.unit_scale) ? 1.0f / (float)ka.N : 1.0f;
     kc.counts = c.counts;
     kc.stats = c.stats;
-    kc.inj_signal = final_pass ? c.inj_signal : -1;
+    {
+        // pass 0: the single pass or the column pass; pass 1: the row pass
+        constexpr int kPass = PL::KIND == kRowPass ? 1 : 0;
+        constexpr int kPasses = PL::KIND == kSingle ? 1 : 2;
+        const int want = c.inj_pass < 0 ? kPasses - 1 : c.inj_pass;
+        kc.inj_signal = want == kPass ? c.inj_signal : -1;
+        kc.inj_stage = c.inj_stage < 0 ? (int)sizeof...(Rs) - 1 : c.inj_stage;
+    }
     kc.inj_elem = c.inj_elem;
     kc.inj_part = c.inj_part;
     kc.inj_bit = c.inj_bit;

@@ -78,9 +78,24 @@ def supported(N: int, dtype=torch.complex64) -> bool:
     return bool(_lib.load().tfft_supported(N, _precision(dtype)))
 
 
-def inject_arm(signal: int, element: int, part: int, bit: int, dtype=torch.complex64) -> None:
-    _lib.check(_lib.load().tfft_inject_arm(signal, element, part, bit, _precision(dtype)),
-               "tfft_inject_arm")
+def inject_arm(signal: int, element: int, part: int, bit: int, dtype=torch.complex64,
+               pass_: int = -1, stage: int = -1) -> None:
+    """Arm one bit flip for the next call (see tfft_inject_arm_desc): pass_
+    -1 last, 0 single / column pass, 1 row pass; stage -1 after the last
+    radix stage, else after radix stage `stage`."""
+    import ctypes
+    d = _lib.InjectDesc(signal=int(signal), element=int(element), part=int(part), bit=int(bit),
+                        precision=_precision(dtype), pass_=int(pass_), stage=int(stage), reserved=0)
+    _lib.check(_lib.load().tfft_inject_arm_desc(ctypes.byref(d)), "tfft_inject_arm_desc")
+
+
+def route_info(N: int, dtype=torch.complex64, ft_mode: int = 2) -> dict:
+    """The route a call takes now: passes, N1, N2, stages of each pass, T."""
+    import ctypes
+    buf = (ctypes.c_longlong * 6)()
+    _lib.check(_lib.load().tfft_route_info(N, _precision(dtype), ft_mode, buf, 6), f"tfft_route_info(N={N})")
+    keys = ("passes", "N1", "N2", "stages0", "stages1", "T")
+    return {k: int(buf[i]) for i, k in enumerate(keys)}
 
 
 def inject_disarm() -> None:

@@ -54,6 +54,17 @@ def test_invalid_arguments_rejected_on_host():
     assert lib.tfft_inject_arm(0, 0, 2, 3, 0) == _lib.TFFT_EINVAL
     assert lib.tfft_inject_arm(0, 0, 0, 63, 1) == _lib.TFFT_OK
     assert lib.tfft_inject_disarm() == _lib.TFFT_OK
+    d = _lib.InjectDesc(signal=0, element=0, part=0, bit=3, precision=0, pass_=2, stage=-1)
+    assert lib.tfft_inject_arm_desc(ctypes.byref(d)) == _lib.TFFT_EINVAL      # no third pass
+    d.pass_, d.stage = 0, -2
+    assert lib.tfft_inject_arm_desc(ctypes.byref(d)) == _lib.TFFT_EINVAL      # stage below -1
+    assert lib.tfft_inject_arm_desc(None) == _lib.TFFT_EINVAL
+    d.pass_, d.stage = 1, 0
+    assert lib.tfft_inject_arm_desc(ctypes.byref(d)) == _lib.TFFT_OK
+    # an armed flip that does not fit the call is refused before any device work:
+    # 256 points run as one pass, so pass 1 does not exist
+    assert c2c(dummy, dummy + (1 << 20), 256, 4, -1, 0, 0, 0.0, None, None) == _lib.TFFT_EINVAL
+    assert lib.tfft_inject_disarm() == _lib.TFFT_OK
     assert lib.tfft_set_tuning(64, 0, 33, 0.0) == _lib.TFFT_EINVAL
     assert lib.tfft_prepare(0, 0, 0, 0, None) == _lib.TFFT_EINVAL
     assert lib.tfft_prepare(256, -1, 0, 0, None) == _lib.TFFT_EINVAL
@@ -222,3 +233,14 @@ def test_shipped_tuning_table_is_complete_and_consistent():
         assert lib.tfft_load_tuning(_lib.TUNING_PATH.encode()) == len(doc["entries"])
     finally:
         lib.tfft_load_tuning(_lib.TUNING_PATH.encode())
+
+
+def test_route_info_matches_routes():
+    lib = _lib.load()
+    buf = (ctypes.c_longlong * 6)()
+    assert lib.tfft_route_info(256, 0, 2, buf, 6) == 0
+    assert buf[0] == 1 and buf[1] == 256 and buf[2] == 1 and buf[3] >= 1 and buf[4] == 0
+    assert lib.tfft_route_info(1 << 20, 0, 2, buf, 6) == 0
+    assert buf[0] == 2 and buf[1] * buf[2] == 1 << 20 and buf[3] >= 1 and buf[4] >= 1
+    assert lib.tfft_route_info(100, 0, 2, buf, 6) == _lib.TFFT_EUNSUPPORTED
+    assert lib.tfft_route_info(256, 0, 2, None, 6) == _lib.TFFT_EINVAL
