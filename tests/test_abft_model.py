@@ -286,3 +286,114 @@ def test_gradient_closed_form_vs_finite_differences_and_torch():
     lt = (torch.tensor(w) * torch.fft.fft(xt).abs() ** 2).sum()
     lt.backward()
     assert oracle.rel_l2(g, xt.grad.numpy()) < 1e-12
+
+
+# --- per-transaction detection with delayed batched correction (Sec. 4.1) ---
+
+def _group_with_faults(N, G, faults, seed):
+    """Inputs, exact transforms (numpy.fft) and outputs with additive faults
+    injected mid-transform (radix-2 DIT, stage and position per fault)."""
+    X = synth.signals(G, N, seed=seed, dtype=np.complex128)
+    Y = np.fft.fft(X)
+    Yf = Y.copy()
+    for b, stage, pos, eps in faults:
+        Yf[b] = dit_radix2_with_fault(X[b], stage, pos, eps)
+    return X, Y, Yf
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_per_transaction_clean_and_single_fault(precision):
+    N, G = 64, 8
+    X, Y, _ = _group_with_faults(N, G, [], seed=40)
+    r = am.abft_group_per_transaction(X, Y, precision)
+    assert r["faulty"] == [] and r["events"] == []
+    assert np.array_equal(r["Y"], Y)
+    lg = int(math.log2(N))
+    for bstar in range(G):
+        for stage in (0, lg // 2, lg):
+            eps = 0.3 - 0.1j
+            X, Y, Yf = _group_with_faults(N, G, [(bstar, stage, (3 * bstar + stage) % N, eps)], seed=41)
+            r = am.abft_group_per_transaction(X, Yf, precision)
+            # located exactly: the transaction whose own check failed
+            assert r["faulty"] == [bstar]
+            assert r["events"] == [(bstar, "corrected")]
+            # Eq. 5 with the sums of the whole group: the corrected output is the DFT
+            assert oracle.rel_l2(r["Y"], Y) < 1e-13
+
+
+def test_per_transaction_two_faults_sequential():
+    """Two faulty transactions in one group: the first is corrected when the
+    second appears, from the right-side sums of the transactions before the
+    second; the second at the end of the group.  Both end equal to the DFT,
+    where the group-level check (one sum for the whole group) cannot tell
+    them apart."""
+    N, G = 128, 8
+    for (b1, b2) in [(0, 7), (2, 3), (5, 6)]:
+        X, Y, Yf = _group_with_faults(N, G, [(b1, 2, 9, 0.2 + 0.05j), (b2, 5, 77, -0.4j)], seed=42)
+        r = am.abft_group_per_transaction(X, Yf, "fp64")
+        assert r["faulty"] == [b1, b2]
+        assert r["events"] == [(b1, "corrected"), (b2, "corrected")]
+        assert oracle.rel_l2(r["Y"], Y) < 1e-13
+        # one group sum holds both faults: whatever the group-level check
+        # decides, it cannot restore both signals
+        rg = am.abft_group(X, Yf, "fp64")
+        assert rg["action"] == "uncorrectable" or oracle.rel_l2(rg["Y"], Y) > 1e-6
+
+
+def test_per_transaction_non_finite_then_finite_fault():
+    N, G = 64, 6
+    X, Y, Yf = _group_with_faults(N, G, [(4, 3, 10, 0.5)], seed=43)
+    Yf[1, 7] = complex(np.inf, 0.0)
+    r = am.abft_group_per_transaction(X, Yf, "fp32")
+    assert r["faulty"] == [1, 4]
+    assert r["events"] == [(1, "rebuilt"), (4, "corrected")]
+    assert oracle.rel_l2(r["Y"], Y) < 1e-12
+
+
+def test_per_transaction_threshold_is_per_signal():
+    """A fault in a weak signal of a strong group: above that signal's own
+    threshold (so the per-transaction check finds it), below the threshold
+    of the group's energy (so the group-level check cannot)."""
+    N, G, kappa = 256, 8, 8.0
+    X = synth.signals(G, N, seed=44, dtype=np.complex128)
+    X[3] *= 1e-4
+    Y = np.fft.fft(X)
+    nu3 = float(np.sum(np.abs(X[3]) ** 2))
+    nu = float(np.sum(np.abs(X) ** 2))
+    tau3 = am.threshold(N, nu3, "fp32", kappa)
+    tau_g = am.threshold(N, nu, "fp32", kappa)
+    assert 20 * tau3 < tau_g
+    Yf = Y.copy()
+    Yf[3, 40] += 10 * tau3      # |e_k| = 1: D0 moves by exactly this much
+    r = am.abft_group_per_transaction(X, Yf, "fp32", kappa=kappa)
+    assert r["faulty"] == [3] and r["events"] == [(3, "corrected")]
+    # the correction comes from sums over the whole group, 10^4 times the
+    # weak signal: its rounding is u times that ratio
+    assert oracle.rel_l2(r["Y"][3], Y[3]) < 1e-10
+    assert am.abft_group(X, Yf, "fp32", kappa=kappa)["action"] == "clean"
+
+
+def test_per_transaction_fp32_bit_flips_keep_each_signal_within_tolerance():
+    """fp32 outputs as stored, every bit of one value per case, groups of
+    G = 8: with each transaction checked against its own threshold, an
+    undetected flip is at most tau_b / |e_k| = tau_b, a relative
+    kappa u sqrt(log2 N) of its signal, independent of G -- so, unlike the
+    group-level check, the group size is not bounded by the tolerance."""
+    N, G, kappa, tol = 1024, 8, 8.0, 2e-6
+    X = synth.signals(G, N, seed=45, dtype=np.complex64).astype(np.complex128)
+    Y = np.fft.fft(X).astype(np.complex64).astype(np.complex128)
+    worst_clean = 0.0
+    for bit in range(31):
+        for part in (0, 1):
+            b, k = (bit + part) % G, (11 * bit + part) % N
+            Yf = Y.copy()
+            Yf[b, k] = am.flip_bit(complex(Y[b, k]), part, bit, "fp32")
+            r = am.abft_group_per_transaction(X, Yf, "fp32", kappa=kappa)
+            err = oracle.rel_l2(r["Y"][b], Y[b])
+            assert err < tol, (bit, part, r["events"], err)
+            if not r["faulty"]:
+                assert abs(Yf[b, k] - Y[b, k]) <= r["tau"][b]
+                worst_clean = max(worst_clean, err)
+            else:
+                assert r["faulty"] == [b] and r["events"][0][1] in ("corrected", "rebuilt")
+    assert worst_clean < tol
