@@ -43,7 +43,9 @@ typedef enum {
     TFFT_EALIGN = -3,       /* x or y not aligned to the element size */
     TFFT_EHIP = -4,         /* HIP runtime error, see tfft_last_hip_error() */
     TFFT_ENOMEM = -5,       /* table allocation failed */
-    TFFT_ECAPTURE = -6      /* would allocate during stream capture */
+    TFFT_ECAPTURE = -6,     /* would allocate during stream capture */
+    TFFT_ENOTPREPARED = -7, /* tfft_c2c_noalloc: tables of the length not built yet */
+    TFFT_ESCRATCH = -8      /* tfft_c2c_noalloc: one signal exceeds the scratch buffer */
 } tfft_status;
 
 enum { TFFT_FORWARD = -1, TFFT_INVERSE = +1 };       /* sign of the exponent */
@@ -79,6 +81,30 @@ typedef struct {
  * (tfft_supported()).  batch = 0 is a no-op. */
 int tfft_c2c(const void* x, void* y, long long N, long long batch, int dir, int precision,
              int ft_mode, double scale, tfft_ft_counts* counts, void* hip_stream);
+
+/* Size of the static device scratch buffer of tfft_c2c_noalloc (bytes). */
+#define TFFT_NOALLOC_SCRATCH_BYTES (64ull << 20)
+
+/* For callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * transform, arguments, results and errors as tfft_c2c, but the call never
+ * allocates.  The intermediate of a two-pass length lives in a static device
+ * array of TFFT_NOALLOC_SCRATCH_BYTES (64 MiB) per device, held from the
+ * first call on that device until the process ends; the transform runs over
+ * chunks of signals that fit it.  Limits and errors, beyond tfft_c2c's:
+ *   - TFFT_ESCRATCH when one signal (N * 8 bytes in fp32, N * 16 in fp64)
+ *     is larger than the scratch buffer; any batch is accepted;
+ *   - TFFT_ENOTPREPARED when the tables of (N, precision, ft_mode) were not
+ *     built beforehand: call tfft_prepare(N, 0, precision, ft_mode, NULL)
+ *     once first (that call allocates);
+ *   - launches are never timed by tfft_profile.
+ * Every call on one device shares that device's scratch array, whose
+ * contents persist between calls (each call writes the intermediate before
+ * reading it, so nothing needs clearing); calls that overlap in time on one
+ * device (different streams, or host threads) race on it and must be ordered
+ * by the caller. */
+int tfft_c2c_noalloc(const void* x, void* y, long long N, long long batch, int dir, int precision,
+                     int ft_mode, double scale, tfft_ft_counts* counts, void* hip_stream);
 
 /* Build (and cache) the tables of length N for ABFT mode ft_mode and, when
  * batch > 0 and N runs as two passes, reserve the two-pass workspace that

@@ -19,6 +19,9 @@ TFFT_EALIGN = -3
 TFFT_EHIP = -4
 TFFT_ENOMEM = -5
 TFFT_ECAPTURE = -6
+TFFT_ENOTPREPARED = -7
+TFFT_ESCRATCH = -8
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 FORWARD = -1
 INVERSE = +1
@@ -35,6 +38,7 @@ _I = ctypes.c_int
 _D = ctypes.c_double
 SIGNATURES = {
     "tfft_c2c": ([_VP, _VP, _LL, _LL, _I, _I, _I, _D, _VP, _VP], _I),
+    "tfft_c2c_noalloc": ([_VP, _VP, _LL, _LL, _I, _I, _I, _D, _VP, _VP], _I),
     "tfft_c2c_ragged": ([_VP, _VP, _VP, _I, _I, _I, _I, _VP, _VP], _I),
     "tfft_prepare": ([_LL, _LL, _I, _I, _VP], _I),
     "tfft_ragged_supported": ([_LL, _I], _I),

@@ -27,6 +27,11 @@
 
 using namespace tfft;
 
+// Intermediate of two-pass transforms made through tfft_c2c_noalloc: one copy
+// per device, held from the first such call on that device until the process
+// ends, shared by every such call on that device.
+static __device__ __align__(256) unsigned char scratch[TFFT_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 thread_local int g_last_hip = 0;
@@ -409,11 +414,11 @@ void fill_common(KArgs<V>& a, const KernelEntry& e, const SubTables& st, const T
 }
 
 template <class V> int run(const KernelEntry& e, const void* x, void* y, const KArgs<V>& a,
-                           long long grid, hipStream_t stream) {
+                           long long grid, hipStream_t stream, bool timed = true) {
     if (grid <= 0) return TFFT_OK;
     if (grid > 0x7fffffffLL) return TFFT_EUNSUPPORTED;
     LaunchRec rec{};
-    const bool prof = g_prof && !capturing(stream) && prof_selected(e);
+    const bool prof = timed && g_prof && !capturing(stream) && prof_selected(e);
     if (prof) {
         rec.e = &e;
         rec.bytes = 2.0 * (double)a.batch * (double)a.N * (double)sizeof(V);
@@ -429,10 +434,19 @@ template <class V> int run(const KernelEntry& e, const void* x, void* y, const K
     return err == hipSuccess ? TFFT_OK : hip_fail(err);
 }
 
+// Where a two-pass transform keeps its intermediate: the library workspace of
+// (device, stream), or a fixed caller-side buffer of `cap` bytes (the
+// no-allocation entry point), in which case chunks shrink to fit it and no
+// launch is timed.
+struct WsSource {
+    void* fixed = nullptr;
+    size_t cap = 0;
+};
+
 template <class V>
 int transform(const Route& rt, const void* x, void* y, long long N, long long batch, int dir,
               double scale, tfft_ft_counts* counts, const Tuning& tu, const Inject& inj,
-              hipStream_t stream, bool may_alloc) {
+              hipStream_t stream, bool may_alloc, const WsSource& wsrc = WsSource{}) {
     using R = typename RealOf<V>::type;
     const int precision = sizeof(R) == 4 ? TFFT_FP32 : TFFT_FP64;
     const int conj = dir == TFFT_INVERSE ? 1 : 0;
@@ -450,7 +464,8 @@ int transform(const Route& rt, const void* x, void* y, long long N, long long ba
         a.x_intact = x != y ? 1 : 0;
         arm_launch(a, inj, 0, 1, rt.single->n_stages);
         const long long per_block = (long long)rt.single->slots_per_block * tu.T;
-        return run<V>(*rt.single, x, y, a, (batch + per_block - 1) / per_block, stream);
+        return run<V>(*rt.single, x, y, a, (batch + per_block - 1) / per_block, stream,
+                      wsrc.fixed == nullptr);
     }
     // two passes over chunks of signals
     SubTables *sa = nullptr, *sb = nullptr;
@@ -460,10 +475,17 @@ int transform(const Route& rt, const void* x, void* y, long long N, long long ba
     if (rc == TFFT_OK) rc = get_pass(precision, N, may_alloc, &pt);
     if (rc != TFFT_OK) return rc;
     const size_t sig_bytes = (size_t)N * sizeof(V);
-    const long long chunk = chunk_signals(N, batch, sizeof(V), tu);
+    long long chunk = chunk_signals(N, batch, sizeof(V), tu);
     void* ws = nullptr;
-    rc = get_workspace((size_t)chunk * sig_bytes, stream, may_alloc, &ws);
-    if (rc != TFFT_OK) return rc;
+    const bool timed = wsrc.fixed == nullptr;
+    if (wsrc.fixed) {
+        if (sig_bytes > wsrc.cap) return TFFT_ESCRATCH;
+        chunk = std::min(chunk, (long long)(wsrc.cap / sig_bytes));
+        ws = wsrc.fixed;
+    } else {
+        rc = get_workspace((size_t)chunk * sig_bytes, stream, may_alloc, &ws);
+        if (rc != TFFT_OK) return rc;
+    }
 
     KArgs<V> A{}, B{};
     fill_common(A, *rt.col, *sa, tu, counts);
@@ -493,9 +515,9 @@ int transform(const Route& rt, const void* x, void* y, long long N, long long ba
         arm_launch(B, inj, 1, 2, rt.row->n_stages);
         if (!(inj.signal >= c0 && inj.signal < c0 + cnt)) A.inj_signal = B.inj_signal = -1;
         const long long groups = (cnt + tu.T - 1) / tu.T;
-        rc = run<V>(*rt.col, xb + (size_t)c0 * sig_bytes, ws, A, groups * A.tiles, stream);
+        rc = run<V>(*rt.col, xb + (size_t)c0 * sig_bytes, ws, A, groups * A.tiles, stream, timed);
         if (rc != TFFT_OK) return rc;
-        rc = run<V>(*rt.row, ws, yb + (size_t)c0 * sig_bytes, B, groups * B.tiles, stream);
+        rc = run<V>(*rt.row, ws, yb + (size_t)c0 * sig_bytes, B, groups * B.tiles, stream, timed);
         if (rc != TFFT_OK) return rc;
     }
     return TFFT_OK;
@@ -1063,6 +1085,8 @@ const char* tfft_strerror(int status) {
         case TFFT_EHIP: return "HIP runtime error";
         case TFFT_ENOMEM: return "out of device memory";
         case TFFT_ECAPTURE: return "allocation needed during stream capture";
+        case TFFT_ENOTPREPARED: return "tables not built: call tfft_prepare for this length first";
+        case TFFT_ESCRATCH: return "one signal exceeds the no-allocation scratch buffer (64 MiB)";
         default: return "unknown status";
     }
 }
@@ -1368,8 +1392,34 @@ int tfft_inject_disarm(void) {
     return TFFT_OK;
 }
 
-int tfft_c2c(const void* x, void* y, long long N, long long batch, int dir, int precision,
-             int ft_mode, double scale, tfft_ft_counts* counts, void* hip_stream) {
+}  // extern "C"
+
+namespace {
+
+// Device address of `scratch` on each device, resolved once per device with
+// that device current (the array's name in host code is only a stand-in for
+// the symbol, not a device address).  Caller holds g_mu.
+constexpr int kMaxDevices = 64;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_for_device(int dev, void** out) {
+    if (dev < 0 || dev >= kMaxDevices) return TFFT_EUNSUPPORTED;
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol);
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return TFFT_OK;
+}
+
+// Argument checks and dispatch shared by tfft_c2c and tfft_c2c_noalloc.
+// noalloc: the intermediate of a two-pass length goes to the device's
+// scratch array, nothing is allocated (missing tables are reported, not
+// built) and no launch is timed.
+int c2c_impl(const void* x, void* y, long long N, long long batch, int dir, int precision,
+             int ft_mode, double scale, tfft_ft_counts* counts, void* hip_stream, bool noalloc) {
     if (N < 1 || batch < 0) return TFFT_EINVAL;
     if (dir != TFFT_FORWARD && dir != TFFT_INVERSE) return TFFT_EINVAL;
     if (check_precision(precision) != TFFT_OK) return TFFT_EINVAL;
@@ -1385,6 +1435,8 @@ int tfft_c2c(const void* x, void* y, long long N, long long batch, int dir, int 
     const char* yb = static_cast<const char*>(y);
     const size_t bytes = (size_t)N * (size_t)batch * S;
     if (xb != yb && xb < yb + bytes && yb < xb + bytes) return TFFT_EINVAL;
+    // one signal of a two-pass length must fit the scratch array
+    if (noalloc && (size_t)N > TFFT_NOALLOC_SCRATCH_BYTES / S) return TFFT_ESCRATCH;
     if (scale == 0.0) scale = dir == TFFT_INVERSE ? 1.0 / (double)N : 1.0;
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
 
@@ -1402,14 +1454,35 @@ int tfft_c2c(const void* x, void* y, long long N, long long batch, int dir, int 
     if (inj.armed && (inj.precision != precision || inj.signal >= batch || inj.element >= N ||
                       !inject_fits(inj, rt.single ? rt.single : rt.col, rt.single ? nullptr : rt.row)))
         return TFFT_EINVAL;
-    const bool may_alloc = !capturing(stream);
+    WsSource wsrc;
+    if (noalloc) {
+        int rc = scratch_for_device(current_device(), &wsrc.fixed);
+        if (rc != TFFT_OK) return rc;
+        wsrc.cap = TFFT_NOALLOC_SCRATCH_BYTES;
+    }
+    const bool may_alloc = !noalloc && !capturing(stream);
     int rc;
     if (precision == TFFT_FP32)
-        rc = transform<float2>(rt, x, y, N, batch, dir, scale, counts, tu, inj, stream, may_alloc);
+        rc = transform<float2>(rt, x, y, N, batch, dir, scale, counts, tu, inj, stream, may_alloc, wsrc);
     else
-        rc = transform<double2>(rt, x, y, N, batch, dir, scale, counts, tu, inj, stream, may_alloc);
+        rc = transform<double2>(rt, x, y, N, batch, dir, scale, counts, tu, inj, stream, may_alloc, wsrc);
+    if (rc == TFFT_ECAPTURE && wsrc.fixed) rc = TFFT_ENOTPREPARED;
     if (rc == TFFT_OK) g_inj = Inject{};   // one-shot
     return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tfft_c2c(const void* x, void* y, long long N, long long batch, int dir, int precision,
+             int ft_mode, double scale, tfft_ft_counts* counts, void* hip_stream) {
+    return c2c_impl(x, y, N, batch, dir, precision, ft_mode, scale, counts, hip_stream, false);
+}
+
+int tfft_c2c_noalloc(const void* x, void* y, long long N, long long batch, int dir, int precision,
+                     int ft_mode, double scale, tfft_ft_counts* counts, void* hip_stream) {
+    return c2c_impl(x, y, N, batch, dir, precision, ft_mode, scale, counts, hip_stream, true);
 }
 
 int tfft_ragged_supported(long long N, int precision) {

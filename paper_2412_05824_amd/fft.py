@@ -63,6 +63,30 @@ def fft_c2c(x: torch.Tensor, dir: int = -1, ft_mode: int = 2, out: torch.Tensor 
     return out, counts
 
 
+def fft_c2c_noalloc(x: torch.Tensor, out: torch.Tensor, dir: int = -1, ft_mode: int = 2,
+                    counts: torch.Tensor | None = None, scale: float = 0.0):
+    """tfft_c2c_noalloc: the transform of fft_c2c without any device
+    allocation (two-pass intermediates in the library's static scratch
+    array).  out, and counts unless ft_mode is FT_OFF, are supplied by the
+    caller; the tables of the length must have been built by prepare()."""
+    if not (x.is_cuda and out.is_cuda):
+        raise ValueError("x and out must be device tensors")
+    if x.dim() != 2 or not x.is_contiguous():
+        raise ValueError("x must be a contiguous [batch, N] tensor")
+    if out.shape != x.shape or out.dtype != x.dtype or not out.is_contiguous() or out.device != x.device:
+        raise ValueError("out must match x in shape, dtype, device and be contiguous")
+    if ft_mode != _lib.FT_OFF and counts is None:
+        raise ValueError("counts is required unless ft_mode is FT_OFF")
+    prec = _precision(x.dtype)
+    batch, N = x.shape
+    cptr = counts.data_ptr() if counts is not None else None
+    with torch.cuda.device(x.device):
+        st = _lib.load().tfft_c2c_noalloc(x.data_ptr(), out.data_ptr(), N, batch, dir, prec, ft_mode,
+                                          float(scale), cptr, _stream_ptr(x.device))
+    _lib.check(st, f"tfft_c2c_noalloc(N={N}, batch={batch}, dir={dir}, ft={ft_mode})")
+    return out, counts
+
+
 def prepare(N: int, dtype=torch.complex64, ft_mode: int = 2, batch: int = 0, device=None) -> None:
     """Build the tables of length N and, for batch > 0, reserve the two-pass
     workspace for up to `batch` signals on torch's current stream (call

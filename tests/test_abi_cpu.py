@@ -30,7 +30,8 @@ def test_every_declared_symbol_is_exported_and_bound():
 
 def test_strerror_and_status_codes():
     for st in (_lib.TFFT_OK, _lib.TFFT_EINVAL, _lib.TFFT_EUNSUPPORTED, _lib.TFFT_EALIGN,
-               _lib.TFFT_EHIP, _lib.TFFT_ENOMEM, _lib.TFFT_ECAPTURE):
+               _lib.TFFT_EHIP, _lib.TFFT_ENOMEM, _lib.TFFT_ECAPTURE, _lib.TFFT_ENOTPREPARED,
+               _lib.TFFT_ESCRATCH):
         assert _lib.strerror(st) and _lib.strerror(st) != "unknown status"
     assert _lib.strerror(-99) == "unknown status"
 
@@ -244,3 +245,22 @@ def test_route_info_matches_routes():
     assert buf[0] == 2 and buf[1] * buf[2] == 1 << 20 and buf[3] >= 1 and buf[4] >= 1
     assert lib.tfft_route_info(100, 0, 2, buf, 6) == _lib.TFFT_EUNSUPPORTED
     assert lib.tfft_route_info(256, 0, 2, None, 6) == _lib.TFFT_EINVAL
+
+
+def test_noalloc_validates_on_host():
+    """tfft_c2c_noalloc rejects what tfft_c2c rejects, and a signal larger
+    than its scratch array, before touching the device."""
+    lib = _lib.load()
+    f = lib.tfft_c2c_noalloc
+    dummy = 4096  # never dereferenced: validation fails first
+    assert f(dummy, dummy, 0, 4, -1, 0, 0, 0.0, None, None) == _lib.TFFT_EINVAL
+    assert f(dummy, dummy, 64, 4, 0, 0, 0, 0.0, None, None) == _lib.TFFT_EINVAL
+    assert f(dummy, dummy, 100, 4, -1, 0, 0, 0.0, None, None) == _lib.TFFT_EUNSUPPORTED
+    assert f(dummy, dummy, 64, 0, -1, 0, 0, 0.0, None, None) == _lib.TFFT_OK
+    assert f(dummy, dummy, 64, 4, -1, 0, 2, 0.0, None, None) == _lib.TFFT_EINVAL
+    assert f(dummy + 4, dummy + 4, 64, 4, -1, 0, 0, 0.0, None, None) == _lib.TFFT_EALIGN
+    big = 1 << 40
+    # 2^24 complex64 = 128 MiB per signal, 2^23 complex128 = 128 MiB: above 64 MiB
+    assert _lib.NOALLOC_SCRATCH_BYTES == 64 << 20
+    assert f(dummy, big, 1 << 24, 1, -1, 0, 0, 0.0, None, None) == _lib.TFFT_ESCRATCH
+    assert f(dummy, big, 1 << 23, 1, -1, 1, 0, 0.0, None, None) == _lib.TFFT_ESCRATCH
