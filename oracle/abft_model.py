@@ -183,7 +183,10 @@ def abft_group_per_transaction(X, Yp, precision: str = "fp32", kappa: float = 32
     fault appears or the group ends, from the sums accumulated so far:
     c = W x_s - y_s (= minus its fault, Eq. 5), y_b += c and y_s += c, or,
     when c is not finite or larger than one signal's rms output norm, a
-    rebuild y_b = W x_s - (sum of the other outputs in the sums).
+    rebuild y_b = W x_s - (sum of the other outputs in the sums).  An
+    additive correction is accepted when |e^T c + D0_b| stays within the
+    threshold of the summed transactions' energy (the rounding of c comes
+    from all of them; in exact arithmetic e^T c = -D0_b).
 
     X, Yp: [G, N] inputs and unscaled outputs as produced.  Returns a dict:
     "Y" the repaired outputs, "events" a list of (b, action) with action in
@@ -216,7 +219,10 @@ def abft_group_per_transaction(X, Yp, precision: str = "fp32", kappa: float = 32
             small = (not nonfinite) and bool(np.all(np.isfinite(c))) and float(np.max(np.abs(c))) <= y_rms
         if small:
             Y[b] = Y[b] + c
-            ok = abs(np.dot(e, c) + d) <= tau
+            # c carries the rounding of every signal in the sums, so the
+            # check that it explains the discrepancy uses their energy
+            tau_v = threshold(N, nu_s, precision, kappa)
+            ok = abs(np.dot(e, c) + d) <= tau_v
             events.append((b, "corrected" if ok else "uncorrectable"))
         else:
             Y[b] = Wxs - y_others
