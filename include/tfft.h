@@ -226,7 +226,11 @@ int tfft_supported(long long N, int precision);
  * field out of range. */
 typedef struct {
     long long signal, element;
-    int part, bit, precision, pass, stage, reserved;
+    int part, bit, precision, pass, stage;
+    int two;            /* 1: flip the same value of signal2 as well (two faults
+                           in one call; signal2 != signal, and in a ragged
+                           batch of the same length); 0: one fault */
+    long long signal2;
 } tfft_inject_desc;
 int tfft_inject_arm_desc(const tfft_inject_desc* desc);
 
@@ -238,6 +242,22 @@ int tfft_inject_disarm(void);
  * (1..32) and the detection threshold factor kappa (> 0); pass 0 to keep a
  * value.  Used by the autotuner and by tests. */
 int tfft_set_tuning(long long N, int precision, int T, double kappa);
+
+/* Detection granularity for (N, precision) in every ABFT mode.
+ *   0  once per group of T transactions (Sec. 4.3 multi-transaction
+ *      threadblock ABFT): one reduction of D0 = sum_b (q_b - p_b) and of the
+ *      location code D1 = sum_b (b+1)(q_b - p_b) per group, threshold from
+ *      the group's input energy, faulty signal b* = D1/D0 - 1;
+ *   1  per transaction (Sec. 4.1, delayed batched correction): each
+ *      signal's q_b - p_b is checked against a threshold from its own input
+ *      energy; a faulty signal is noted and repaired at the end of the group
+ *      from the right-side sums of the transactions before the next faulty
+ *      one (or of the whole group), oldest first.  A group then holds at most
+ *      as many transactions as the plan's lanes per slot and wave (up to 16);
+ *      a larger T is reduced to that.
+ * Defaults: 1 for TFFT_FP32 (a per-signal threshold keeps an undetected
+ * flip below the fp32 tolerance at any T), 0 for TFFT_FP64. */
+int tfft_set_granularity(long long N, int precision, int gran);
 int tfft_get_tuning(long long N, int precision, int* T, double* kappa);
 
 /* Lengths above the single-pass limit run as a column pass and a row pass
@@ -266,7 +286,9 @@ int tfft_routes(long long N, int precision, int ft_mode, long long* codes, int c
  * [0] passes (1 or 2), [1] N1 (column-pass length; N for a single pass),
  * [2] N2 (row-pass length; 1 for a single pass), [3] radix stages of pass 0,
  * [4] radix stages of pass 1 (0 for a single pass), [5] transactions per
- * checksum group T.  TFFT_EUNSUPPORTED for a length without a route. */
+ * checksum group T as launched, [6] detection granularity as launched (see
+ * tfft_set_granularity; 0 without ABFT).  TFFT_EUNSUPPORTED for a length
+ * without a route. */
 int tfft_route_info(long long N, int precision, int ft_mode, long long* info, int n);
 int tfft_set_route(long long N, int precision, long long code);
 int tfft_get_route(long long N, int precision, int ft_mode, long long* code);

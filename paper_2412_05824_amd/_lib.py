@@ -53,6 +53,7 @@ SIGNATURES = {
     "tfft_route_info": ([_LL, _I, _I, ctypes.POINTER(_LL), _I], _I),
     "tfft_inject_disarm": ([], _I),
     "tfft_set_tuning": ([_LL, _I, _I, _D], _I),
+    "tfft_set_granularity": ([_LL, _I, _I], _I),
     "tfft_get_tuning": ([_LL, _I, ctypes.POINTER(_I), ctypes.POINTER(_D)], _I),
     "tfft_calibration": ([_I], _I),
     "tfft_profile": ([_I], _I),
@@ -71,7 +72,7 @@ SIGNATURES = {
 class InjectDesc(ctypes.Structure):
     """tfft_inject_desc of include/tfft.h."""
     _fields_ = [("signal", _LL), ("element", _LL), ("part", _I), ("bit", _I),
-                ("precision", _I), ("pass_", _I), ("stage", _I), ("reserved", _I)]
+                ("precision", _I), ("pass_", _I), ("stage", _I), ("two", _I), ("signal2", _LL)]
 
 
 class TfftError(RuntimeError):

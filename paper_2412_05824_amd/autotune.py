@@ -6,8 +6,10 @@ Per (precision, N) it sweeps, with ABFT correction on:
   * the route: single pass (when built) or each column/row split n1 x N/n1
     (the multi-pass decomposition of Sec. 3.1), over the compiled plan
     variants (tile width, elements per lane) of each pass;
-  * T, the transactions per checksum group (Sec. 4.3), limited by the
-    accuracy bound below;
+  * the detection granularity: once per group of T transactions with the
+    location code (Sec. 4.3), or per transaction with delayed batched
+    correction (Sec. 4.1), and T, the transactions per group, limited by
+    the accuracy bounds below;
   * for two-pass routes, the chunk of signals whose intermediate lives in
     the workspace;
 then, without ABFT, T and the chunk again on the same route (a shared plan
@@ -17,10 +19,15 @@ fault-free data and agree with the default configuration's output to
 within twice the precision's tolerance (two correct transforms differ by at
 most the sum of their errors).
 
-Accuracy bound on T: a flip just below the detection threshold changes one
-signal by about kappa * u * sqrt(T * log2 Ns) of its norm (Ns the longest
-pass), which must stay under the acceptance tolerance (2e-6 fp32, 1e-13
-fp64), so T <= (tol / (kappa * u))^2 / log2 Ns.
+Accuracy bounds on T.  Checked once per group, a flip just below the
+detection threshold changes one signal by about kappa * u * sqrt(T * log2 Ns)
+of its norm (Ns the longest pass), which must stay under the acceptance
+tolerance (2e-6 fp32, 1e-13 fp64), so T <= (tol / (kappa * u))^2 / log2 Ns.
+Checked per transaction, each signal has its own threshold; T then only sets
+how many signals share the right-side sums of a correction, whose rounding
+(about u * sqrt(T * log2 Ns) of one signal's norm) stays far below the
+tolerance up to T = 16, the most a plan keeps; the library reduces a larger
+T to what the plan keeps, and the tuner skips such duplicates.
 
     python -m paper_2412_05824_amd.autotune --out paper_2412_05824_amd/tuning/mi355x.json
 """
@@ -37,6 +44,7 @@ TOL = {"fp32": 2e-6, "fp64": 1e-13}
 UNIT = {"fp32": 2.0 ** -24, "fp64": 2.0 ** -53}
 KAPPA = {"fp32": 8.0, "fp64": 16.0}
 T_CHOICES = (1, 2, 4, 8, 16)
+GRANS = {"fp32": (1, 0), "fp64": (0, 1)}   # per transaction, per group
 CHUNKS_MIB = (16, 32, 64, 128, 256, 512)
 
 
@@ -86,6 +94,7 @@ def tune(precisions, logs, modes=(2, 0), reps=5, warmup=2, total_bytes=1 << 30, 
                 continue
             xv, yv, rv = x.view(-1, N), y.view(-1, N), ref.view(-1, N)
             T0, k0 = tf.get_tuning(N, dtype)
+            gran0 = tf.route_info(N, dtype, 2)["gran"]
             tf.set_route(N, dtype, 0)
             tf.fft_c2c(xv, ft_mode=tf.FT_OFF, out=rv)
             torch.cuda.synchronize()
@@ -100,12 +109,25 @@ def tune(precisions, logs, modes=(2, 0), reps=5, warmup=2, total_bytes=1 << 30, 
                 for code in codes:
                     n1, va, vb = tf.route_parts(code)
                     longest = N if n1 == 1 else max(n1, N // n1)
-                    # without ABFT, T only sets the signals per workgroup
-                    tmax = max_T(prec, longest, KAPPA[prec]) if ft else 4
                     chunks = [None] if n1 == 1 else [c << 20 for c in CHUNKS_MIB]
-                    for T in [t for t in T_CHOICES if t <= tmax]:
+                    cands = []
+                    for gran in (GRANS[prec] if ft else (0,)):
+                        # without ABFT, T only sets the signals per workgroup
+                        tmax = 4 if not ft else (16 if gran else max_T(prec, longest, KAPPA[prec]))
+                        seen = set()
+                        for T in [t for t in T_CHOICES if t <= tmax]:
+                            tf.set_route(N, dtype, code)
+                            tf.set_granularity(N, dtype, gran)
+                            tf.set_tuning(N, dtype, T, KAPPA[prec])
+                            teff = tf.route_info(N, dtype, ft)["T"]
+                            if teff in seen:
+                                continue   # reduced to a T already measured
+                            seen.add(teff)
+                            cands.append((gran, T))
+                    for gran, T in cands:
                         for chunk in chunks:
                             tf.set_route(N, dtype, code)
+                            tf.set_granularity(N, dtype, gran)
                             tf.set_tuning(N, dtype, T, KAPPA[prec])
                             if chunk:
                                 tf.set_chunk(N, dtype, chunk)
@@ -116,11 +138,12 @@ def tune(precisions, logs, modes=(2, 0), reps=5, warmup=2, total_bytes=1 << 30, 
                             err = torch.linalg.vector_norm(yv - rv).item() / ref_norm
                             ok = det == 0 and err <= 2 * TOL[prec]
                             gbs = 2 * total * esize / (ms * 1e-3) / 1e9
-                            log(f"{prec} N={N} ft={ft} n1={n1} v={va}/{vb} T={T} chunk={chunk} {ms:.4f} ms "
+                            log(f"{prec} N={N} ft={ft} n1={n1} v={va}/{vb} gran={gran} T={T} chunk={chunk} {ms:.4f} ms "
                                 f"{gbs:.1f} GB/s err={err:.2e} det={det}{'' if ok else ' REJECTED'}")
                             if ok and (best is None or ms < best["ms"]):
                                 best = {"precision": prec, "N": N, "ft_mode": ft, "split_n1": n1,
-                                        "variant_a": va, "variant_b": vb, "T": T, "kappa": KAPPA[prec],
+                                        "variant_a": va, "variant_b": vb, "T": T, "gran": gran,
+                                        "kappa": KAPPA[prec],
                                         "ms": round(ms, 5), "gbs": round(gbs, 1)}
                                 if chunk:
                                     best["chunk_bytes"] = chunk
@@ -132,6 +155,7 @@ def tune(precisions, logs, modes=(2, 0), reps=5, warmup=2, total_bytes=1 << 30, 
                 # back to the defaults before the next mode / length
                 tf.set_route(N, dtype, 0)
                 tf.set_tuning(N, dtype, T0, k0)
+                tf.set_granularity(N, dtype, gran0)
                 tf.set_chunk(N, dtype, 128 << 20)
         del x, y, ref
         torch.cuda.empty_cache()

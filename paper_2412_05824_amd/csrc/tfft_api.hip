@@ -77,6 +77,7 @@ struct Tuning {
     double kappa;
     long long chunk_bytes;
     long long route;      // route code (see route_for): 0 the default policy
+    int gran;             // 0 detection once per group (location code), 1 per transaction
 };
 
 std::mutex g_mu;
@@ -98,6 +99,7 @@ std::map<std::tuple<int, long long, int>, Tuning> g_tuning;   // (prec, N, ft mo
 struct Inject {
     bool armed = false;
     long long signal = -1, element = 0;
+    long long signal2 = -1;   // a second signal hit the same way (-1: none)
     int part = 0, bit = 0, precision = 0;
     int pass = -1;    // -1 last pass, 0 first (single or column pass), 1 row pass
     int stage = -1;   // -1 after the last radix stage, else after stage `stage`
@@ -107,10 +109,12 @@ struct Inject {
 // route with `passes` passes, of a plan with `stages` radix stages
 template <class R> void arm_launch(KCall<R>& k, const Inject& inj, int pass, int passes, int stages) {
     k.inj_signal = -1;
+    k.inj_signal2 = -1;
     if (!inj.armed) return;
     const int want = inj.pass < 0 ? passes - 1 : inj.pass;
     if (want != pass) return;
     k.inj_signal = inj.signal;
+    k.inj_signal2 = inj.signal2;
     k.inj_elem = inj.element;
     k.inj_part = inj.part;
     k.inj_bit = inj.bit;
@@ -224,19 +228,41 @@ bool route_for(int precision, long long N, int ft, Route* r, long long code = 0)
 }
 
 Tuning default_tuning(int precision, long long N) {
-    // Groups of T signals share one checksum reduction (Sec. 4.3).  In fp32 an
-    // undetected flip just under the threshold perturbs one signal by about
-    // kappa * u * sqrt(T log2 Ns) of its norm, so T stays small to keep that
-    // under the 2e-6 relative tolerance; fp64 has ample margin.
+    // Groups of T signals share one checksum reduction (Sec. 4.3).  Checked
+    // once per group, an undetected flip just under the group's threshold
+    // perturbs one signal by about kappa * u * sqrt(T log2 Ns) of its norm,
+    // which in fp32 exceeds the 2e-6 tolerance unless T is 1 or 2; checked
+    // per transaction (Sec. 4.1), each signal has its own threshold and T
+    // only sets how many transactions share the right-side sums.  fp32
+    // therefore checks per transaction, fp64 (ample margin) per group with
+    // the location code.
+    (void)N;
     Tuning t{};
     t.chunk_bytes = 128ll << 20;
     t.route = 0;
     if (precision == TFFT_FP32) {
         t.kappa = 8.0;
-        t.T = N <= 128 ? 2 : 1;
+        t.T = 4;
+        t.gran = 1;
     } else {
         t.kappa = 16.0;
         t.T = 8;
+        t.gran = 0;
+    }
+    return t;
+}
+
+// The tuning a launch of plans pa (and pb, the row pass) really uses: no
+// granularity without ABFT, and per-transaction checking limited to the
+// transactions whose partials a plan keeps (the same T for both passes, so
+// their signal groups coincide).
+Tuning effective(const Tuning& tu, int ft, const KernelEntry* pa, const KernelEntry* pb = nullptr) {
+    Tuning t = tu;
+    if (ft == TFFT_FT_OFF) t.gran = 0;
+    if (t.gran) {
+        if (pa && t.T > pa->tx_max) t.T = pa->tx_max;
+        if (pb && t.T > pb->tx_max) t.T = pb->tx_max;
+        if (t.T < 1) t.T = 1;
     }
     return t;
 }
@@ -404,12 +430,14 @@ void fill_common(KArgs<V>& a, const KernelEntry& e, const SubTables& st, const T
     a.tw = static_cast<const V*>(st.tw);
     a.left = static_cast<const V*>(st.left);
     a.T = tu.T;
+    a.gran = tu.gran;
     const double u = e.precision == TFFT_FP32 ? 0x1p-24 : 0x1p-53;
     const double Ns = (double)e.Ns;
     a.tau_coef = (R)(tu.kappa * u * std::sqrt(Ns * std::log2(Ns)));
     a.cap = e.precision == TFFT_FP32 ? (R)0x1p64 : (R)0x1p512;
     a.counts = reinterpret_cast<FtCounts*>(counts);
     a.inj_signal = -1;
+    a.inj_signal2 = -1;
     a.stats = g_stats ? 1 : 0;
 }
 
@@ -445,9 +473,11 @@ struct WsSource {
 
 template <class V>
 int transform(const Route& rt, const void* x, void* y, long long N, long long batch, int dir,
-              double scale, tfft_ft_counts* counts, const Tuning& tu, const Inject& inj,
+              double scale, tfft_ft_counts* counts, const Tuning& tu_in, const Inject& inj,
               hipStream_t stream, bool may_alloc, const WsSource& wsrc = WsSource{}) {
     using R = typename RealOf<V>::type;
+    const Tuning tu = rt.single ? effective(tu_in, rt.single->ft, rt.single)
+                                : effective(tu_in, rt.col->ft, rt.col, rt.row);
     const int precision = sizeof(R) == 4 ? TFFT_FP32 : TFFT_FP64;
     const int conj = dir == TFFT_INVERSE ? 1 : 0;
     if (rt.single) {
@@ -513,7 +543,10 @@ int transform(const Route& rt, const void* x, void* y, long long N, long long ba
         // global signal index: the kernels compare sig_base + s
         arm_launch(A, inj, 0, 2, rt.col->n_stages);
         arm_launch(B, inj, 1, 2, rt.row->n_stages);
-        if (!(inj.signal >= c0 && inj.signal < c0 + cnt)) A.inj_signal = B.inj_signal = -1;
+        // a chunk holding neither target runs without the hook
+        const bool hit = (inj.signal >= c0 && inj.signal < c0 + cnt) ||
+                         (inj.signal2 >= c0 && inj.signal2 < c0 + cnt);
+        if (!hit) A.inj_signal = B.inj_signal = A.inj_signal2 = B.inj_signal2 = -1;
         const long long groups = (cnt + tu.T - 1) / tu.T;
         rc = run<V>(*rt.col, xb + (size_t)c0 * sig_bytes, ws, A, groups * A.tiles, stream, timed);
         if (rc != TFFT_OK) return rc;
@@ -635,7 +668,10 @@ int ragged_build(tfft_ragged_plan_s* P, const long long* sizes, long long count)
         if (!ragged_route(kv.first, &L.rt)) return TFFT_EUNSUPPORTED;
         L.ids = kv.second;
         L.N = kv.first;
-        L.tu = get_tuning(TFFT_FP32, L.N);
+        // per-transaction checking: T within what every plan of the route
+        // keeps (the FT-0 entries carry the same plan limits as the others)
+        L.tu = L.rt.single ? effective(get_tuning(TFFT_FP32, L.N), TFFT_FT_CORRECT, L.rt.single)
+                           : effective(get_tuning(TFFT_FP32, L.N), TFFT_FT_CORRECT, L.rt.col, L.rt.row);
         L.T = L.tu.T;
         L.groups = ((long long)L.ids.size() + L.T - 1) / L.T;
         lens.push_back(std::move(L));
@@ -893,6 +929,7 @@ int ragged_exec(tfft_ragged_plan_s* P, const void* x, void* y, int dir, int unit
     c.y = static_cast<float2*>(y);
     c.counts = reinterpret_cast<FtCounts*>(counts);
     c.inj_signal = inj.armed ? inj.signal : -1;
+    c.inj_signal2 = inj.armed ? inj.signal2 : -1;
     c.inj_elem = inj.element;
     c.inj_part = inj.part;
     c.inj_bit = inj.bit;
@@ -1187,14 +1224,25 @@ int tfft_route_info(long long N, int precision, int ft_mode, long long* info, in
     const Tuning tu = get_tuning(precision, N, ft_mode);
     Route r;
     if (!route_for(precision, N, ft_mode, &r, tu.route)) return TFFT_EUNSUPPORTED;
-    long long v[6];
+    long long v[7];
+    Tuning te;
     if (r.single) {
         v[0] = 1; v[1] = N; v[2] = 1; v[3] = r.single->n_stages; v[4] = 0;
+        te = effective(tu, ft_mode, r.single);
     } else {
         v[0] = 2; v[1] = r.N1; v[2] = r.N2; v[3] = r.col->n_stages; v[4] = r.row->n_stages;
+        te = effective(tu, ft_mode, r.col, r.row);
     }
-    v[5] = tu.T;
-    for (int i = 0; i < n && i < 6; ++i) info[i] = v[i];
+    v[5] = te.T;
+    v[6] = te.gran;
+    for (int i = 0; i < n && i < 7; ++i) info[i] = v[i];
+    return TFFT_OK;
+}
+
+int tfft_set_granularity(long long N, int precision, int gran) {
+    if (N < 1 || check_precision(precision) != TFFT_OK || gran < 0 || gran > 1) return TFFT_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    update_tuning(precision, N, [&](Tuning& tu) { tu.gran = gran; });
     return TFFT_OK;
 }
 
@@ -1262,6 +1310,10 @@ int tfft_load_tuning(const char* path) {
             if (e.get("T")) {
                 if (!json_int(e.get("T"), &v) || v < 1 || v > 32) return TFFT_EINVAL;
                 tu.T = (int)v;
+            }
+            if (e.get("gran")) {
+                if (!json_int(e.get("gran"), &v) || v < 0 || v > 1) return TFFT_EINVAL;
+                tu.gran = (int)v;
             }
             if (e.get("chunk_bytes")) {
                 if (!json_int(e.get("chunk_bytes"), &v) || v < 1) return TFFT_EINVAL;
@@ -1362,6 +1414,7 @@ int tfft_inject_arm_desc(const tfft_inject_desc* d) {
     const int width = d->precision == TFFT_FP32 ? 32 : 64;
     if (d->bit < 0 || d->bit >= width) return TFFT_EINVAL;
     if (d->pass < -1 || d->pass > 1 || d->stage < -1) return TFFT_EINVAL;
+    if (d->two != 0 && (d->two != 1 || d->signal2 < 0 || d->signal2 == d->signal)) return TFFT_EINVAL;
     std::lock_guard<std::mutex> lk(g_mu);
     g_inj.armed = true;
     g_inj.signal = d->signal;
@@ -1371,6 +1424,7 @@ int tfft_inject_arm_desc(const tfft_inject_desc* d) {
     g_inj.precision = d->precision;
     g_inj.pass = d->pass;
     g_inj.stage = d->stage;
+    g_inj.signal2 = d->two ? d->signal2 : -1;
     return TFFT_OK;
 }
 
@@ -1451,7 +1505,7 @@ int c2c_impl(const void* x, void* y, long long N, long long batch, int dir, int 
         if (!rt.single) return TFFT_EUNSUPPORTED;
     }
     Inject inj = g_inj;
-    if (inj.armed && (inj.precision != precision || inj.signal >= batch || inj.element >= N ||
+    if (inj.armed && (inj.precision != precision || inj.signal >= batch || inj.signal2 >= batch || inj.element >= N ||
                       !inject_fits(inj, rt.single ? rt.single : rt.col, rt.single ? nullptr : rt.row)))
         return TFFT_EINVAL;
     WsSource wsrc;
@@ -1586,6 +1640,10 @@ int tfft_c2c_ragged(tfft_ragged_plan plan, const void* x, void* y, int dir, int 
     if (inj.armed) {
         if (inj.precision != plan->precision || inj.signal >= plan->count ||
             inj.element >= plan->sizes[(size_t)inj.signal])
+            return TFFT_EINVAL;
+        // a second target must have the same length (same element numbering)
+        if (inj.signal2 >= 0 && (inj.signal2 >= plan->count ||
+                                 plan->sizes[(size_t)inj.signal2] != plan->sizes[(size_t)inj.signal]))
             return TFFT_EINVAL;
         RRoute rr;
         if (!ragged_route(plan->sizes[(size_t)inj.signal], &rr) ||

@@ -75,6 +75,7 @@ template <class R> struct KCall {
     int stats;            // 1: record max |D0| / tau over groups (calibration)
     FtCounts* counts;     // device counters (ABFT only)
     long long inj_signal; // signal to corrupt (-1: none)
+    long long inj_signal2;// a second signal hit the same way (-1: none)
     long long inj_elem;   // element index in this kernel's numbering (see Geo::inj_r)
     int inj_part;         // 0 real, 1 imaginary
     int inj_bit;          // bit to flip
@@ -97,6 +98,8 @@ template <class V> struct KArgs : KCall<typename RealOf<V>::type> {
     long long sig_base;   // global index of local signal 0 (counters only)
     R tau_coef;           // kappa * u * sqrt(Ns log2 Ns); tau = tau_coef * sqrt(nu)
     R cap;                // magnitude cap: larger outputs mark their signal corrupted
+    int gran;             // detection granularity: 0 once per group of T transactions
+                          // (location by D1/D0), 1 per transaction (note and continue)
     int x_intact;         // 1: inputs can be re-read on the error path
     int tiles;            // workgroups per signal group (tile geometries)
     long long nblk;       // workgroups' worth of work of the launch (resident
@@ -529,6 +532,70 @@ template <class V, class PL, bool IND> struct Geo {
         if constexpr (BLOCK) return __syncthreads_or(f ? 1 : 0) != 0;
         else return __any(f ? 1 : 0) != 0;
     }
+
+    // ---- per-transaction checking ----
+    // The lanes of a slot that share a wave (TXW of them) reduce a
+    // transaction's values with cross-lane exchanges; lane tx_tl() == b of
+    // that wave part keeps transaction b's partial, so a group of up to
+    // TX_MAX transactions leaves one partial per lane and no array indexed
+    // by b.  Slots spanning TX_PARTS waves add the parts through LDS once
+    // per group.
+    static constexpr bool SINGLE = PL::KIND == kSingle;
+    static constexpr int TXW = SINGLE ? (P < kWave ? P : kWave) : kWave / C;
+    static constexpr int TX_MAX = TXW < 16 ? TXW : 16;
+    static constexpr int TX_PARTS = SINGLE ? (P > kWave ? P / kWave : 1) : (PL::MULTI_WAVE ? PL::WAVES : 1);
+    __device__ __forceinline__ int tx_tl() const {
+        if constexpr (SINGLE) return P > kWave ? tid % kWave : t;
+        else return (tid % kWave) / C;
+    }
+    // lane of this wave holding transaction b's values for this slot
+    __device__ __forceinline__ int tx_lane(int b) const {
+        if constexpr (SINGLE) return P > kWave ? b : (tid % kWave) - t + b;
+        else return b * C + slot;
+    }
+    template <class T> __device__ __forceinline__ T tx_wave_sum(T v) const {
+        if constexpr (SINGLE) return xor_reduce<1, TXW, OpAdd>(v);
+        else return xor_reduce<C, kWave, OpAdd>(v);
+    }
+    // add the wave parts of the kept partials (K values per lane): every
+    // lane tx_tl() < T of every wave ends with the slot's totals, summed in
+    // the same order everywhere
+    template <int K, class T> __device__ __forceinline__ void tx_parts_sum(T (&v)[K], int T_, T* txr) const {
+        if constexpr (TX_PARTS > 1) {
+            const int tl = tx_tl();
+            const int part = tid / kWave;   // wave = part of the slot
+            auto at = [&](int k, int pr) -> T* {
+                return txr + (((k * TX_MAX + tl) * TX_PARTS + pr) * C + (SINGLE ? 0 : slot));
+            };
+            const bool mine = tl < T_ && tl < TX_MAX;
+            if (mine) {
+#pragma unroll
+                for (int k = 0; k < K; ++k) *at(k, part) = v[k];
+            }
+            __syncthreads();
+            if (mine) {
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    T acc = *at(k, 0);
+#pragma unroll
+                    for (int pr = 1; pr < TX_PARTS; ++pr) acc = acc + *at(k, pr);
+                    v[k] = acc;
+                }
+            }
+        }
+    }
+    // bit b set when lane tx_lane(b) of this wave has f set (b < T_)
+    __device__ __forceinline__ unsigned tx_mask(bool f, int T_) const {
+        const unsigned long long bal = __ballot(f ? 1 : 0);
+        if constexpr (SINGLE) {
+            const int first = P > kWave ? 0 : (tid % kWave) - t;
+            return (unsigned)(bal >> first) & (T_ >= 32 ? 0xffffffffu : ((1u << T_) - 1u));
+        } else {
+            unsigned m = 0;
+            for (int b = 0; b < T_; ++b) m |= (unsigned)((bal >> (b * C + slot)) & 1ull) << b;
+            return m;
+        }
+    }
 };
 
 // ---------------------------------------------------------------------------
@@ -566,10 +633,14 @@ template <class V, class PL, int FT, bool IND = false> struct Smem {
         FT != 0 && (PL::KIND == kColPass || (PL::KIND == kSingle && PL::SLOTS >= 2 && PL::Ns <= 2048) ||
                     kResident<V, PL, FT, IND>);
     static constexpr int AW = AW_LDS ? PL::Ns : 0;
+    // per-transaction checking: wave parts of the kept partials (3 values)
+    using G = Geo<V, PL, IND>;
+    static constexpr int TXR = (FT != 0 && G::TX_PARTS > 1) ? 3 * G::TX_MAX * G::TX_PARTS * (PL::TILE ? PL::C : 1) : 0;
     static constexpr int TWS_OFF = PL::LDS_DATA * (int)sizeof(V);
     static constexpr int AW_OFF = TWS_OFF + TWS * (int)sizeof(V);
     static constexpr int RED_OFF = AW_OFF + AW * (int)sizeof(V);
-    static constexpr int BYTES = RED_OFF + RED * (int)sizeof(R);
+    static constexpr int TXR_OFF = RED_OFF + RED * (int)sizeof(R);
+    static constexpr int BYTES = TXR_OFF + TXR * (int)sizeof(R);
 };
 
 // Buffers that other workgroups of the same launch read back (the persistent
@@ -698,6 +769,10 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
     V qs = V{0, 0}, qw = V{0, 0};   // sum_b q_b, sum_b (b+1) q_b
     R nu = 0;                        // input energy of the group
     unsigned nfmask = 0;             // transactions with a non-finite / oversized output
+    // per-transaction checking: this lane's kept partial, the slot's
+    // q_b - p_b (D0 of transaction b = tx_tl()) and input energy nu_b
+    R txd[3] = {0, 0, 0};
+    const bool per_tx = FT != 0 && a.gran != 0;
     if constexpr (KEEP_XS) {
 #pragma unroll
         for (int r = 0; r < E; ++r) xs[r] = V{0, 0};
@@ -752,9 +827,10 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
 #pragma unroll
             for (int r = 0; r < E; ++r) reg[r].y = -reg[r].y;
         }
+        V p = V{0, 0};
+        R nub = 0;   // input energy of this transaction
         {
             const R wb = (R)(b + 1);
-            V p = V{0, 0};
 #pragma unroll
             for (int r = 0; r < E; ++r) {
                 const V z = reg[r];   // raw loaded value
@@ -769,20 +845,24 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
                     else av = left_at(r);
                     if constexpr (PL::KIND == kRowPass) av = cmul(av, tw);
                     p = cmac(p, av, z);
-                    nu = fmad(z.x, z.x, fmad(z.y, z.y, nu));
+                    nub = fmad(z.x, z.x, fmad(z.y, z.y, nub));
                     if constexpr (KEEP_XS) xs[r] = cadd(xs[r], z);
                 }
             }
             if constexpr (FT != 0) {
-                ps = cadd(ps, p);
-                pw = V{fmad(wb, p.x, pw.x), fmad(wb, p.y, pw.y)};
+                if (!per_tx) {
+                    ps = cadd(ps, p);
+                    pw = V{fmad(wb, p.x, pw.x), fmad(wb, p.y, pw.y)};
+                    nu = nu + nub;
+                }
             }
         }
 
         // test hook: one bit flip in the value of position inj_elem after
         // radix stage inj_stage (a uniform branch on kernel arguments)
         auto inject = [&](int stage, V (&rg)[E]) {
-            if (kc.inj_signal >= 0 && kc.inj_stage == stage && valid && g.gid(a, s) == kc.inj_signal) {
+            if (kc.inj_signal >= 0 && kc.inj_stage == stage && valid &&
+                (g.gid(a, s) == kc.inj_signal || g.gid(a, s) == kc.inj_signal2)) {
                 const int rh = g.inj_r(a, kc);
 #pragma unroll
                 for (int r = 0; r < E; ++r) {
@@ -797,10 +877,27 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
 
         if constexpr (FT != 0) {
             const V q = encode_out<V, E, P, M>(reg);
-            const R wb = (R)(b + 1);
-            qs = cadd(qs, q);
-            qw = V{fmad(wb, q.x, qw.x), fmad(wb, q.y, qw.y)};
-            if (!cfin(q.x, q.y, a.cap)) nfmask |= 1u << b;
+            if (per_tx) {
+                // check of transaction b (Sec. 4.1, note and continue): the
+                // slot's q_b - p_b and nu_b, reduced over the lanes of this
+                // wave and kept by lane b; the decision is taken for all
+                // transactions of the group at its end
+                int tt = g.t;
+                asm volatile("" : "+v"(tt));
+                const V lf = wM<V, M>(tt % M);
+                const V d = csub(cmul(lf, q), p);
+                const R w0 = g.tx_wave_sum(d.x), w1 = g.tx_wave_sum(d.y), w2 = g.tx_wave_sum(nub);
+                if (g.tx_tl() == b) {
+                    txd[0] = w0;
+                    txd[1] = w1;
+                    txd[2] = w2;
+                }
+            } else {
+                const R wb = (R)(b + 1);
+                qs = cadd(qs, q);
+                qw = V{fmad(wb, q.x, qw.x), fmad(wb, q.y, qw.y)};
+                if (!cfin(q.x, q.y, a.cap)) nfmask |= 1u << b;
+            }
         }
 
         if (valid) {
@@ -824,224 +921,352 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
         // The group close decides and corrects; its arithmetic never reaches
         // a fault-free output, so the compiler may fuse freely here.
 #pragma clang fp contract(fast)
-        // ---- group close: reduce the checksum differences over the slot ----
         const V lanef = wM<V, M>(t % M);   // e_{t + P r} = w_M^t w_M^{P r}
-        const V dd0 = csub(cmul(lanef, qs), ps);   // this lane's share of D0
-        const V dd1 = csub(cmul(lanef, qw), pw);   // and of D1
-        const R nfc = (R)__builtin_popcount(nfmask);
-        V D0, D1;
-        R nu_s, nf_count;
-        if (a.T == 1) {   // one transaction: D1 = D0, no location needed
-            R v[4] = {dd0.x, dd0.y, nu, nfc};
-            g.template reduce<OpAdd>(v, red);
-            D0 = V{v[0], v[1]};
-            D1 = D0;
-            nu_s = v[2];
-            nf_count = v[3];
-        } else {
-            R v[6] = {dd0.x, dd0.y, dd1.x, dd1.y, nu, nfc};
-            g.template reduce<OpAdd>(v, red);
-            D0 = V{v[0], v[1]};
-            D1 = V{v[2], v[3]};
-            nu_s = v[4];
-            nf_count = v[5];
-        }
-        unsigned nf = 0;
-        if (nf_count > (R)0) {   // rare: which transactions held a non-finite output
-            unsigned nfv[1] = {nfmask};
-            g.template reduce<OpOr>(nfv, reinterpret_cast<unsigned*>(red));
-            nf = nfv[0];
-        }
 
-        // decision, identical on every lane of the slot:
-        // 0 clean or unchecked, 1 add the correction, 2 rebuild, 3 uncorrectable
-        int action = 0, bstar = -1;
-        const R tau = a.tau_coef * __builtin_sqrt(nu_s);
-        const bool checked = (nu_s == nu_s) && nu_s < (R)INFINITY;
-        const R d0 = __builtin_sqrt(D0.x * D0.x + D0.y * D0.y);
-        if (checked) {
-            if (nf != 0) {
-                if ((nf & (nf - 1)) != 0) action = 3;
-                else { bstar = __builtin_ctz(nf); action = 2; }
-            } else if (!(d0 <= tau)) {
-                const R den = D0.x * D0.x + D0.y * D0.y;
-                const R rr = (D1.x * D0.x + D1.y * D0.y) / den;
-                const R ri = (D1.y * D0.x - D1.x * D0.y) / den;
-                const R rnd = __builtin_rint(rr);
-                const R dx = rr - rnd;
-                const bool ok = rnd >= (R)1 && rnd <= (R)a.T && (dx * dx + ri * ri) <= (R)0.0625 &&
-                                g.sig((int)rnd - 1) < a.batch;
-                if (ok) { bstar = (int)rnd - 1; action = 1; }
-                else action = 3;
-            }
-        }
-        if (kc.stats && checked && nf == 0 && t == 0 && tau > (R)0) {
-            // calibration: largest |D0| / tau seen (non-negative doubles order as integers)
-            const double q = (double)d0 / (double)tau;
-            atomicMax(&kc.counts->calib, (unsigned long long)__double_as_longlong(q));
-        }
-
-        // Location fallback on the error path: when D1/D0 is not an index (an
-        // error just above the threshold, where location noise dominates) and
-        // the inputs are intact, re-encode every signal of the group and take
-        // the one whose own checksums disagree most.
-        if (g.domain_any(action == 3 && nf == 0 && a.x_intact)) {
+        // ---- delayed batched correction (Sec. 4.1, Eq. 5) ----
+        // Correct transaction bstar of this slot from the right-side sums of
+        // transactions [0, upto): c = W x_s - Y e, with x_s = X e summed from
+        // the intact inputs (in registers when in place) and Y e from the
+        // stored outputs (HBM, where transactions corrected earlier in the
+        // group already hold their repaired values).  act: 0 nothing for this
+        // slot, 1 add c when it is finite and small, else rebuild, 2 rebuild
+        // y_b* = W x_s - sum_{b != b*} y_b.  The repair is accepted when
+        // |e^T c + dref| <= tau_v (c explains the discrepancy) or, for a
+        // rebuild, when the rebuilt values are finite.  Called by the whole
+        // synchronisation domain together (it exchanges through LDS).
+        const Geo<V, PL, IND>& g0 = g;
+        auto correct = [&](int act, int bstar, int upto, V dref, R tau_v, R nu_sum) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            R best = (R)-1;
-            int bbest = -1;
-            for (int b = 0; b < a.T; ++b) {
-                const long long sb = g.sig(b);
-                const bool vb = sb < a.batch;
-                V p = V{0, 0};
-                V bucket[M];
+            // opaque coordinates: called in a loop, nothing derived from the
+            // lane or the group may be hoisted out of it (the 64-bit addresses
+            // of every element would then stay live through the loop)
+            Geo<V, PL, IND> g = g0;
+            asm volatile("" : "+v"(g.t), "+v"(g.sig0), "+v"(g.lds_off), "+v"(g.line), "+v"(g.slot),
+                              "+v"(g.tile), "+v"(g.tw_base.x), "+v"(g.tw_base.y));
+            const int t = g.t;
+            const auto li = g.lidx();
+            const V lanef = wM<V, M>(t % M);
+            const long long sstar = g.sig(bstar < 0 ? 0 : bstar);
+            // loops run over the whole group (a uniform bound) and skip the
+            // transactions past upto, which may differ between the slots of a wave
+            int nvalid = 0;
+            for (int b = 0; b < a.T; ++b) nvalid += (b < upto && g.sig(b) < a.batch) ? 1 : 0;
 #pragma unroll
-                for (int m = 0; m < M; ++m) bucket[m] = V{0, 0};
-                if (vb) {
-#pragma unroll
-                    for (int r = 0; r < E; ++r) {
-                        V xv = ld_x<COH>(x, g.in_off(a, sb, t + P * r));
-                        if (kc.conj_in) xv.y = -xv.y;
-                        V av = left[t + P * r];
-                        if constexpr (PL::KIND == kRowPass) av = cmul(av, g.twiddle(a, r));
-                        p = cadd(p, cmul(av, xv));
-                        V yv = ld_y<COH>(y, g.out_off(a, sb, t + P * r));
-                        if (kc.conj_out) yv.y = -yv.y;
-                        bucket[(P * r) % M] = cadd(bucket[(P * r) % M], V{yv.x / kc.scale, yv.y / kc.scale});
-                    }
-                }
-                V q = bucket[0];
-#pragma unroll
-                for (int m = 1; m < M; ++m) q = cadd(q, cmul(bucket[m], wM<V, M>(m)));
-                q = cmul(lanef, q);
-                R d[2] = {q.x - p.x, q.y - p.y};
-                g.template reduce<OpAdd>(d, red);
-                const R m2 = d[0] * d[0] + d[1] * d[1];
-                if (vb && m2 > best) { best = m2; bbest = b; }
-            }
-            if (action == 3 && nf == 0 && bbest >= 0) {
-                bstar = bbest;
-                action = 1;
-                if (t == 0) atomicAdd(&kc.counts->fallback, 1ull);
-            }
-        }
-        const long long sstar = g.sig(bstar < 0 ? 0 : bstar);
-
-        if constexpr (FT == 1) {
-            if (action != 0 && t == 0) {
-                atomicAdd(&kc.counts->detected, 1ull);
-                if (action == 3) atomicAdd(&kc.counts->uncorrectable, 1ull);
-                else atomicExch(&kc.counts->last_signal, (unsigned long long)g.gid(a, sstar));
-            }
-        } else {
-            if (g.domain_any(action == 1 || action == 2)) {
-                // ---- delayed batched correction: W x_s on the slot's lanes ----
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                // x_s = X e: kept in registers when in place, else summed
-                // again from the group's intact inputs
-#pragma unroll
-                for (int r = 0; r < E; ++r) {
-                    V acc = V{0, 0};
-                    if constexpr (KEEP_XS) {
-                        acc = xs[r];
-                    } else {
-                        for (int b = 0; b < a.T; ++b) {
-                            const long long sb = g.sig(b);
-                            if (sb >= a.batch) continue;
-                            V xv = ld_x<COH>(x, g.in_off(a, sb, t + P * r));
-                            if (kc.conj_in) xv.y = -xv.y;
-                            acc = cadd(acc, xv);
-                        }
-                    }
-                    if constexpr (PL::KIND == kRowPass) acc = cmul(acc, g.twiddle(a, r));
-                    reg[r] = acc;
-                }
-                NoHook nohook;
-                slot_fft<V, E, P, BLOCK, decltype(li), NoHook, 0, 1, Rs...>(reg, a.tw, t, lds, li, nohook);   // W x_s
-                // c = W x_s - Y e, element by element, Y e summed from the
-                // group's stored outputs (internal domain); skip: leave out b*
-                auto corr_elem = [&](int r, int skip) -> V {
-                    V acc = reg[r];
+            for (int r = 0; r < E; ++r) {
+                V acc = V{0, 0};
+                if constexpr (KEEP_XS) {
+                    acc = xs[r];
+                } else {
                     for (int b = 0; b < a.T; ++b) {
                         const long long sb = g.sig(b);
-                        if (sb >= a.batch || b == skip) continue;
-                        V yv = ld_y<COH>(y, g.out_off(a, sb, t + P * r));
-                        if (kc.conj_out) yv.y = -yv.y;
-                        acc = V{acc.x - yv.x / kc.scale, acc.y - yv.y / kc.scale};
+                        if (b >= upto || sb >= a.batch) continue;
+                        V xv = ld_x<COH>(x, g.in_off(a, sb, t + P * r));
+                        if (kc.conj_in) xv.y = -xv.y;
+                        acc = cadd(acc, xv);
                     }
-                    return acc;
-                };
-                const R yrms2 = (R)Ns * nu_s / (R)a.T;
-                bool cf = true, small = true;
-                V bucket[M];
+                }
+                if constexpr (PL::KIND == kRowPass) acc = cmul(acc, g.twiddle(a, r));
+                reg[r] = acc;
+            }
+            NoHook nohook;
+            slot_fft<V, E, P, BLOCK, decltype(li), NoHook, 0, 1, Rs...>(reg, a.tw, t, lds, li, nohook);   // W x_s
+            // c = W x_s - Y e, element by element, Y e summed from the stored
+            // outputs (internal domain); skip: leave out b*
+            auto corr_elem = [&](int r, int skip) -> V {
+                V acc = reg[r];
+                for (int b = 0; b < a.T; ++b) {
+                    const long long sb = g.sig(b);
+                    if (b >= upto || sb >= a.batch || b == skip) continue;
+                    V yv = ld_y<COH>(y, g.out_off(a, sb, t + P * r));
+                    if (kc.conj_out) yv.y = -yv.y;
+                    acc = V{acc.x - yv.x / kc.scale, acc.y - yv.y / kc.scale};
+                }
+                return acc;
+            };
+            const R yrms2 = (R)Ns * nu_sum / (R)(nvalid > 0 ? nvalid : 1);
+            bool cf = true, small = true;
+            V bucket[M];
 #pragma unroll
-                for (int m = 0; m < M; ++m) bucket[m] = V{0, 0};
+            for (int m = 0; m < M; ++m) bucket[m] = V{0, 0};
+#pragma unroll
+            for (int r = 0; r < E; ++r) {
+                const V c = corr_elem(r, -1);
+                cf = cf && cfin(c.x, c.y, a.cap);
+                small = small && (c.x * c.x + c.y * c.y) <= yrms2;
+                bucket[(P * r) % M] = cadd(bucket[(P * r) % M], c);
+            }
+            V ec = bucket[0];
+#pragma unroll
+            for (int m = 1; m < M; ++m) ec = cadd(ec, cmul(bucket[m], wM<V, M>(m)));
+            ec = cmul(lanef, ec);
+            R w4[4] = {ec.x, ec.y, cf ? (R)0 : (R)1, small ? (R)0 : (R)1};
+            g.template reduce<OpAdd>(w4, red);
+            // additive only when c is finite and no larger than one signal's
+            // rms output norm; otherwise rebuild from the other outputs
+            if (act == 1 && !(w4[2] == (R)0 && w4[3] == (R)0)) act = 2;
+            bool ok = true;
+            if (act == 1) {
+                const R vx = w4[0] + dref.x, vy = w4[1] + dref.y;
+                ok = __builtin_sqrt(vx * vx + vy * vy) <= tau_v;
+            }
+            bool rebuilt_ok = true;
+            if (act == 1 && ok) {
+                // y_b* += scale * cj(c)
 #pragma unroll
                 for (int r = 0; r < E; ++r) {
-                    const V c = corr_elem(r, -1);
-                    cf = cf && cfin(c.x, c.y, a.cap);
-                    small = small && (c.x * c.x + c.y * c.y) <= yrms2;
-                    bucket[(P * r) % M] = cadd(bucket[(P * r) % M], c);
+                    V cc = corr_elem(r, -1);
+                    if (kc.conj_out) cc.y = -cc.y;
+                    const long long o = g.out_off(a, sstar, t + P * r);
+                    const V old = ld_y<COH>(y, o);
+                    st_y<COH>(y, o, V{old.x + kc.scale * cc.x, old.y + kc.scale * cc.y});
                 }
-                V ec = bucket[0];
+            } else if (act == 2) {
+                // y_b* = scale * cj(W x_s - sum_{b != b*} y_b)
 #pragma unroll
-                for (int m = 1; m < M; ++m) ec = cadd(ec, cmul(bucket[m], wM<V, M>(m)));
-                ec = cmul(lanef, ec);
-                R w4[4] = {ec.x, ec.y, cf ? (R)0 : (R)1, small ? (R)0 : (R)1};
-                g.template reduce<OpAdd>(w4, red);
-                // additive only when c is finite and no larger than one signal's
-                // rms output norm; otherwise rebuild from the other outputs
-                if (action == 1 && !(w4[2] == (R)0 && w4[3] == (R)0)) action = 2;
-                bool ok = true;
-                if (action == 1) {
-                    const R vx = w4[0] + D0.x, vy = w4[1] + D0.y;
-                    ok = __builtin_sqrt(vx * vx + vy * vy) <= tau;
-                }
-                bool rebuilt_ok = true;
-                if (action == 1 && ok) {
-                    // y_b* += scale * cj(c)
-#pragma unroll
-                    for (int r = 0; r < E; ++r) {
-                        V cc = corr_elem(r, -1);
-                        if (kc.conj_out) cc.y = -cc.y;
-                        const long long o = g.out_off(a, sstar, t + P * r);
-                        const V old = ld_y<COH>(y, o);
-                        st_y<COH>(y, o, V{old.x + kc.scale * cc.x, old.y + kc.scale * cc.y});
-                    }
-                } else if (action == 2) {
-                    // y_b* = scale * cj(W x_s - sum_{b != b*} y_b)
-#pragma unroll
-                    for (int r = 0; r < E; ++r) {
-                        V vv = corr_elem(r, bstar);
-                        if (kc.conj_out) vv.y = -vv.y;
-                        vv = V{kc.scale * vv.x, kc.scale * vv.y};
-                        rebuilt_ok = rebuilt_ok && cfin(vv.x, vv.y, a.cap);
-                        st_y<COH>(y, g.out_off(a, sstar, t + P * r), vv);
-                    }
-                }
-                unsigned badv[1] = {(action == 2 && !rebuilt_ok) ? 1u : 0u};
-                g.template reduce<OpOr>(badv, reinterpret_cast<unsigned*>(red));
-                if (action == 2 && badv[0] != 0u) ok = false;
-                if ((action == 1 || action == 2) && t == 0) {
-                    atomicAdd(&kc.counts->detected, 1ull);
-                    if (!ok) atomicAdd(&kc.counts->uncorrectable, 1ull);
-                    else if (action == 1) atomicAdd(&kc.counts->corrected, 1ull);
-                    else atomicAdd(&kc.counts->rebuilt, 1ull);
-                    atomicExch(&kc.counts->last_signal, (unsigned long long)g.gid(a, sstar));
+                for (int r = 0; r < E; ++r) {
+                    V vv = corr_elem(r, bstar);
+                    if (kc.conj_out) vv.y = -vv.y;
+                    vv = V{kc.scale * vv.x, kc.scale * vv.y};
+                    rebuilt_ok = rebuilt_ok && cfin(vv.x, vv.y, a.cap);
+                    st_y<COH>(y, g.out_off(a, sstar, t + P * r), vv);
                 }
             }
-            if (action == 3 && t == 0) {
+            unsigned badv[1] = {(act == 2 && !rebuilt_ok) ? 1u : 0u};
+            g.template reduce<OpOr>(badv, reinterpret_cast<unsigned*>(red));
+            if (act == 2 && badv[0] != 0u) ok = false;
+            if ((act == 1 || act == 2) && t == 0) {
                 atomicAdd(&kc.counts->detected, 1ull);
-                atomicAdd(&kc.counts->uncorrectable, 1ull);
+                if (!ok) atomicAdd(&kc.counts->uncorrectable, 1ull);
+                else if (act == 1) atomicAdd(&kc.counts->corrected, 1ull);
+                else atomicAdd(&kc.counts->rebuilt, 1ull);
+                atomicExch(&kc.counts->last_signal, (unsigned long long)g.gid(a, sstar));
             }
+            // the next correction of this group re-reads these outputs
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        };
+
+        // Pending repairs, from whichever granularity is in use; one call site
+        // below serves both, so the correction is compiled once.
+        unsigned Fr = 0u;              // per transaction: faulty transactions not yet repaired
+        int gact = 0, gb = -1;         // per group: 1 add / 2 rebuild, and the located signal
+        V gD0 = V{0, 0};
+        R gtau = 0, gnu = 0;
+        if (per_tx) {
+            // ---- per-transaction decisions, taken at the end of the group ----
+            R* txr = reinterpret_cast<R*>(smem + Smem<V, PL, FT, IND>::TXR_OFF);
+            // the host limits T to what the plan keeps; never read past it
+            const int Tq = a.T < Geo<V, PL, IND>::TX_MAX ? a.T : Geo<V, PL, IND>::TX_MAX;
+            g.template tx_parts_sum<3>(txd, Tq, txr);
+            const int tl = g.tx_tl();
+            // lane tl (< T) holds transaction tl's D0 = q - p and nu
+            const R tau_b = a.tau_coef * __builtin_sqrt(txd[2]);
+            const bool checked = tl < Tq && (txd[2] == txd[2]) && txd[2] < (R)INFINITY;
+            const R d0 = __builtin_sqrt(txd[0] * txd[0] + txd[1] * txd[1]);
+            const bool bad = checked && !(d0 <= tau_b);
+            if (kc.stats && checked && !bad && tau_b > (R)0 && g.sig(tl) < a.batch) {
+                const double q = (double)d0 / (double)tau_b;
+                atomicMax(&kc.counts->calib, (unsigned long long)__double_as_longlong(q));
+            }
+            const unsigned F = g.tx_mask(bad, Tq);   // faulty transactions of this slot
+            if constexpr (FT == 1) {
+                if (t == 0) {
+                    for (unsigned f = F; f != 0u; f &= f - 1u) {
+                        atomicAdd(&kc.counts->detected, 1ull);
+                        atomicExch(&kc.counts->last_signal,
+                                   (unsigned long long)g.gid(a, g.sig(__builtin_ctz(f))));
+                    }
+                }
+            } else {
+                // in place, x_s holds the whole group's inputs: a lone fault
+                // is repaired from it, two or more are not separable
+                const int nbad = __builtin_popcount(F);
+                const bool lone = !KEEP_XS || nbad <= 1;
+                if (!lone && t == 0) {
+                    atomicAdd(&kc.counts->detected, (unsigned long long)nbad);
+                    atomicAdd(&kc.counts->uncorrectable, (unsigned long long)nbad);
+                }
+                Fr = lone ? F : 0u;
+            }
+        } else {
+            // ---- group close: reduce the checksum differences over the slot ----
+            const V dd0 = csub(cmul(lanef, qs), ps);   // this lane's share of D0
+            const V dd1 = csub(cmul(lanef, qw), pw);   // and of D1
+            const R nfc = (R)__builtin_popcount(nfmask);
+            V D0, D1;
+            R nu_s, nf_count;
+            if (a.T == 1) {   // one transaction: D1 = D0, no location needed
+                R v[4] = {dd0.x, dd0.y, nu, nfc};
+                g.template reduce<OpAdd>(v, red);
+                D0 = V{v[0], v[1]};
+                D1 = D0;
+                nu_s = v[2];
+                nf_count = v[3];
+            } else {
+                R v[6] = {dd0.x, dd0.y, dd1.x, dd1.y, nu, nfc};
+                g.template reduce<OpAdd>(v, red);
+                D0 = V{v[0], v[1]};
+                D1 = V{v[2], v[3]};
+                nu_s = v[4];
+                nf_count = v[5];
+            }
+            unsigned nf = 0;
+            if (nf_count > (R)0) {   // rare: which transactions held a non-finite output
+                unsigned nfv[1] = {nfmask};
+                g.template reduce<OpOr>(nfv, reinterpret_cast<unsigned*>(red));
+                nf = nfv[0];
+            }
+
+            // decision, identical on every lane of the slot:
+            // 0 clean or unchecked, 1 add the correction, 2 rebuild, 3 uncorrectable
+            int action = 0, bstar = -1;
+            const R tau = a.tau_coef * __builtin_sqrt(nu_s);
+            const bool checked = (nu_s == nu_s) && nu_s < (R)INFINITY;
+            const R d0 = __builtin_sqrt(D0.x * D0.x + D0.y * D0.y);
+            if (checked) {
+                if (nf != 0) {
+                    if ((nf & (nf - 1)) != 0) action = 3;
+                    else { bstar = __builtin_ctz(nf); action = 2; }
+                } else if (!(d0 <= tau)) {
+                    const R den = D0.x * D0.x + D0.y * D0.y;
+                    const R rr = (D1.x * D0.x + D1.y * D0.y) / den;
+                    const R ri = (D1.y * D0.x - D1.x * D0.y) / den;
+                    const R rnd = __builtin_rint(rr);
+                    const R dx = rr - rnd;
+                    const bool ok = rnd >= (R)1 && rnd <= (R)a.T && (dx * dx + ri * ri) <= (R)0.0625 &&
+                                    g.sig((int)rnd - 1) < a.batch;
+                    if (ok) { bstar = (int)rnd - 1; action = 1; }
+                    else action = 3;
+                }
+            }
+            if (kc.stats && checked && nf == 0 && t == 0 && tau > (R)0) {
+                // calibration: largest |D0| / tau seen (non-negative doubles order as integers)
+                const double q = (double)d0 / (double)tau;
+                atomicMax(&kc.counts->calib, (unsigned long long)__double_as_longlong(q));
+            }
+
+            // Location fallback on the error path: when D1/D0 is not an index (an
+            // error just above the threshold, where location noise dominates) and
+            // the inputs are intact, re-encode every signal of the group and take
+            // the one whose own checksums disagree most.
+            if (g.domain_any(action == 3 && nf == 0 && a.x_intact)) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                R best = (R)-1;
+                int bbest = -1;
+                for (int b = 0; b < a.T; ++b) {
+                    const long long sb = g.sig(b);
+                    const bool vb = sb < a.batch;
+                    V p = V{0, 0};
+                    V bucket[M];
+#pragma unroll
+                    for (int m = 0; m < M; ++m) bucket[m] = V{0, 0};
+                    if (vb) {
+#pragma unroll
+                        for (int r = 0; r < E; ++r) {
+                            V xv = ld_x<COH>(x, g.in_off(a, sb, t + P * r));
+                            if (kc.conj_in) xv.y = -xv.y;
+                            V av = left[t + P * r];
+                            if constexpr (PL::KIND == kRowPass) av = cmul(av, g.twiddle(a, r));
+                            p = cadd(p, cmul(av, xv));
+                            V yv = ld_y<COH>(y, g.out_off(a, sb, t + P * r));
+                            if (kc.conj_out) yv.y = -yv.y;
+                            bucket[(P * r) % M] = cadd(bucket[(P * r) % M], V{yv.x / kc.scale, yv.y / kc.scale});
+                        }
+                    }
+                    V q = bucket[0];
+#pragma unroll
+                    for (int m = 1; m < M; ++m) q = cadd(q, cmul(bucket[m], wM<V, M>(m)));
+                    q = cmul(lanef, q);
+                    R d[2] = {q.x - p.x, q.y - p.y};
+                    g.template reduce<OpAdd>(d, red);
+                    const R m2 = d[0] * d[0] + d[1] * d[1];
+                    if (vb && m2 > best) { best = m2; bbest = b; }
+                }
+                if (action == 3 && nf == 0 && bbest >= 0) {
+                    bstar = bbest;
+                    action = 1;
+                    if (t == 0) atomicAdd(&kc.counts->fallback, 1ull);
+                }
+            }
+            const long long sstar = g.sig(bstar < 0 ? 0 : bstar);
+
+            if constexpr (FT == 1) {
+                if (action != 0 && t == 0) {
+                    atomicAdd(&kc.counts->detected, 1ull);
+                    if (action == 3) atomicAdd(&kc.counts->uncorrectable, 1ull);
+                    else atomicExch(&kc.counts->last_signal, (unsigned long long)g.gid(a, sstar));
+                }
+            } else {
+                if (action == 1 || action == 2) {
+                    gact = action;
+                    gb = bstar;
+                    gD0 = D0;
+                    gtau = tau;
+                    gnu = nu_s;
+                }
+                if (action == 3 && t == 0) {
+                    atomicAdd(&kc.counts->detected, 1ull);
+                    atomicAdd(&kc.counts->uncorrectable, 1ull);
+                }
+            }
+        }
+
+        if constexpr (FT != 1) {
+            // Repairs, oldest first.  Per transaction (note and continue), a
+            // faulty transaction is corrected from the sums of the
+            // transactions before the next faulty one, or of the whole group;
+            // per group, the located signal from the whole group's sums.  (The
+            // guard keeps the loop's set-up off the fault-free path.)
+            if (g.domain_any(Fr != 0u || gact != 0)) do {
+                int act = 0, bstar = -1, upto = a.T;
+                V dref = V{0, 0};
+                R tau_v = 0, nu_sum = 0;
+                if (Fr != 0u) {
+                    bstar = __builtin_ctz(Fr);
+                    Fr &= Fr - 1u;
+                    upto = Fr ? (int)__builtin_ctz(Fr) : a.T;
+                    dref = V{__shfl(txd[0], g.tx_lane(bstar)), __shfl(txd[1], g.tx_lane(bstar))};
+                    for (int b = 0; b < a.T; ++b) {
+                        const R nb = __shfl(txd[2], g.tx_lane(b));
+                        if (b < upto && nb == nb && nb < (R)INFINITY) nu_sum += nb;
+                    }
+                    // c carries the rounding of every signal in the sums
+                    tau_v = a.tau_coef * __builtin_sqrt(nu_sum);
+                    act = 1;
+                } else if (gact != 0) {
+                    act = gact;
+                    bstar = gb;
+                    dref = gD0;
+                    tau_v = gtau;
+                    nu_sum = gnu;
+                    gact = 0;
+                }
+                correct(act, bstar, upto, dref, tau_v, nu_sum);
+            } while (g.domain_any(Fr != 0u));
         }
     }
 }
 
+// Occupancy the checking kernels are held to: what their LDS allows, at
+// most four waves per SIMD (three in place).  The error path (correction) needs more registers
+// than the transform; without the floor the compiler lowers the occupancy of
+// the whole kernel for it and then spends the registers in the hot loop too.
+// With it, the error path spills instead, which costs nothing when no fault
+// occurs.
+template <class V, class PL, int FT, bool IND> struct Occupancy {
+    static constexpr int LDS_PER_CU = 160 * 1024;
+    static constexpr int WG_PER_CU = LDS_PER_CU / Smem<V, PL, FT, IND>::BYTES;
+    static constexpr int LDS_WAVES = WG_PER_CU * PL::WAVES / 4;   // per SIMD
+    // in place, the right-side input sum stays in registers through the group
+    static constexpr int CAP = FT == 3 ? 3 : 4;
+    static constexpr int WAVES = FT == 0 || !PL::TILE ? 1 : (LDS_WAVES < 1 ? 1 : (LDS_WAVES > CAP ? CAP : LDS_WAVES));
+};
+
 template <class V, class PL, int FT, bool IND, int... Rs>
-__global__ __launch_bounds__(PL::THREADS) void k_fft(const V* __restrict__ x, V* __restrict__ y,
-                                                     KArgs<V> a) {
+__global__ __launch_bounds__(PL::THREADS) __attribute__((amdgpu_waves_per_eu(Occupancy<V, PL, FT, IND>::WAVES)))
+void k_fft(const V* __restrict__ x, V* __restrict__ y, KArgs<V> a) {
     __shared__ __align__(16) char smem[Smem<V, PL, FT, IND>::BYTES];
     if constexpr (kResident<V, PL, FT, IND>) {
         // e^T W into LDS once; every exchange and reduction of the first

@@ -83,6 +83,7 @@ struct RaggedCall {
     float2* y;
     FtCounts* counts;
     long long inj_signal;      // global signal index (-1: none)
+    long long inj_signal2;     // a second signal hit the same way (-1: none)
     long long inj_elem;
     int inj_part, inj_bit;
     int inj_pass;              // -1 last pass, 0 single / column pass, 1 row pass

@@ -137,6 +137,7 @@ __device__ __forceinline__ void ragged_step(const RaggedCall& c, const RaggedDes
         constexpr int kPasses = PL::KIND == kSingle ? 1 : 2;
         const int want = c.inj_pass < 0 ? kPasses - 1 : c.inj_pass;
         kc.inj_signal = want == kPass ? c.inj_signal : -1;
+        kc.inj_signal2 = want == kPass ? c.inj_signal2 : -1;
         kc.inj_stage = c.inj_stage < 0 ? (int)sizeof...(Rs) - 1 : c.inj_stage;
     }
     kc.inj_elem = c.inj_elem;

@@ -26,6 +26,7 @@ struct KernelEntry {
     LaunchFn launch;
     int ragged_id;          // index in the ragged plan list (-1: regular plan)
     int variant;            // plans of one (kind, Ns): 0 default, 1.. alternatives
+    int tx_max;             // per-transaction checking: most transactions per group
 };
 
 // grid: workgroups' worth of work.  Resident kernels launch at most as many
@@ -72,6 +73,7 @@ template <class V, class PL, int FT, bool IND, int... Rs> KernelEntry make_entry
     e.launch = &launch_fft<V, PL, FT, IND, Rs...>;
     e.ragged_id = -1;
     e.variant = 0;
+    e.tx_max = Geo<V, PL, IND>::TX_MAX;
     return e;
 }
 

@@ -103,22 +103,24 @@ def supported(N: int, dtype=torch.complex64) -> bool:
 
 
 def inject_arm(signal: int, element: int, part: int, bit: int, dtype=torch.complex64,
-               pass_: int = -1, stage: int = -1) -> None:
+               pass_: int = -1, stage: int = -1, signal2: int | None = None) -> None:
     """Arm one bit flip for the next call (see tfft_inject_arm_desc): pass_
     -1 last, 0 single / column pass, 1 row pass; stage -1 after the last
-    radix stage, else after radix stage `stage`."""
+    radix stage, else after radix stage `stage`; signal2: the same flip in a
+    second signal (two faults in one call)."""
     import ctypes
     d = _lib.InjectDesc(signal=int(signal), element=int(element), part=int(part), bit=int(bit),
-                        precision=_precision(dtype), pass_=int(pass_), stage=int(stage), reserved=0)
+                        precision=_precision(dtype), pass_=int(pass_), stage=int(stage),
+                        two=0 if signal2 is None else 1, signal2=-1 if signal2 is None else int(signal2))
     _lib.check(_lib.load().tfft_inject_arm_desc(ctypes.byref(d)), "tfft_inject_arm_desc")
 
 
 def route_info(N: int, dtype=torch.complex64, ft_mode: int = 2) -> dict:
     """The route a call takes now: passes, N1, N2, stages of each pass, T."""
     import ctypes
-    buf = (ctypes.c_longlong * 6)()
-    _lib.check(_lib.load().tfft_route_info(N, _precision(dtype), ft_mode, buf, 6), f"tfft_route_info(N={N})")
-    keys = ("passes", "N1", "N2", "stages0", "stages1", "T")
+    buf = (ctypes.c_longlong * 7)()
+    _lib.check(_lib.load().tfft_route_info(N, _precision(dtype), ft_mode, buf, 7), f"tfft_route_info(N={N})")
+    keys = ("passes", "N1", "N2", "stages0", "stages1", "T", "gran")
     return {k: int(buf[i]) for i, k in enumerate(keys)}
 
 
@@ -128,6 +130,12 @@ def inject_disarm() -> None:
 
 def set_tuning(N: int, dtype, T: int = 0, kappa: float = 0.0) -> None:
     _lib.check(_lib.load().tfft_set_tuning(N, _precision(dtype), T, float(kappa)), "tfft_set_tuning")
+
+
+def set_granularity(N: int, dtype, gran: int) -> None:
+    """Detection granularity of (N, dtype): 0 once per group (location code),
+    1 per transaction (see tfft_set_granularity)."""
+    _lib.check(_lib.load().tfft_set_granularity(N, _precision(dtype), int(gran)), "tfft_set_granularity")
 
 
 def get_tuning(N: int, dtype):

@@ -264,3 +264,40 @@ def test_noalloc_validates_on_host():
     assert _lib.NOALLOC_SCRATCH_BYTES == 64 << 20
     assert f(dummy, big, 1 << 24, 1, -1, 0, 0, 0.0, None, None) == _lib.TFFT_ESCRATCH
     assert f(dummy, big, 1 << 23, 1, -1, 1, 0, 0.0, None, None) == _lib.TFFT_ESCRATCH
+
+
+def test_granularity_and_second_target_validated_on_host():
+    lib = _lib.load()
+    assert lib.tfft_set_granularity(256, 0, 2) == _lib.TFFT_EINVAL
+    assert lib.tfft_set_granularity(0, 0, 1) == _lib.TFFT_EINVAL
+    assert lib.tfft_set_granularity(256, 3, 1) == _lib.TFFT_EINVAL
+    buf = (ctypes.c_longlong * 7)()
+    # fp32 checks per transaction by default, fp64 per group; none without ABFT
+    assert lib.tfft_route_info(4096, 0, 2, buf, 7) == _lib.TFFT_OK and buf[6] == 1
+    assert lib.tfft_route_info(4096, 0, 0, buf, 7) == _lib.TFFT_OK and buf[6] == 0
+    assert lib.tfft_route_info(4096, 1, 2, buf, 7) == _lib.TFFT_OK and buf[6] == 0
+    # per transaction, T is reduced to what the plan keeps (at most 16)
+    T0, k0 = ctypes.c_int(), ctypes.c_double()
+    assert lib.tfft_get_tuning(4096, 0, ctypes.byref(T0), ctypes.byref(k0)) == _lib.TFFT_OK
+    try:
+        assert lib.tfft_set_tuning(4096, 0, 32, 0.0) == _lib.TFFT_OK
+        assert lib.tfft_route_info(4096, 0, 2, buf, 7) == _lib.TFFT_OK and 1 <= buf[5] <= 16
+        assert lib.tfft_route_info(4096, 0, 0, buf, 7) == _lib.TFFT_OK and buf[5] == 32
+        assert lib.tfft_set_granularity(4096, 0, 0) == _lib.TFFT_OK
+        assert lib.tfft_route_info(4096, 0, 2, buf, 7) == _lib.TFFT_OK and buf[5] == 32 and buf[6] == 0
+    finally:
+        # every mode back to the loaded values (set_tuning applies to all modes)
+        assert lib.tfft_set_granularity(4096, 0, 1) == _lib.TFFT_OK
+        assert lib.tfft_set_tuning(4096, 0, T0.value, k0.value) == _lib.TFFT_OK
+    d = _lib.InjectDesc(signal=3, element=0, part=0, bit=3, precision=0, pass_=-1, stage=-1, two=1, signal2=3)
+    assert lib.tfft_inject_arm_desc(ctypes.byref(d)) == _lib.TFFT_EINVAL     # same signal twice
+    d.two, d.signal2 = 2, 4
+    assert lib.tfft_inject_arm_desc(ctypes.byref(d)) == _lib.TFFT_EINVAL
+    d.two, d.signal2 = 1, -1
+    assert lib.tfft_inject_arm_desc(ctypes.byref(d)) == _lib.TFFT_EINVAL
+    d.two, d.signal2 = 1, 4
+    assert lib.tfft_inject_arm_desc(ctypes.byref(d)) == _lib.TFFT_OK
+    # a second target outside the batch is refused by the call, before device work
+    dummy = 4096
+    assert lib.tfft_c2c(dummy, dummy + (1 << 20), 256, 4, -1, 0, 0, 0.0, None, None) == _lib.TFFT_EINVAL
+    assert lib.tfft_inject_disarm() == _lib.TFFT_OK
