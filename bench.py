@@ -392,6 +392,7 @@ def fp64_sweep(tf, torch, dev, args):
             continue
         xv, yv = x.view(-1, N), y.view(-1, N)
         ms = {}
+        counts.zero_()   # the previous length's injected flips are counted already
         for ft in (tf.FT_OFF, tf.FT_CORRECT):
             def step():
                 tf.fft_c2c(xv, dir=tf.FORWARD, ft_mode=ft, out=yv, counts=counts)
