@@ -322,13 +322,15 @@ def flip_value(v: complex, part: int, bit: int, real_dtype) -> complex:
 
 def injection_run(tf, torch, np, stream, counts, launch, y, N, batch, ft_ms, rng, dtype,
                   n_launch=100, direction=None):
-    """n_launch ABFT launches timed like the ABFT sweep (HIP events around
-    each launch), one of them (seeded) with a single-bit flip in a random
-    output element.  Reports the mean launch time and its overhead over the
-    sweep's, the counts, and the flip: its size relative to the hit signal's
-    norm, whether it is significant (an uncorrected flip of that size would
-    take the signal past the acceptance tolerance) and the hit signal's
-    relative distance, after correction, to its fault-free output."""
+    """Two windows of n_launch ABFT launches back to back (HIP events around
+    each launch): fault-free, then with one (seeded) launch carrying a
+    single-bit flip in a random output element.  Reports the mean launch
+    time of both, the injection overhead (one window over the other), the
+    extra time of the launch that carried the flip over the window's median,
+    the counts, and the flip: its size relative to the hit signal's norm,
+    whether it is significant (an uncorrected flip of that size would take
+    the signal past the acceptance tolerance) and the hit signal's relative
+    distance, after correction, to its fault-free output."""
     fp32 = dtype == torch.complex64
     tol = 2e-6 if fp32 else 1e-13
     nbits = 31 if fp32 else 63
@@ -338,20 +340,34 @@ def injection_run(tf, torch, np, stream, counts, launch, y, N, batch, ft_ms, rng
     part, bit = int(rng.integers(0, 2)), int(rng.integers(0, nbits))
     yv = y.view(-1, N)
     kept = torch.empty(N, dtype=dtype, device=y.device)
-    evs = []
-    for i in range(n_launch):
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        if i == hit:
-            tf.inject_arm(sig, elem, part, bit, dtype=dtype)
-        a.record(stream)
-        launch(N, tf.FT_CORRECT)
-        b.record(stream)
-        evs.append((a, b))
-        if i == hit:
-            kept.copy_(yv[sig])   # the corrected signal, before later launches overwrite it
-    torch.cuda.synchronize()
-    inj_ms = sum(a.elapsed_time(b) for a, b in evs) / n_launch
+
+    def window(inject):
+        # n_launch ABFT launches back to back, each bracketed by events; with
+        # inject, launch `hit` carries the flip
+        evs = []
+        for i in range(n_launch):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            if inject and i == hit:
+                tf.inject_arm(sig, elem, part, bit, dtype=dtype)
+            a.record(stream)
+            launch(N, tf.FT_CORRECT)
+            b.record(stream)
+            evs.append((a, b))
+            if inject and i == hit:
+                kept.copy_(yv[sig])   # the corrected signal, before later launches overwrite it
+        torch.cuda.synchronize()
+        return [a.elapsed_time(b) for a, b in evs]
+
+    # the fault-free window is the baseline, timed the same way in the same
+    # context (back-to-back launches of one length)
+    base = window(False)
+    counts.zero_()
+    times = window(True)
+    base_ms = sum(base) / n_launch
+    inj_ms = sum(times) / n_launch
+    others = sorted(t for i, t in enumerate(times) if i != hit)
+    hit_extra_us = 1e3 * (times[hit] - others[len(others) // 2])
     cd = tf.counts_dict(counts)
     launch(N, tf.FT_OFF)                      # fault-free output of the same input
     torch.cuda.synchronize()
@@ -363,7 +379,9 @@ def injection_run(tf, torch, np, stream, counts, launch, y, N, batch, ft_ms, rng
     after = torch.linalg.vector_norm(kept.to(torch.complex128) - clean).item() / norm
     return {
         "inj_ms": inj_ms,
-        "inj_overhead_pct": 100.0 * (inj_ms / ft_ms - 1.0),
+        "inj_base_ms": base_ms,
+        "inj_overhead_pct": 100.0 * (inj_ms / base_ms - 1.0),
+        "inj_hit_launch_extra_us": round(hit_extra_us, 2),
         "inj_flip": {"launch": hit, "signal": sig, "element": elem, "part": part, "bit": bit,
                      "delta_rel": delta_rel if math.isfinite(delta_rel) else "inf",
                      "significant": not (delta_rel <= tol),

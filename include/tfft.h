@@ -287,8 +287,12 @@ int tfft_routes(long long N, int precision, int ft_mode, long long* codes, int c
  * [2] N2 (row-pass length; 1 for a single pass), [3] radix stages of pass 0,
  * [4] radix stages of pass 1 (0 for a single pass), [5] transactions per
  * checksum group T as launched, [6] detection granularity as launched (see
- * tfft_set_granularity; 0 without ABFT).  TFFT_EUNSUPPORTED for a length
- * without a route. */
+ * tfft_set_granularity; 0 without ABFT), [7] and [8] sub-signals per
+ * workgroup of pass 0 and pass 1 (0 for a single pass).  A launch of
+ * directly addressed signals with G workgroups of s sub-signals forms G s
+ * groups: transaction b of group g transforms signal g + b G s (single pass;
+ * for a two-pass chunk, signal g + b * groups, each tile of a group taking
+ * the same signals).  TFFT_EUNSUPPORTED for a length without a route. */
 int tfft_route_info(long long N, int precision, int ft_mode, long long* info, int n);
 int tfft_set_route(long long N, int precision, long long code);
 int tfft_get_route(long long N, int precision, int ft_mode, long long* code);

@@ -1224,18 +1224,20 @@ int tfft_route_info(long long N, int precision, int ft_mode, long long* info, in
     const Tuning tu = get_tuning(precision, N, ft_mode);
     Route r;
     if (!route_for(precision, N, ft_mode, &r, tu.route)) return TFFT_EUNSUPPORTED;
-    long long v[7];
+    long long v[9];
     Tuning te;
     if (r.single) {
         v[0] = 1; v[1] = N; v[2] = 1; v[3] = r.single->n_stages; v[4] = 0;
+        v[7] = r.single->slots_per_block; v[8] = 0;
         te = effective(tu, ft_mode, r.single);
     } else {
         v[0] = 2; v[1] = r.N1; v[2] = r.N2; v[3] = r.col->n_stages; v[4] = r.row->n_stages;
+        v[7] = r.col->slots_per_block; v[8] = r.row->slots_per_block;
         te = effective(tu, ft_mode, r.col, r.row);
     }
     v[5] = te.T;
     v[6] = te.gran;
-    for (int i = 0; i < n && i < 7; ++i) info[i] = v[i];
+    for (int i = 0; i < n && i < 9; ++i) info[i] = v[i];
     return TFFT_OK;
 }
 

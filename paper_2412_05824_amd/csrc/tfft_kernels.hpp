@@ -11,7 +11,12 @@
 //     Sec. 3.1: no trigonometric functions in the kernel), applies the radix-R
 //     DFT in registers and writes output j to g*L*R + k + j*L (g = beta div L);
 //   * stages exchange data through LDS (Sec. 3.2); a slot runs T transactions
-//     back to back (Sec. 4.3 multi-transaction).
+//     back to back (Sec. 4.3 multi-transaction).  In a launch of G slots'
+//     worth of groups, transaction b of group g takes signal g + b G, so the
+//     workgroups running at one time stream neighbouring signals, as with
+//     one transaction each (consecutive signals per group would put every
+//     concurrent workgroup in its own region of memory; ragged batches, whose
+//     workspace is laid out by groups, keep consecutive signals).
 // Three geometries share that machinery:
 //   * Single : one whole signal per slot; slots of at most a wavefront sit
 //     side by side in a wave (lane = slot*P + t) and synchronise with
@@ -331,8 +336,13 @@ template <class V, class PL, bool IND> struct Geo {
                 t = tid;
                 slot = 0;
                 lds_off = 0;
-                sig0 = block * a.T;
-                sig_step = 1;
+                if constexpr (IND) {
+                    sig0 = block * a.T;
+                    sig_step = 1;
+                } else {
+                    sig0 = block;
+                    sig_step = nblocks;
+                }
                 sig_u0 = sig0;
                 lane_in = (unsigned)t;
             } else {
@@ -341,9 +351,14 @@ template <class V, class PL, bool IND> struct Geo {
                 slot = wave * PL::SPW + sigma;
                 lds_off = slot * Ns;
                 const long long wave_u = __builtin_amdgcn_readfirstlane(wave);
-                sig_u0 = (block * PL::WAVES + wave_u) * a.T * PL::SPW;
+                if constexpr (IND) {
+                    sig_u0 = (block * PL::WAVES + wave_u) * a.T * PL::SPW;
+                    sig_step = PL::SPW;
+                } else {
+                    sig_u0 = (block * PL::WAVES + wave_u) * PL::SPW;
+                    sig_step = nblocks * PL::WAVES * PL::SPW;
+                }
                 sig0 = sig_u0 + sigma;
-                sig_step = PL::SPW;
                 lane_in = (unsigned)sigma * (unsigned)a.N + (unsigned)t;
             }
             lane_out = lane_in;
@@ -362,8 +377,13 @@ template <class V, class PL, bool IND> struct Geo {
             const long long grp = bid / a.tiles;
             tile = (int)tl;
             line = (int)(tl * C + slot);
-            sig0 = grp * a.T;
-            sig_step = 1;
+            if constexpr (IND) {
+                sig0 = grp * a.T;
+                sig_step = 1;
+            } else {
+                sig0 = grp;
+                sig_step = G / a.tiles;   // signal groups in the launch
+            }
             sig_u0 = sig0;
             if constexpr (PL::KIND == kColPass) {
                 lane_in = (unsigned)t * (unsigned)a.N2 + (unsigned)slot;

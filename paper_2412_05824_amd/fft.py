@@ -116,11 +116,12 @@ def inject_arm(signal: int, element: int, part: int, bit: int, dtype=torch.compl
 
 
 def route_info(N: int, dtype=torch.complex64, ft_mode: int = 2) -> dict:
-    """The route a call takes now: passes, N1, N2, stages of each pass, T."""
+    """The route a call takes now: passes, N1, N2, stages of each pass, T,
+    granularity and sub-signals per workgroup of each pass."""
     import ctypes
-    buf = (ctypes.c_longlong * 7)()
-    _lib.check(_lib.load().tfft_route_info(N, _precision(dtype), ft_mode, buf, 7), f"tfft_route_info(N={N})")
-    keys = ("passes", "N1", "N2", "stages0", "stages1", "T", "gran")
+    buf = (ctypes.c_longlong * 9)()
+    _lib.check(_lib.load().tfft_route_info(N, _precision(dtype), ft_mode, buf, 9), f"tfft_route_info(N={N})")
+    keys = ("passes", "N1", "N2", "stages0", "stages1", "T", "gran", "slots0", "slots1")
     return {k: int(buf[i]) for i, k in enumerate(keys)}
 
 

@@ -173,9 +173,13 @@ def test_resident_loop_late_group(dev, dtype, N, variant):
     located and corrected like any other, and every other signal must match
     the plain kernel bit for bit."""
     batch = 2600
-    sig, elem, part = batch - 7, N // 3, 0
+    elem, part = N // 3, 0
     bit = 30 if dtype == torch.complex64 else 62
     tf.set_route(N, dtype, tf.route_code(1, variant, 0))
+    # one transaction per group: 2600 groups, several rounds of the resident
+    # workgroups (each group g is signal g); the flip is in the last round
+    tf.set_tuning(N, dtype, T=1)
+    sig = batch - 7
     try:
         x = synth.signals(batch, N, seed=4100 + N, dtype=NPDT[dtype])
         xd = torch.from_numpy(x).to(dev)

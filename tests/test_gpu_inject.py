@@ -19,6 +19,7 @@ import torch
 import oracle
 from oracle import abft_model as am
 import synth
+from groups import group_of
 
 pytestmark = pytest.mark.gpu
 
@@ -128,8 +129,12 @@ def test_location_fallback_just_above_threshold(dev):
     its fault-free output."""
     dtype, N, T = torch.complex128, 1024, 16
     old = tf.get_tuning(N, dtype)
+    old_gran = tf.route_info(N, dtype)["gran"]
     tf.set_tuning(N, dtype, T=T)
+    tf.set_granularity(N, dtype, 0)   # the location code belongs to the per-group check
     try:
+        info = tf.route_info(N, dtype)
+        assert info["gran"] == 0 and info["T"] == T, info
         kappa = tf.get_tuning(N, dtype)[1]
         batch = 4 * T
         x = synth.signals(batch, N, seed=9300, dtype=np.complex128)
@@ -141,8 +146,9 @@ def test_location_fallback_just_above_threshold(dev):
         fallbacks = detected = 0
         for trial in range(40):
             sig, elem, part = int(rng.integers(0, batch)), int(rng.integers(0, N)), int(rng.integers(0, 2))
-            g0 = (sig // T) * T
-            nu = float(np.sum(np.abs(x[g0:g0 + T]) ** 2))
+            members = group_of(sig, batch, info)
+            assert sig in members and len(members) == T
+            nu = float(np.sum(np.abs(x[members]) ** 2))
             tau = kappa * u * math.sqrt(N * math.log2(N)) * math.sqrt(nu)
             v = yc[sig, elem].real if part == 0 else yc[sig, elem].imag
             if v == 0.0:
@@ -172,6 +178,7 @@ def test_location_fallback_just_above_threshold(dev):
         assert fallbacks >= 1, (fallbacks, detected)
     finally:
         tf.set_tuning(N, dtype, T=old[0], kappa=old[1])
+        tf.set_granularity(N, dtype, old_gran)
 
 
 @pytest.mark.parametrize("mode", ["persistent", "per_size"])

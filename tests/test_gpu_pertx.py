@@ -25,6 +25,7 @@ import torch
 
 import oracle
 import synth
+from groups import group_of
 
 pytestmark = pytest.mark.gpu
 
@@ -57,12 +58,20 @@ def _rel(a, b):
 
 
 def test_route_reports_granularity(dev):
-    for N in (256, 4096, 1 << 16):
-        info = tf.route_info(N, torch.complex64)
-        assert info["gran"] == 1, info
-        assert tf.route_info(N, torch.complex64, ft_mode=0)["gran"] == 0
-    assert tf.route_info(1024, torch.complex128)["gran"] == 0
-    # a T beyond what the plan keeps is reduced to it
+    """The route reports the granularity of the shipped tuning table (none
+    without ABFT), follows tfft_set_granularity, and reduces a T beyond what
+    the plan keeps when checking per transaction."""
+    import json
+    table = json.load(open(tf._lib.TUNING_PATH))
+    for e in table["entries"]:
+        if e["ft_mode"] != 2:
+            continue
+        dtype = torch.complex64 if e["precision"] == "fp32" else torch.complex128
+        assert tf.route_info(e["N"], dtype)["gran"] == e["gran"], e
+        assert tf.route_info(e["N"], dtype, ft_mode=0)["gran"] == 0
+    for gran in (0, 1):
+        assert _with_T(1024, 4, lambda: tf.route_info(1024, torch.complex128)["gran"],
+                       dtype=torch.complex128, gran=gran) == gran
     info = _with_T(256, 32, lambda: tf.route_info(256, torch.complex64))
     assert 1 <= info["T"] <= 16, info
 
@@ -73,7 +82,13 @@ def test_every_bit_any_transaction_per_tx(dev, N):
         info = tf.route_info(N, torch.complex64)
         T = info["T"]
         assert info["gran"] == 1 and T >= 4, info
-        batch = 3 * T + 1   # a ragged last group
+        # three rounds of full groups over the workgroups' slots
+        batch = 3 * T * (info["slots0"] if info["passes"] == 1 else 1)
+        g0 = group_of(0, batch, info)
+        tail = group_of(batch - 1, batch, info)
+        assert len(g0) == T and len(tail) == T and g0 != tail, (g0, tail, info)
+        # transactions 0, middle and last of a group, and of another group
+        targets = [g0[0], g0[T // 2], g0[T - 1], tail[0], tail[-1]]
         x = synth.signals(batch, N, seed=9500 + N)
         xd = torch.from_numpy(x).to(dev)
         y0, _ = tf.fft_c2c(xd, ft_mode=tf.FT_OFF)
@@ -83,8 +98,7 @@ def test_every_bit_any_transaction_per_tx(dev, N):
         n_sig = 0
         for trial in range(24):
             pass_, stage = passes[trial % len(passes)]
-            # transactions 0, middle and last of a group, and the tail group
-            sig = [0, T // 2, T - 1, T + 1, 3 * T][trial % 5]
+            sig = targets[trial % 5]
             bit = int(rng.integers(0, 31))
             elem, part = int(rng.integers(0, N)), int(rng.integers(0, 2))
             tf.inject_arm(sig, elem, part, bit, pass_=pass_, stage=stage)
@@ -115,13 +129,18 @@ def test_two_faults_in_one_group_both_repaired(dev, N):
     sums of the transactions before the newer one, the newer from the whole
     group's, with the older already repaired."""
     def body():
-        T = tf.route_info(N, torch.complex64)["T"]
-        batch = 2 * T
+        info = tf.route_info(N, torch.complex64)
+        T = info["T"]
+        batch = 2 * T * (info["slots0"] if info["passes"] == 1 else 1)   # two rounds of full groups
         x = synth.signals(batch, N, seed=9600 + N)
         xd = torch.from_numpy(x).to(dev)
         y0, _ = tf.fft_c2c(xd, ft_mode=tf.FT_OFF)
         yc = y0.cpu().numpy()
-        for s1, s2, bit in [(1, 3, 25), (0, T - 1, 30), (T + 2, T + 3, 22)]:
+        ga, gb = group_of(1, batch, info), group_of(batch - 1, batch, info)
+        assert len(ga) == T and len(gb) >= 2, (ga, gb)
+        # two transactions of one group: neighbours, first and last, and in
+        # the last group
+        for s1, s2, bit in [(ga[1], ga[2], 25), (ga[0], ga[-1], 30), (gb[0], gb[-1], 22)]:
             tf.inject_arm(s1, N // 3, 0, bit, signal2=s2)
             y, counts = tf.fft_c2c(xd, ft_mode=tf.FT_CORRECT)
             c = tf.counts_dict(counts)
@@ -141,7 +160,8 @@ def test_two_faults_in_one_column_pass_group(dev):
     def body():
         info = tf.route_info(N, torch.complex64)
         T = info["T"]
-        batch = T
+        batch = T   # one group of the column pass
+        assert group_of(0, batch, info) == list(range(T))
         x = synth.signals(batch, N, seed=9650)
         xd = torch.from_numpy(x).to(dev)
         y0, _ = tf.fft_c2c(xd, ft_mode=tf.FT_OFF)
@@ -159,6 +179,8 @@ def test_in_place_one_fault_repaired_two_not(dev):
     N, T = 1024, 4
     def body():
         batch = 2 * T
+        info = tf.route_info(N, torch.complex64)
+        pair = group_of(1, batch, info)[:2]
         x = synth.signals(batch, N, seed=9700)
         y0, _ = tf.fft_c2c(torch.from_numpy(x).to(dev), ft_mode=tf.FT_OFF)
         yc = y0.cpu().numpy()
@@ -169,7 +191,7 @@ def test_in_place_one_fault_repaired_two_not(dev):
         assert c["detected"] == 1 and c["corrected"] + c["rebuilt"] == 1, c
         assert _rel(y.cpu().numpy()[2], yc[2]) <= TOL
         xd = torch.from_numpy(x).to(dev)
-        tf.inject_arm(1, 100, 0, 29, signal2=2)
+        tf.inject_arm(pair[0], 100, 0, 29, signal2=pair[1])
         y, counts = tf.fft_c2c(xd, ft_mode=tf.FT_CORRECT, out=xd)
         c = tf.counts_dict(counts)
         assert c["detected"] == 2 and c["uncorrectable"] == 2 and c["corrected"] + c["rebuilt"] == 0, c
