@@ -86,6 +86,10 @@ def parse():
     p.add_argument("--ragged-signals", type=int, default=10000)
     p.add_argument("--copy-ref", action="store_true",
                    help="only run a plain 1 GiB device copy (reference for counter scaling)")
+    p.add_argument("--study", choices=("roc", "ablation", "offline"), default=None,
+                   help="only run a study and print its JSON line: roc (detection vs false alarm over "
+                        "the threshold), ablation (ABFT granularity x transactions per group), offline "
+                        "(fused vs unfused ABFT)")
     return p.parse_args()
 
 
@@ -110,6 +114,12 @@ def main():
     stream = torch.cuda.current_stream(dev)
     if args.ragged_only:
         print(json.dumps({"ragged": ragged_compare(tf, synth, np, torch, dev, args)}), flush=True)
+        return
+    if args.study:
+        fn = {"roc": lambda: roc_study(tf, torch, np, dev),
+              "ablation": lambda: ablation_study(tf, torch, dev),
+              "offline": lambda: offline_study(tf, torch, dev)}[args.study]
+        print(json.dumps({"study": args.study, **fn()}), flush=True)
         return
     if args.copy_ref:
         src = torch.zeros(TOTAL_ELEMS, dtype=torch.complex64, device=dev)
@@ -581,6 +591,222 @@ def ragged_one(tf, synth, np, torch, dev, args, sizes, desc):
     del x, y
     torch.cuda.empty_cache()
     return out
+
+
+# ---------------------------------------------------------------------------
+# Studies (outside the headline step): ROC of the detection threshold and the
+# ABFT granularity ablation.
+# ---------------------------------------------------------------------------
+
+ROC_KAPPAS = (0.125, 0.25, 0.5, 1.0, 1.5, 2.0, 3.0, 4.0, 6.0, 8.0, 12.0, 16.0, 32.0, 64.0, 256.0)
+
+
+def roc_study(tf, torch, np, dev, N=1024, n_clean=2000, n_inj=1000, kappas=ROC_KAPPAS):
+    """Detection vs false alarm over the threshold factor kappa (Sec. 5.3
+    "Error Injection Analysis": 2000 normally distributed signals, 1000 of
+    them with one flipped bit of one value; the paper sweeps its threshold
+    delta, here tau = kappa u sqrt(N log2 N) sqrt(nu)).  Each signal is
+    checked on its own (per-transaction granularity, one transaction per
+    group).  Flips are drawn once (signal, element, real/imag, any bit of
+    the binary32/binary64 value) and replayed for every kappa; a flip is
+    significant when it moves its signal by more than the acceptance
+    tolerance (relative L2), the ones the check must not miss."""
+    out = {}
+    for dtype, prec, nbits, tol in ((torch.complex64, "fp32", 32, 2e-6), (torch.complex128, "fp64", 64, 1e-13)):
+        rdt = torch.float32 if prec == "fp32" else torch.float64
+        g = torch.Generator(device=dev)
+        g.manual_seed(6000)
+        x = torch.randn(n_clean, N, 2, dtype=rdt, device=dev, generator=g).view(dtype).view(n_clean, N)
+        y = torch.empty_like(x)
+        tf.fft_c2c(x, ft_mode=tf.FT_OFF, out=y)
+        yc = y.to(torch.complex128).cpu().numpy()
+        rng = np.random.default_rng(6001)
+        flips = []
+        for _ in range(n_inj):
+            s, e, part, bit = (int(rng.integers(0, n_clean)), int(rng.integers(0, N)),
+                               int(rng.integers(0, 2)), int(rng.integers(0, nbits)))
+            v = complex(yc[s, e])
+            delta = abs(flip_value(v, part, bit, np.float32 if prec == "fp32" else np.float64) - v)
+            rel = delta / float(np.linalg.norm(yc[s]))
+            flips.append((s, e, part, bit, not (rel <= tol)))
+        n_sig = sum(1 for f in flips if f[4])
+        T0, k0 = tf.get_tuning(N, dtype)
+        gran0 = tf.route_info(N, dtype)["gran"]
+        counts = tf.new_counts(dev)
+        pts = []
+        try:
+            tf.set_granularity(N, dtype, 1)
+            for kappa in kappas:
+                tf.set_tuning(N, dtype, 1, kappa)
+                counts.zero_()
+                tf.fft_c2c(x, ft_mode=tf.FT_DETECT, out=y, counts=counts)
+                fa = tf.counts_dict(counts)["detected"]
+                det = det_sig = 0
+                for s, e, part, bit, sig in flips:
+                    counts.zero_()
+                    tf.inject_arm(0, e, part, bit, dtype=dtype)
+                    tf.fft_c2c(x[s:s + 1], ft_mode=tf.FT_DETECT, out=y[:1], counts=counts)
+                    hit = tf.counts_dict(counts)["detected"] > 0
+                    det += hit
+                    det_sig += hit and sig
+                pts.append({"kappa": kappa, "false_alarm_rate": fa / n_clean, "detection_rate": det / n_inj,
+                            "detection_rate_significant": det_sig / max(1, n_sig)})
+        finally:
+            tf.set_tuning(N, dtype, T0, k0)
+            tf.set_granularity(N, dtype, gran0)
+        out[prec] = {"N": N, "clean_signals": n_clean, "injected": n_inj, "significant": n_sig,
+                     "default_kappa": k0, "points": pts}
+        del x, y
+    torch.cuda.empty_cache()
+    return {"workload": f"{n_clean} N(0,1) signals of {N} points per precision (seed 6000), "
+                        f"{n_inj} single-bit flips (seed 6001), FT_DETECT per transaction, T = 1",
+            **out}
+
+
+def ablation_study(tf, torch, dev, reps=5):
+    """ABFT granularity x transactions per group (Sec. 4.2-4.3; Table 2's
+    stepwise comparison, with this library's two fused forms): overhead of
+    the correcting kernels over the plain ones on a 1 GiB batch, per length,
+    for the check once per group (location code) at T = 1..32 and per
+    transaction at T = 1..16.  The route of each length stays the tuned one;
+    rows whose group size breaks the accuracy bound are marked (those
+    settings are never chosen by the autotuner)."""
+    from paper_2412_05824_amd import autotune
+    rows = []
+    for dtype, prec, lens in ((torch.complex64, "fp32", (1024, 4096, 1 << 16, 1 << 20)),
+                              (torch.complex128, "fp64", (1024, 4096, 1 << 16))):
+        esize = 8 if prec == "fp32" else 16
+        total = (1 << 30) // esize
+        rdt = torch.float32 if prec == "fp32" else torch.float64
+        g = torch.Generator(device=dev)
+        g.manual_seed(6100)
+        x = (torch.rand(total, 2, dtype=rdt, device=dev, generator=g) * 2 - 1).view(dtype).view(-1)
+        y = torch.empty_like(x)
+        counts = tf.new_counts(dev)
+        for N in lens:
+            xv, yv = x.view(-1, N), y.view(-1, N)
+            T0, k0 = tf.get_tuning(N, dtype)
+            info0 = tf.route_info(N, dtype)
+            gran0 = info0["gran"]
+
+            def tm(ft):
+                run = lambda: tf.fft_c2c(xv, ft_mode=ft, out=yv, counts=counts)
+                for _ in range(2):
+                    run()
+                torch.cuda.synchronize()
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                best = 1e30
+                for _ in range(3):
+                    a.record()
+                    for _ in range(reps):
+                        run()
+                    b.record()
+                    torch.cuda.synchronize()
+                    best = min(best, a.elapsed_time(b) / reps)
+                return best
+            try:
+                offs = []
+                for T in (1, 2):
+                    tf.set_tuning(N, dtype, T, 0)
+                    offs.append(tm(tf.FT_OFF))
+                off = min(offs)
+                longest = N if info0["passes"] == 1 else max(info0["N1"], info0["N2"])
+                for gran, Ts in ((0, (1, 2, 4, 8, 16, 32)), (1, (1, 2, 4, 8, 16))):
+                    tf.set_granularity(N, dtype, gran)
+                    seen = set()
+                    for T in Ts:
+                        tf.set_tuning(N, dtype, T, 0)
+                        teff = tf.route_info(N, dtype)["T"]
+                        if teff in seen:
+                            continue
+                        seen.add(teff)
+                        counts.zero_()
+                        ms = tm(tf.FT_CORRECT)
+                        within = gran == 1 or teff <= autotune.max_T(prec, longest, k0)
+                        rows.append({"precision": prec, "N": N, "granularity": "transaction" if gran else "group",
+                                     "T": teff, "ft_ms": round(ms, 4), "off_ms": round(off, 4),
+                                     "overhead_pct": round(100 * (ms / off - 1), 1),
+                                     "within_accuracy_bound": within,
+                                     "detected": tf.counts_dict(counts)["detected"]})
+            finally:
+                tf.set_tuning(N, dtype, T0, k0)
+                tf.set_granularity(N, dtype, gran0)
+        del x, y
+        torch.cuda.empty_cache()
+    return {"workload": "1 GiB uniform batch per length, forward, tuned route; plain kernel at its best of T = 1, 2",
+            "rows": rows}
+
+
+def offline_study(tf, torch, dev, reps=5):
+    """Fused vs offline two-side ABFT (Sec. 5.2 and Fig. 20's comparison,
+    with this library's own plain transform as the base): per length, on a
+    1 GiB batch, the plain transform, the fused correcting kernels and the
+    offline scheme (tfft_c2c_offline: separate checksum passes, transform of
+    the right-side sums, check and fix), without and with one seeded flip in
+    a window of 20 launches."""
+    rows = []
+    for dtype, prec, lens in ((torch.complex64, "fp32", (256, 4096, 1 << 16, 1 << 20, 1 << 22)),
+                              (torch.complex128, "fp64", (1024, 1 << 16))):
+        esize = 8 if prec == "fp32" else 16
+        total = (1 << 30) // esize
+        rdt = torch.float32 if prec == "fp32" else torch.float64
+        g = torch.Generator(device=dev)
+        g.manual_seed(6200)
+        x = (torch.rand(total, 2, dtype=rdt, device=dev, generator=g) * 2 - 1).view(dtype).view(-1)
+        y = torch.empty_like(x)
+        counts = tf.new_counts(dev)
+        for N in lens:
+            xv, yv = x.view(-1, N), y.view(-1, N)
+            batch = xv.shape[0]
+            runs = {
+                "plain": lambda: tf.fft_c2c(xv, ft_mode=tf.FT_OFF, out=yv),
+                "fused": lambda: tf.fft_c2c(xv, ft_mode=tf.FT_CORRECT, out=yv, counts=counts),
+                "offline": lambda: tf.fft_c2c_offline(xv, out=yv, counts=counts),
+            }
+            ms = {}
+            for k, fn in runs.items():
+                for _ in range(2):
+                    fn()
+                torch.cuda.synchronize()
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                best = 1e30
+                for _ in range(3):
+                    a.record()
+                    for _ in range(reps):
+                        fn()
+                    b.record()
+                    torch.cuda.synchronize()
+                    best = min(best, a.elapsed_time(b) / reps)
+                ms[k] = best
+            # one flip in a window of 20 launches, fused and offline
+            inj = {}
+            for k in ("fused", "offline"):
+                counts.zero_()
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record()
+                for i in range(20):
+                    if i == 7:
+                        tf.inject_arm(batch // 2, N // 3, 0, 29 if prec == "fp32" else 61, dtype=dtype)
+                    runs[k]()
+                b.record()
+                torch.cuda.synchronize()
+                c = tf.counts_dict(counts)
+                inj[k] = {"ms": a.elapsed_time(b) / 20, "detected": c["detected"],
+                          "repaired": c["corrected"] + c["rebuilt"]}
+            rows.append({"precision": prec, "N": N, "plain_ms": round(ms["plain"], 4),
+                         "fused_ms": round(ms["fused"], 4), "offline_ms": round(ms["offline"], 4),
+                         "fused_overhead_pct": round(100 * (ms["fused"] / ms["plain"] - 1), 1),
+                         "offline_overhead_pct": round(100 * (ms["offline"] / ms["plain"] - 1), 1),
+                         "fused_inj_overhead_pct": round(100 * (inj["fused"]["ms"] / ms["plain"] - 1), 1),
+                         "offline_inj_overhead_pct": round(100 * (inj["offline"]["ms"] / ms["plain"] - 1), 1),
+                         "inj_counts": {k: {kk: v[kk] for kk in ("detected", "repaired")} for k, v in inj.items()}})
+        del x, y
+        torch.cuda.empty_cache()
+    return {"workload": "1 GiB uniform batch per length, forward; with injection: one exponent-bit flip "
+                        "in a window of 20 launches", "rows": rows}
 
 
 if __name__ == "__main__":

@@ -82,6 +82,23 @@ typedef struct {
 int tfft_c2c(const void* x, void* y, long long N, long long batch, int dir, int precision,
              int ft_mode, double scale, tfft_ft_counts* counts, void* hip_stream);
 
+/* Offline (unfused) two-side ABFT, the comparison baseline for the fused
+ * kernels (Sec. 2.2 offline FT-FFT; Sec. 5.2): the same transform as
+ * tfft_c2c with TFFT_FT_CORRECT, but the checksums come from kernels of their
+ * own that read the batch again, as a library-based scheme computes them:
+ * an input pass (a^T x_b, |x_b|^2 and the right-side sum of each group of 16
+ * consecutive signals), the plain transform, the transform of the right-side
+ * sums, an output pass (e^T y_b) with a per-signal check against the same
+ * threshold as the fused kernels, and a fix that rebuilds a group's faulty
+ * signal as W(X e) - sum of the others (Eq. 5; two faults in a group are
+ * counted uncorrectable).  counts (device) is required; detected, rebuilt,
+ * uncorrectable and last_signal are updated.  Allocates a workspace per
+ * (device, stream) of about (2 + 1/16) x the batch (grow-only, like the
+ * two-pass workspace; a captured call that would allocate returns
+ * TFFT_ECAPTURE).  An armed injection hits the plain transform. */
+int tfft_c2c_offline(const void* x, void* y, long long N, long long batch, int dir, int precision,
+                     double scale, tfft_ft_counts* counts, void* hip_stream);
+
 /* Size of the static device scratch buffer of tfft_c2c_noalloc (bytes). */
 #define TFFT_NOALLOC_SCRATCH_BYTES (64ull << 20)
 

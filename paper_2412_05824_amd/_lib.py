@@ -39,6 +39,7 @@ _D = ctypes.c_double
 SIGNATURES = {
     "tfft_c2c": ([_VP, _VP, _LL, _LL, _I, _I, _I, _D, _VP, _VP], _I),
     "tfft_c2c_noalloc": ([_VP, _VP, _LL, _LL, _I, _I, _I, _D, _VP, _VP], _I),
+    "tfft_c2c_offline": ([_VP, _VP, _LL, _LL, _I, _I, _D, _VP, _VP], _I),
     "tfft_c2c_ragged": ([_VP, _VP, _VP, _I, _I, _I, _I, _VP, _VP], _I),
     "tfft_prepare": ([_LL, _LL, _I, _I, _VP], _I),
     "tfft_ragged_supported": ([_LL, _I], _I),

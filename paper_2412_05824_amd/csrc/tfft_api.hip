@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "tfft.h"
+#include "tfft_offline.hpp"
 #include "tfft_ragged.hpp"
 #include "tfft_workspace.hpp"
 
@@ -94,6 +95,8 @@ struct DeviceAlloc {
     }
 };
 WorkspacePool<DeviceAlloc> g_ws{DeviceAlloc{}};                          // (device, stream)
+WorkspacePool<DeviceAlloc> g_ws_off{DeviceAlloc{}};                      // offline ABFT, (device, stream)
+std::map<std::tuple<int, long long, int>, void*> g_left_full;            // (prec, N, device): e^T W of N
 std::map<std::tuple<int, long long, int>, Tuning> g_tuning;   // (prec, N, ft mode 0..2)
 
 struct Inject {
@@ -301,6 +304,23 @@ template <class R> int upload(const std::vector<R>& h, void** d) {
     return TFFT_OK;
 }
 
+// a = e^T W of length N: a_n = (1 - w_M^N) / (1 - w_M w_N^n), w_M = exp(-2 pi i / M)
+template <class R> int build_left(long long N, void** out) {
+    const long long M = (N % 3 == 0) ? 5 : 3;
+    std::vector<R> left;
+    long double nr, ni;
+    cis_neg(N, M, &nr, &ni);
+    const long double num_re = 1.0L - nr, num_im = -ni;
+    for (long long n = 0; n < N; ++n) {
+        long double wr, wi;   // w_M w_N^n = exp(-2 pi i (N + M n) / (M N))
+        cis_neg(N + M * n, M * N, &wr, &wi);
+        const long double dr = 1.0L - wr, di = -wi;
+        const long double den = dr * dr + di * di;
+        put(left, (num_re * dr + num_im * di) / den, (num_im * dr - num_re * di) / den);
+    }
+    return upload(left, out);
+}
+
 // stage tables w_{L R}^{j k} (k < L, j < R per stage) and a = e^T W
 template <class R> int build_sub(const KernelEntry& e, SubTables* out) {
     const long long N = e.Ns;
@@ -316,22 +336,9 @@ template <class R> int build_sub(const KernelEntry& e, SubTables* out) {
             }
         L *= Rr;
     }
-    // a_n = (1 - w_M^N) / (1 - w_M w_N^n), w_M = exp(-2 pi i / M)
-    const long long M = (N % 3 == 0) ? 5 : 3;
-    std::vector<R> left;
-    long double nr, ni;
-    cis_neg(N, M, &nr, &ni);
-    const long double num_re = 1.0L - nr, num_im = -ni;
-    for (long long n = 0; n < N; ++n) {
-        long double wr, wi;   // w_M w_N^n = exp(-2 pi i (N + M n) / (M N))
-        cis_neg(N + M * n, M * N, &wr, &wi);
-        const long double dr = 1.0L - wr, di = -wi;
-        const long double den = dr * dr + di * di;
-        put(left, (num_re * dr + num_im * di) / den, (num_im * dr - num_re * di) / den);
-    }
     int rc = upload(tw, &out->tw);
     if (rc != TFFT_OK) return rc;
-    return upload(left, &out->left);
+    return build_left<R>(N, &out->left);
 }
 
 // two-level table: w_N^m = hi[m >> bits] * lo[m & (2^bits - 1)]
@@ -1539,6 +1546,99 @@ int tfft_c2c(const void* x, void* y, long long N, long long batch, int dir, int 
 int tfft_c2c_noalloc(const void* x, void* y, long long N, long long batch, int dir, int precision,
                      int ft_mode, double scale, tfft_ft_counts* counts, void* hip_stream) {
     return c2c_impl(x, y, N, batch, dir, precision, ft_mode, scale, counts, hip_stream, true);
+}
+
+int tfft_c2c_offline(const void* x, void* y, long long N, long long batch, int dir, int precision,
+                     double scale, tfft_ft_counts* counts, void* hip_stream) {
+    if (N < 1 || batch < 0 || (dir != TFFT_FORWARD && dir != TFFT_INVERSE)) return TFFT_EINVAL;
+    if (check_precision(precision) != TFFT_OK) return TFFT_EINVAL;
+    if (!(is_pow2(N) || (N % 3 == 0 && is_pow2(N / 3)))) return TFFT_EUNSUPPORTED;
+    if (batch == 0) return TFFT_OK;
+    if (!x || !y || !counts) return TFFT_EINVAL;
+    const size_t S = precision == TFFT_FP32 ? 8 : 16;
+    if (((uintptr_t)x % S) || ((uintptr_t)y % S)) return TFFT_EALIGN;
+    const char* xb = static_cast<const char*>(x);
+    const char* yb = static_cast<const char*>(y);
+    const size_t bytes = (size_t)N * (size_t)batch * S;
+    if (xb != yb && xb < yb + bytes && yb < xb + bytes) return TFFT_EINVAL;
+    if (scale == 0.0) scale = dir == TFFT_INVERSE ? 1.0 / (double)N : 1.0;
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+
+    std::lock_guard<std::mutex> lk(g_mu);
+    ensure_registry();
+    // the plain transform on the route tuned for it
+    const Tuning tu = get_tuning(precision, N, TFFT_FT_OFF);
+    Route rt;
+    if (!route_for(precision, N, TFFT_FT_OFF, &rt, tu.route)) return TFFT_EUNSUPPORTED;
+    if (g_inj.armed && (g_inj.precision != precision || g_inj.signal >= batch || g_inj.signal2 >= batch ||
+                        g_inj.element >= N ||
+                        !inject_fits(g_inj, rt.single ? rt.single : rt.col, rt.single ? nullptr : rt.row)))
+        return TFFT_EINVAL;
+    const bool may_alloc = !capturing(stream);
+    const int dev = current_device();
+    // full-length left vector
+    void* left = nullptr;
+    {
+        auto key = std::make_tuple(precision, N, dev);
+        auto it = g_left_full.find(key);
+        if (it != g_left_full.end()) {
+            left = it->second;
+        } else {
+            if (!may_alloc) return TFFT_ECAPTURE;
+            int rc = precision == TFFT_FP32 ? build_left<float>(N, &left) : build_left<double>(N, &left);
+            if (rc != TFFT_OK) return rc;
+            g_left_full[key] = left;
+        }
+    }
+    // workspace: p and q, energies, flags, right-side sums
+    const long long groups = (batch + kOfflineT - 1) / kOfflineT;
+    auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    // p and q as complex double, energies as double (offline totals)
+    const size_t off_nu = up(2 * (size_t)batch * 16), off_fl = off_nu + up((size_t)batch * 8);
+    const size_t off_xs = off_fl + up((size_t)batch * 4);
+    const size_t ws_bytes = off_xs + (size_t)groups * (size_t)N * S;
+    void* ws = nullptr;
+    switch (g_ws_off.get(dev, stream, ws_bytes, may_alloc, &ws)) {
+        case WsResult::kOk: break;
+        case WsResult::kWouldAllocate: return TFFT_ECAPTURE;
+        default: return TFFT_ENOMEM;
+    }
+    char* w = static_cast<char*>(ws);
+    OfflineArgs o{};
+    o.x = x;
+    o.y = y;
+    o.N = N;
+    o.batch = batch;
+    o.left = left;
+    o.M = N % 3 == 0 ? 5 : 3;
+    o.conj = dir == TFFT_INVERSE ? 1 : 0;
+    o.scale = scale;
+    const double u = precision == TFFT_FP32 ? 0x1p-24 : 0x1p-53;
+    const double kappa = get_tuning(precision, N, TFFT_FT_CORRECT).kappa;
+    o.tau_coef = kappa * u * std::sqrt((double)N * std::log2((double)N));
+    o.cs = w;
+    o.nu = w + off_nu;
+    o.flags = w + off_fl;
+    o.xs = w + off_xs;
+    o.counts = counts;
+    const bool f32 = precision == TFFT_FP32;
+    hipError_t e = f32 ? offline_launch<float2>(o, stream, 0) : offline_launch<double2>(o, stream, 0);
+    if (e != hipSuccess) return hip_fail(e);
+    // the plain transform (the hook, when armed, hits it), then W x_s
+    const Inject inj = g_inj;
+    int rc = f32 ? transform<float2>(rt, x, y, N, batch, dir, scale, nullptr, tu, inj, stream, may_alloc)
+                 : transform<double2>(rt, x, y, N, batch, dir, scale, nullptr, tu, inj, stream, may_alloc);
+    if (rc != TFFT_OK) return rc;
+    const Inject none{};
+    rc = f32 ? transform<float2>(rt, o.xs, o.xs, N, groups, TFFT_FORWARD, 1.0, nullptr, tu, none, stream, may_alloc)
+             : transform<double2>(rt, o.xs, o.xs, N, groups, TFFT_FORWARD, 1.0, nullptr, tu, none, stream, may_alloc);
+    if (rc != TFFT_OK) return rc;
+    for (int step = 1; step <= 2; ++step) {
+        e = f32 ? offline_launch<float2>(o, stream, step) : offline_launch<double2>(o, stream, step);
+        if (e != hipSuccess) return hip_fail(e);
+    }
+    g_inj = Inject{};   // one-shot
+    return TFFT_OK;
 }
 
 int tfft_ragged_supported(long long N, int precision) {

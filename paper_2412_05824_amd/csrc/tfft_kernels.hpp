@@ -547,10 +547,15 @@ template <class V, class PL, bool IND> struct Geo {
             }
         }
     }
-    // any lane of the synchronisation domain (wave or workgroup)
+    // any lane of the synchronisation domain (wave or workgroup), for flags
+    // that are identical on every lane of a slot (decisions taken from
+    // reduced values).  A workgroup that synchronises as a whole holds one
+    // slot, or tiles whose waves each carry lanes of every slot, so every
+    // wave sees every slot's flag and its own vote is the workgroup's: no
+    // barrier is needed, and all waves take the same branch.
     __device__ __forceinline__ bool domain_any(bool f) const {
-        if constexpr (BLOCK) return __syncthreads_or(f ? 1 : 0) != 0;
-        else return __any(f ? 1 : 0) != 0;
+        static_assert(!BLOCK || PL::SLOTS == 1 || PL::TILE, "a wave must see every slot of its workgroup");
+        return __any(f ? 1 : 0) != 0;
     }
 
     // ---- per-transaction checking ----

@@ -87,6 +87,27 @@ def fft_c2c_noalloc(x: torch.Tensor, out: torch.Tensor, dir: int = -1, ft_mode: 
     return out, counts
 
 
+def fft_c2c_offline(x: torch.Tensor, dir: int = -1, out: torch.Tensor | None = None,
+                    counts: torch.Tensor | None = None, scale: float = 0.0):
+    """tfft_c2c_offline: the transform with offline (unfused) two-side ABFT,
+    the comparison baseline for the fused kernels."""
+    if not x.is_cuda or x.dim() != 2 or not x.is_contiguous():
+        raise ValueError("x must be a contiguous [batch, N] device tensor")
+    prec = _precision(x.dtype)
+    batch, N = x.shape
+    if out is None:
+        out = torch.empty_like(x)
+    elif out.shape != x.shape or out.dtype != x.dtype or not out.is_contiguous() or out.device != x.device:
+        raise ValueError("out must match x in shape, dtype, device and be contiguous")
+    if counts is None:
+        counts = new_counts(x.device)
+    with torch.cuda.device(x.device):
+        st = _lib.load().tfft_c2c_offline(x.data_ptr(), out.data_ptr(), N, batch, dir, prec, float(scale),
+                                          counts.data_ptr(), _stream_ptr(x.device))
+    _lib.check(st, f"tfft_c2c_offline(N={N}, batch={batch}, dir={dir})")
+    return out, counts
+
+
 def prepare(N: int, dtype=torch.complex64, ft_mode: int = 2, batch: int = 0, device=None) -> None:
     """Build the tables of length N and, for batch > 0, reserve the two-pass
     workspace for up to `batch` signals on torch's current stream (call

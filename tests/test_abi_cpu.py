@@ -278,10 +278,13 @@ def test_granularity_and_second_target_validated_on_host():
     assert lib.tfft_set_granularity(0, 0, 1) == _lib.TFFT_EINVAL
     assert lib.tfft_set_granularity(256, 3, 1) == _lib.TFFT_EINVAL
     buf = (ctypes.c_longlong * 7)()
-    # fp32 checks per transaction by default, fp64 per group; none without ABFT
-    assert lib.tfft_route_info(4096, 0, 2, buf, 7) == _lib.TFFT_OK and buf[6] == 1
-    assert lib.tfft_route_info(4096, 0, 0, buf, 7) == _lib.TFFT_OK and buf[6] == 0
-    assert lib.tfft_route_info(4096, 1, 2, buf, 7) == _lib.TFFT_OK and buf[6] == 0
+    # the granularity of the loaded tuning table; none without ABFT
+    table = {(e["precision"], e["N"]): e for e in json.load(open(_lib.TUNING_PATH))["entries"]
+             if e.get("ft_mode", 2) == 2}
+    for prec, p in (("fp32", 0), ("fp64", 1)):
+        assert lib.tfft_route_info(4096, p, 2, buf, 7) == _lib.TFFT_OK
+        assert buf[6] == table[(prec, 4096)]["gran"]
+        assert lib.tfft_route_info(4096, p, 0, buf, 7) == _lib.TFFT_OK and buf[6] == 0
     # per transaction, T is reduced to what the plan keeps (at most 16)
     T0, k0 = ctypes.c_int(), ctypes.c_double()
     assert lib.tfft_get_tuning(4096, 0, ctypes.byref(T0), ctypes.byref(k0)) == _lib.TFFT_OK
