@@ -17,6 +17,9 @@ Printed as ONE JSON line, with:
   * cpu_baseline: the fp64 CPU oracle on a bounded sample of the same sweep;
   * fp64_sweep: complex128 forward and inverse, N = 2^6..2^20, batch 2^26/N,
     standard-normal inputs, ABFT off and correct, seeded single-bit flips;
+  * three_pass: complex64 forward transforms of N = 2^23..2^29 as three
+    launches, ABFT off and correct, per-pass kernel times, one seeded flip
+    in each pass;
   * autograd: loss = sum(w * |FFT(x)|^2) on x complex64 [16384, 4096], one
     forward + backward (ABFT-protected adjoint) per step;
   * ragged: 10,000 signals with lengths drawn uniformly from {2^k, 3*2^k :
@@ -81,6 +84,7 @@ def parse():
     p.add_argument("--no-ragged", action="store_true", help="skip the ragged-batch comparison")
     p.add_argument("--no-fp64", action="store_true", help="skip the fp64 forward+inverse sweep")
     p.add_argument("--no-autograd", action="store_true", help="skip the autograd step")
+    p.add_argument("--no-three", action="store_true", help="skip the three-pass sweep (N = 2^23..2^29)")
     p.add_argument("--ragged-only", action="store_true",
                    help="only run the ragged-batch comparison (for profiling its kernels)")
     p.add_argument("--ragged-signals", type=int, default=10000)
@@ -198,7 +202,7 @@ def main():
     if kernels:
         k0 = max(kernels, key=lambda k: k["total_ms"])
         _lib.check(lib.tfft_profile_only(0 if k0["precision"] == "fp32" else 1,
-                                         ("single", "colpass", "rowpass", "ragged").index(k0["kind"]),
+                                         ("single", "colpass", "rowpass", "ragged", "colpass3", "rowpass3").index(k0["kind"]),
                                          k0["Ns"], k0["ft"]), "tfft_profile_only")
     total_ms = time_sweep(tf.FT_CORRECT, args.steps, 0, per_kernel=per_kernel_ms)
     timed = [k for k in _lib.profile_read() if k["ft"] >= 2]
@@ -236,6 +240,7 @@ def main():
     if not args.no_ragged:
         ragged = ragged_compare(tf, synth, np, torch, dev, args)
 
+    three = None if args.no_three else three_pass_sweep(tf, torch, np, dev, args, x)
     fp64 = None if args.no_fp64 else fp64_sweep(tf, torch, dev, args)
     grad = None if args.no_autograd else autograd_step(tf, torch, dev, args)
 
@@ -315,6 +320,7 @@ def main():
         "sweep": {str(k): v for k, v in sweep.items()},
         "ragged": ragged,
         "fp64_sweep": fp64,
+        "three_pass": three,
         "autograd": grad,
     }
     print(json.dumps(out), flush=True)
@@ -399,6 +405,103 @@ def injection_run(tf, torch, np, stream, counts, launch, y, N, batch, ft_ms, rng
                      "hit_signal_within_tol": after <= tol},
         "inj_counts": {k: cd[k] for k in ("detected", "corrected", "rebuilt", "uncorrectable")},
     }
+
+
+def three_pass_sweep(tf, torch, np, dev, args, x1g):
+    """complex64 forward transforms of N = 2^23..2^29 on the three-pass
+    route (three launches per chunk of signals), batch 2^27 / N (at least
+    one signal; the headline input for N <= 2^27, a seeded device input
+    beyond), ABFT off and correct, with the per-pass kernel times from the
+    launch-timing log and one seeded single-bit flip in each pass checked
+    against the fault-free output.  GB/s counts the transform's input and
+    output once (2 N batch 8 bytes); each pass moves that much again."""
+    from paper_2412_05824_amd import _lib
+    lib = _lib.load()
+    dt = torch.complex64
+    counts = tf.new_counts(dev)
+    rng = np.random.default_rng(2300)
+    reps = max(3, args.steps // 2)
+    out = {}
+    for lg in range(23, 30):
+        N = 1 << lg
+        if not tf.supported(N, dt):
+            continue
+        info = tf.route_info(N, dt)
+        if N <= TOTAL_ELEMS:
+            x = x1g.view(-1, N)
+        else:
+            g = torch.Generator(device=dev)
+            g.manual_seed(2300 + lg)
+            x = (torch.rand(N, 2, dtype=torch.float32, device=dev, generator=g) * 2 - 1).view(dt).view(1, N)
+        y = torch.empty_like(x)
+        batch = x.shape[0]
+        tf.prepare(N, dt, tf.FT_CORRECT, batch=batch, device=dev)
+        tf.prepare(N, dt, tf.FT_OFF, batch=batch, device=dev)
+        ms = {}
+        counts.zero_()
+        for ft in (tf.FT_OFF, tf.FT_CORRECT):
+            for _ in range(max(1, args.warmup)):
+                tf.fft_c2c(x, ft_mode=ft, out=y, counts=counts)
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(reps):
+                tf.fft_c2c(x, ft_mode=ft, out=y, counts=counts)
+            b.record()
+            torch.cuda.synchronize()
+            ms[ft] = a.elapsed_time(b) / reps
+        clean = tf.counts_dict(counts)["detected"]
+        # per-pass kernel times (every launch bracketed by events)
+        lib.tfft_profile_only(-1, -1, -1, -1)
+        lib.tfft_profile(1)
+        _lib.profile_read()
+        for _ in range(reps):
+            tf.fft_c2c(x, ft_mode=tf.FT_CORRECT, out=y, counts=counts)
+        torch.cuda.synchronize()
+        passes = [{"kind": k["kind"], "Ns": k["Ns"], "launches": k["launches"],
+                   "avg_us": round(1e3 * k["total_ms"] / k["launches"], 2),
+                   "gbs": round(k["bytes"] / (k["total_ms"] * 1e-3) / 1e9, 1)}
+                  for k in _lib.profile_read()]
+        lib.tfft_profile(0)
+        # one flip per pass, the hit signal against its fault-free output
+        tf.fft_c2c(x, ft_mode=tf.FT_OFF, out=y)
+        flips = []
+        for pass_ in (0, 1, 2):
+            sig, elem = int(rng.integers(0, batch)), int(rng.integers(0, N))
+            part, bit = int(rng.integers(0, 2)), int(rng.integers(20, 31))
+            ref = y[sig].clone()
+            counts.zero_()
+            tf.inject_arm(sig, elem, part, bit, dtype=dt, pass_=pass_)
+            yi = torch.empty_like(y)
+            tf.fft_c2c(x, ft_mode=tf.FT_CORRECT, out=yi, counts=counts)
+            torch.cuda.synchronize()
+            c = tf.counts_dict(counts)
+            after = (torch.linalg.vector_norm((yi[sig] - ref).to(torch.complex128)).item() /
+                     torch.linalg.vector_norm(ref.to(torch.complex128)).item())
+            flips.append({"pass": pass_, "signal": sig, "element": elem, "part": part, "bit": bit,
+                          "counts": {k: c[k] for k in ("detected", "corrected", "rebuilt", "uncorrectable")},
+                          "hit_signal_rel_after": after, "hit_signal_within_tol": after <= 2e-6,
+                          "others_unchanged": bool(torch.equal(torch.cat([yi[:sig], yi[sig + 1:]]),
+                                                               torch.cat([y[:sig], y[sig + 1:]])))})
+            del yi
+        nbytes = 2 * N * batch * 8
+        out[str(N)] = {"route": [info["N1"], info["N2"], info["N3"]], "batch": batch,
+                       "ft_ms": round(ms[tf.FT_CORRECT], 4), "off_ms": round(ms[tf.FT_OFF], 4),
+                       "ft_gbs": round(nbytes / (ms[tf.FT_CORRECT] * 1e-3) / 1e9, 1),
+                       "off_gbs": round(nbytes / (ms[tf.FT_OFF] * 1e-3) / 1e9, 1),
+                       "ft_overhead_pct": round(100.0 * (ms[tf.FT_CORRECT] / ms[tf.FT_OFF] - 1.0), 1),
+                       "clean_detected": clean, "passes": passes, "flips": flips}
+        print(f"# three-pass N=2^{lg}: {out[str(N)]['ft_gbs']} GB/s ABFT on, "
+              f"{out[str(N)]['off_gbs']} off", file=sys.stderr, flush=True)
+        del y
+        if N > TOTAL_ELEMS:
+            del x
+        torch.cuda.empty_cache()
+    return {"workload": "complex64 forward C2C, N=2^23..2^29 as three launches (column pass N1, column "
+                        "pass N2 with the outer twiddle, row pass N3 with the transposed store), "
+                        "batch=max(1, 2^27/N), inputs U[-1,1), ABFT correct vs off, one seeded flip per pass",
+            "per_n": out}
 
 
 def fp64_sweep(tf, torch, dev, args):

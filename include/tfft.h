@@ -228,12 +228,19 @@ int tfft_supported(long long N, int precision);
  *              position k of its N1-point sequence; after the last stage the
  *              intermediate value of row k), in the row pass n1 + N1 * k (row
  *              n1, position k of its N2-point sequence; after the last stage
- *              output element n1 + N1 * k).
+ *              output element n1 + N1 * k); for a three-pass length N = N1 *
+ *              N2 * N3 (M = N2 * N3), where the value is stored within the
+ *              signal: pass 0 k1 * M + m (column m), pass 1 k1 * M + k2 * N3
+ *              + n3 (row k1, column n3, position k2), pass 2 the output
+ *              element k1 + N1 * (k2 + N2 * k3) (row k1 of pair k2, position
+ *              k3); after an earlier stage, the position the stage's
+ *              sequence holds there.
  *   part       0: real part, 1: imaginary part.
  *   bit        bit of the IEEE binary32 (0..31) or binary64 (0..63) value.
  *   precision  TFFT_FP32 or TFFT_FP64; must match the call.
  *   pass       -1: the last pass; 0: the single pass or the column pass;
- *              1: the row pass.
+ *              1: the row pass (three passes: the second column pass); 2:
+ *              the third pass of a three-pass length.
  *   stage      -1: after the last radix stage (an output value of the pass,
  *              before its checksum and store); s >= 0: after radix stage s,
  *              on the value held between stage s and s + 1.
@@ -278,19 +285,29 @@ int tfft_set_granularity(long long N, int precision, int gran);
 int tfft_get_tuning(long long N, int precision, int* T, double* kappa);
 
 /* Lengths above the single-pass limit run as a column pass and a row pass
- * over chunks of signals whose intermediate (chunk_bytes, default 128 MiB)
- * lives in a library workspace.  Sets the chunk size for (N, precision);
- * 0 keeps the current value. */
+ * (three passes: two intermediates) over chunks of signals whose
+ * intermediate (chunk_bytes, default 128 MiB, at least one signal) lives in
+ * a library workspace.  Sets the chunk size for (N, precision); 0 keeps the
+ * current value. */
 int tfft_set_chunk(long long N, int precision, long long chunk_bytes);
 
-/* Routes.  A length runs either as one single-pass kernel or as a column
- * pass of length n1 followed by a row pass of length N/n1 (the multi-pass
- * decomposition of Sec. 3.1), each from one of the compiled plan variants
- * of that length (tile width).  A route is coded as
- *     code = n1 | va << 32 | vb << 40
- * with n1 = 1 for a single pass of plan variant va, or n1 > 1 for a column
- * pass of variant va and a row pass of variant vb; code 0 is the default
- * policy (single pass when built, else the most balanced split, variant 0).
+/* Routes.  A length runs as one single-pass kernel, as a column pass of
+ * length n1 followed by a row pass of length N/n1 (the multi-pass
+ * decomposition of Sec. 3.1), or as three passes N = n1 * n2 * n3 (the
+ * three launches Sec. 3.3 gives lengths beyond 2^22): a column pass of n1
+ * over the M = n2 * n3 columns, a column pass of n2 over the n3 columns of
+ * each row of M with the twiddle w_N^{k1 m} applied at its load, and a row
+ * pass of n3 with the twiddle w_M^{k2 n3} whose store transposes to the
+ * output order k1 + n1 * (k2 + n2 * k3); up to N = 2^29 in single
+ * precision.  Each pass takes one of the compiled plan variants of its
+ * length (tile width).  A route is coded as
+ *     code = n1 | va << 32 | vb << 40 | log2(n2) << 48
+ * with n1 = 1 for a single pass of plan variant va; n1 > 1 and no n2 for a
+ * column pass of variant va and a row pass of variant vb; n1 > 1 and n2 for
+ * three passes, column pass variant va (vb = 0).  Code 0 is the default
+ * policy (single pass when built, else the most balanced two-pass split,
+ * else the three-pass split with the smallest largest length, variants 0).
+ * The passes of three-pass routes check groups of one signal (T = 1).
  * tfft_routes writes up to cap codes built for (N, precision, ft_mode) and
  * returns how many exist.  tfft_set_route fixes the route of (N, precision)
  * in every ABFT mode (TFFT_EUNSUPPORTED if not built).  tfft_get_route
@@ -300,12 +317,14 @@ int tfft_set_chunk(long long N, int precision, long long chunk_bytes);
 int tfft_routes(long long N, int precision, int ft_mode, long long* codes, int cap);
 
 /* The route tfft_c2c takes now for (N, precision, ft_mode): up to n values
- * [0] passes (1 or 2), [1] N1 (column-pass length; N for a single pass),
- * [2] N2 (row-pass length; 1 for a single pass), [3] radix stages of pass 0,
- * [4] radix stages of pass 1 (0 for a single pass), [5] transactions per
+ * [0] passes (1, 2 or 3), [1] N1 (column-pass length; N for a single pass),
+ * [2] N2 (length of pass 1; 1 for a single pass), [3] radix stages of pass
+ * 0, [4] radix stages of pass 1 (0 for a single pass), [5] transactions per
  * checksum group T as launched, [6] detection granularity as launched (see
  * tfft_set_granularity; 0 without ABFT), [7] and [8] sub-signals per
- * workgroup of pass 0 and pass 1 (0 for a single pass).  A launch of
+ * workgroup of pass 0 and pass 1 (0 for a single pass), [9] N3 (length of
+ * pass 2; 1 below three passes), [10] radix stages and [11] sub-signals per
+ * workgroup of pass 2 (0 below three passes).  A launch of
  * directly addressed signals with G workgroups of s sub-signals forms G s
  * groups: transaction b of group g transforms signal g + b G s (single pass;
  * for a two-pass chunk, signal g + b * groups, each tile of a group taking
@@ -317,6 +336,7 @@ int tfft_get_route(long long N, int precision, int ft_mode, long long* code);
 /* Load a tuning table (JSON, as written by the autotuner):
  *   {"entries": [{"precision": "fp32" | "fp64", "N": n, "ft_mode": f,
  *                 "split_n1": s, "variant_a": va, "variant_b": vb,
+ *                 "split_n2": n2 (three passes; absent or 0: two),
  *                 "T": t, "kappa": k, "chunk_bytes": b, ...}, ...]}
  * Each entry sets the fields it names for (N, precision) in ABFT mode f, or
  * in every mode when ft_mode is absent; other keys are ignored.  All
@@ -339,14 +359,15 @@ int tfft_calibration(int on);
  * kernel "precision kind Ns ft launches total_ms algorithmic_bytes" into buf
  * (host memory of buflen bytes), clears the log and returns the text length;
  * with buf == NULL it returns the size needed instead.  kind is single,
- * colpass or rowpass; algorithmic bytes count each launch's input read and
- * output write once. */
+ * colpass, rowpass, ragged, colpass3 or rowpass3; algorithmic bytes count
+ * each launch's input read and output write once. */
 int tfft_profile(int on);
 int tfft_profile_read(char* buf, long long buflen);
 
 /* Restrict the per-launch timing above to the launches of one kernel:
  * precision (TFFT_FP32 / TFFT_FP64), kind (0 single, 1 colpass, 2 rowpass,
- * 3 ragged persistent), sub-length Ns and ABFT mode ft; -1 in a field
+ * 3 ragged persistent, 4 colpass3, 5 rowpass3: the second and third pass of
+ * a three-pass length), sub-length Ns and ABFT mode ft; -1 in a field
  * matches any value (all -1, the default, times every launch).  Events cost
  * the stream a few microseconds per launch, so a benchmark that times one
  * kernel live brackets only that kernel's launches.  Returns TFFT_EINVAL

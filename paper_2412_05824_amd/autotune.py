@@ -108,7 +108,8 @@ def tune(precisions, logs, modes=(2, 0), reps=5, warmup=2, total_bytes=1 << 30, 
                 codes = tf.routes(N, dtype, ft) if best_code is None else [best_code]
                 for code in codes:
                     n1, va, vb = tf.route_parts(code)
-                    longest = N if n1 == 1 else max(n1, N // n1)
+                    n2 = tf.route_n2(code)
+                    longest = N if n1 == 1 else (max(n1, n2, N // (n1 * n2)) if n2 else max(n1, N // n1))
                     chunks = [None] if n1 == 1 else [c << 20 for c in CHUNKS_MIB]
                     cands = []
                     for gran in (GRANS[prec] if ft else (0,)):
@@ -138,10 +139,11 @@ def tune(precisions, logs, modes=(2, 0), reps=5, warmup=2, total_bytes=1 << 30, 
                             err = torch.linalg.vector_norm(yv - rv).item() / ref_norm
                             ok = det == 0 and err <= 2 * TOL[prec]
                             gbs = 2 * total * esize / (ms * 1e-3) / 1e9
-                            log(f"{prec} N={N} ft={ft} n1={n1} v={va}/{vb} gran={gran} T={T} chunk={chunk} {ms:.4f} ms "
+                            log(f"{prec} N={N} ft={ft} n1={n1} n2={n2} v={va}/{vb} gran={gran} T={T} chunk={chunk} {ms:.4f} ms "
                                 f"{gbs:.1f} GB/s err={err:.2e} det={det}{'' if ok else ' REJECTED'}")
                             if ok and (best is None or ms < best["ms"]):
                                 best = {"precision": prec, "N": N, "ft_mode": ft, "split_n1": n1,
+                                        "split_n2": n2,
                                         "variant_a": va, "variant_b": vb, "T": T, "gran": gran,
                                         "kappa": KAPPA[prec],
                                         "ms": round(ms, 5), "gbs": round(gbs, 1)}
@@ -151,7 +153,8 @@ def tune(precisions, logs, modes=(2, 0), reps=5, warmup=2, total_bytes=1 << 30, 
                     entries.append(best)
                     log(f"best {prec} N={N} ft={ft}: {best}")
                     if best_code is None:
-                        best_code = tf.route_code(best["split_n1"], best["variant_a"], best["variant_b"])
+                        best_code = tf.route_code(best["split_n1"], best["variant_a"], best["variant_b"],
+                                                  best["split_n2"])
                 # back to the defaults before the next mode / length
                 tf.set_route(N, dtype, 0)
                 tf.set_tuning(N, dtype, T0, k0)

@@ -104,7 +104,7 @@ struct Inject {
     long long signal = -1, element = 0;
     long long signal2 = -1;   // a second signal hit the same way (-1: none)
     int part = 0, bit = 0, precision = 0;
-    int pass = -1;    // -1 last pass, 0 first (single or column pass), 1 row pass
+    int pass = -1;    // -1 last pass, 0 first (single or column pass), 1 row pass (three passes: 1, 2)
     int stage = -1;   // -1 after the last radix stage, else after stage `stage`
 } g_inj;
 
@@ -124,13 +124,16 @@ template <class R> void arm_launch(KCall<R>& k, const Inject& inj, int pass, int
     k.inj_stage = inj.stage < 0 ? stages - 1 : inj.stage;
 }
 
-// an armed injection fits a route: its pass exists and so does its stage
-bool inject_fits(const Inject& inj, const KernelEntry* first, const KernelEntry* second) {
+// an armed injection fits a route of passes first (, second (, third)):
+// its pass exists and so does its stage
+bool inject_fits(const Inject& inj, const KernelEntry* first, const KernelEntry* second,
+                 const KernelEntry* third = nullptr) {
     if (!inj.armed) return true;
-    const int passes = second ? 2 : 1;
+    const KernelEntry* e[3] = {first, second, third};
+    const int passes = third ? 3 : (second ? 2 : 1);
     if (inj.pass >= passes || inj.pass < -1) return false;
-    const KernelEntry* e = (inj.pass == 0 || passes == 1) ? first : second;
-    return inj.stage < e->n_stages && inj.stage >= -1;
+    const KernelEntry* p = e[inj.pass < 0 ? passes - 1 : inj.pass];
+    return inj.stage < p->n_stages && inj.stage >= -1;
 }
 
 bool g_stats = false;   // calibration mode: kernels record max |D0| / tau
@@ -160,6 +163,7 @@ void ensure_registry() {
     register_fp32_tiles(*g_entries);
     register_fp64_single(*g_entries);
     register_fp64_tiles(*g_entries);
+    register_fp32_three(*g_entries);
     register_fp32_ragged_single(*g_entries);
     register_fp32_ragged_tiles(*g_entries);
     for (const KernelEntry& e : *g_entries) {
@@ -174,25 +178,43 @@ const KernelEntry* find_entry(int precision, int kind, long long Ns, int ft, int
     return it == g_by_key.end() ? nullptr : it->second;
 }
 
-// How a length is executed: one single-pass kernel, or a column pass of
-// length N1 and a row pass of length N2.
+// How a length is executed: one single-pass kernel, a column pass of
+// length N1 and a row pass of length N2, or three passes N = N1 N2 N3
+// (Sec. 3.3: three launches beyond 2^22): a column pass of N1 over the
+// M = N2 N3 columns, a column pass of N2 over the N3 columns of each row
+// (b, k1) with the outer twiddle w_N^{k1 m} at its load, and a row pass of
+// N3 over each (b, k2) with the twiddle w_M^{k2 n3} that stores the output
+// transposed, k1 + N1 (k2 + N2 k3).
 struct Route {
     const KernelEntry* single = nullptr;
     const KernelEntry* col = nullptr;
-    const KernelEntry* row = nullptr;
-    long long N1 = 0, N2 = 0;
+    const KernelEntry* row = nullptr;    // two passes
+    const KernelEntry* col3 = nullptr;   // three passes: second and third
+    const KernelEntry* row3 = nullptr;
+    long long N1 = 0, N2 = 0, N3 = 0;
+    int passes() const { return single ? 1 : (row3 ? 3 : 2); }
+    // entry of pass i
+    const KernelEntry* pass(int i) const {
+        if (single) return i == 0 ? single : nullptr;
+        if (i == 0) return col;
+        if (row3) return i == 1 ? col3 : (i == 2 ? row3 : nullptr);
+        return i == 1 ? row : nullptr;
+    }
 };
 
-// Route codes: n1 | va << 32 | vb << 40.  n1 = 1: single pass, plan variant
-// va; n1 > 1: column pass of n1 points (variant va), then row pass of N/n1
-// (variant vb); code 0: the default policy (single pass when built, else
-// the most balanced split, variants 0).
-constexpr long long route_code(long long n1, int va, int vb) {
-    return n1 | ((long long)va << 32) | ((long long)vb << 40);
+// Route codes: n1 | va << 32 | vb << 40 | lg2(n2) << 48.  n1 = 1: single
+// pass, plan variant va; n1 > 1 with no n2: column pass of n1 points
+// (variant va), then row pass of N/n1 (variant vb); n1 > 1 with n2: the
+// three passes N = n1 n2 (N / (n1 n2)), column pass variant va; code 0: the
+// default policy (single pass when built, else the most balanced two-pass
+// split, else the most balanced three-pass split, variants 0).
+constexpr long long route_code(long long n1, int va, int vb, int lg_n2 = 0) {
+    return n1 | ((long long)va << 32) | ((long long)vb << 40) | ((long long)lg_n2 << 48);
 }
 inline long long route_n1(long long code) { return code & 0xffffffffLL; }
 inline int route_va(long long code) { return (int)((code >> 32) & 0xff); }
 inline int route_vb(long long code) { return (int)((code >> 40) & 0xff); }
+inline int route_lg_n2(long long code) { return (int)((code >> 48) & 0x3f); }
 
 // a two-pass split N = n1 * n2 with compiled column and row kernels whose
 // tiles divide the other length
@@ -204,30 +226,86 @@ bool split_ok(int precision, long long N, int ft, long long n1, int va = 0, int 
     return c && w && n2 % c->slots_per_block == 0 && n1 % w->slots_per_block == 0;
 }
 
+// Three passes reach N = 2^29 at most: every lane's byte offset within one
+// transaction's span then stays below 2^32 (the buffer addressing range).
+constexpr long long kMaxThreePassBytes = 1ll << 32;
+
+// a three-pass split N = n1 n2 n3 with compiled kernels whose tiles divide
+// the lengths they walk: M = n2 n3 columns of pass 1, n3 columns of pass 2,
+// n1 rows of pass 3
+bool split3_ok(int precision, long long N, int ft, long long n1, long long n2, int va = 0) {
+    if (n1 < 2 || n2 < 2 || N % (n1 * n2)) return false;
+    const size_t S = precision == TFFT_FP32 ? 8 : 16;
+    if ((double)N * (double)S > (double)kMaxThreePassBytes) return false;
+    const long long n3 = N / (n1 * n2);
+    const KernelEntry* a = find_entry(precision, kColPass, n1, ft, va);
+    const KernelEntry* b = find_entry(precision, kColPass3, n2, ft, 0);
+    const KernelEntry* c = find_entry(precision, kRowPass3, n3, ft, 0);
+    return a && b && c && (n2 * n3) % a->slots_per_block == 0 && n3 % b->slots_per_block == 0 &&
+           n1 % c->slots_per_block == 0;
+}
+
+int lg2(long long v) {
+    int l = 0;
+    while ((1ll << (l + 1)) <= v) ++l;
+    return l;
+}
+
 bool route_for(int precision, long long N, int ft, Route* r, long long code = 0) {
     *r = Route{};
-    if (code < 0 || (code >> 48) != 0) return false;
+    if (code < 0 || (code >> 54) != 0) return false;
     const long long n1c = route_n1(code);
-    const int va = route_va(code), vb = route_vb(code);
+    const int va = route_va(code), vb = route_vb(code), lgn2 = route_lg_n2(code);
     if (code == 0 || n1c == 1) {
+        if (lgn2 != 0) return false;
         if ((r->single = find_entry(precision, kSingle, N, ft, va))) return true;
         if (code != 0) return false;
     }
-    long long n1 = 0;
+    long long n1 = 0, n2 = 0;
     if (code != 0) {
-        if (!split_ok(precision, N, ft, n1c, va, vb)) return false;
+        if (lgn2 != 0) {
+            if (vb != 0 || !split3_ok(precision, N, ft, n1c, 1ll << lgn2, va)) return false;
+            n2 = 1ll << lgn2;
+        } else if (!split_ok(precision, N, ft, n1c, va, vb)) {
+            return false;
+        }
         n1 = n1c;
     } else {
         // balanced split N = N1 * N2 with N1 <= N2
         for (long long c = 2; c * c <= N; c <<= 1)
             if (split_ok(precision, N, ft, c)) n1 = c;
-        if (!n1) return false;
+        if (!n1) {
+            // the three-pass split with the smallest largest length
+            long long best = 0;
+            for (long long a = 2; a < N; a <<= 1)
+                for (long long b = 2; a * b < N; b <<= 1) {
+                    if (!split3_ok(precision, N, ft, a, b)) continue;
+                    const long long m = std::max(std::max(a, b), N / (a * b));
+                    if (!best || m < best || (m == best && a > n1)) { best = m; n1 = a; n2 = b; }
+                }
+            if (!n1) return false;
+        }
     }
     r->N1 = n1;
+    if (n2) {
+        r->N2 = n2;
+        r->N3 = N / (n1 * n2);
+        r->col = find_entry(precision, kColPass, n1, ft, code ? va : 0);
+        r->col3 = find_entry(precision, kColPass3, n2, ft, 0);
+        r->row3 = find_entry(precision, kRowPass3, r->N3, ft, 0);
+        return true;
+    }
     r->N2 = N / n1;
     r->col = find_entry(precision, kColPass, r->N1, ft, code ? va : 0);
     r->row = find_entry(precision, kRowPass, r->N2, ft, code ? vb : 0);
     return true;
+}
+
+// the route's code (what route_for reproduces it from)
+long long code_of(const Route& r) {
+    if (r.single) return route_code(1, r.single->variant, 0);
+    if (r.row3) return route_code(r.N1, r.col->variant, 0, lg2(r.N2));
+    return route_code(r.N1, r.col->variant, r.row->variant);
 }
 
 Tuning default_tuning(int precision, long long N) {
@@ -267,6 +345,18 @@ Tuning effective(const Tuning& tu, int ft, const KernelEntry* pa, const KernelEn
         if (pb && t.T > pb->tx_max) t.T = pb->tx_max;
         if (t.T < 1) t.T = 1;
     }
+    return t;
+}
+
+// the tuning a route really uses.  The passes of a three-pass transform
+// run groups of one signal: their signals are different units (signals,
+// rows (b, k1), pairs (b, k2)), and a correction then needs the outer
+// twiddle of one signal only.
+Tuning effective(const Tuning& tu, int ft, const Route& rt) {
+    if (rt.single) return effective(tu, ft, rt.single);
+    if (!rt.row3) return effective(tu, ft, rt.col, rt.row);
+    Tuning t = effective(tu, ft, rt.col, rt.col3);
+    t.T = 1;
     return t;
 }
 
@@ -456,7 +546,9 @@ template <class V> int run(const KernelEntry& e, const void* x, void* y, const K
     const bool prof = timed && g_prof && !capturing(stream) && prof_selected(e);
     if (prof) {
         rec.e = &e;
-        rec.bytes = 2.0 * (double)a.batch * (double)a.N * (double)sizeof(V);
+        // a three-pass row pass's signals are pairs (b, k2) of N / N2 elements
+        const double len = e.kind == kRowPass3 ? (double)a.N / (double)a.p3_n2 : (double)a.N;
+        rec.bytes = 2.0 * (double)a.batch * len * (double)sizeof(V);
         if (hipEventCreate(&rec.start) != hipSuccess || hipEventCreate(&rec.stop) != hipSuccess)
             return hip_fail(hipGetLastError());
         (void)hipEventRecord(rec.start, stream);
@@ -478,13 +570,116 @@ struct WsSource {
     size_t cap = 0;
 };
 
+// Injection target of pass 1 or 2 of a three-pass transform.  The caller
+// numbers element e by where that pass stores it within the signal: pass 1
+// row k1 = e / M, element e mod M (k2 N3 + n3); pass 2 the transposed
+// output e = k1 + N1 (k2 + N2 k3), which lies in pair (b, k2) at position
+// k1 + N1 k3 of the pass's row numbering.
+template <class R> void arm_three(KCall<R>& k, const Inject& inj, int pass, const Route& rt) {
+    arm_launch(k, inj, pass, 3, rt.pass(pass)->n_stages);
+    if (k.inj_signal < 0 || pass == 0) return;
+    const long long M = rt.N2 * rt.N3, e = inj.element;
+    auto sub = [&](long long b) {
+        if (b < 0) return b;
+        return pass == 1 ? b * rt.N1 + e / M : b * rt.N2 + (e / rt.N1) % rt.N2;
+    };
+    k.inj_signal = sub(inj.signal);
+    k.inj_signal2 = sub(inj.signal2);
+    k.inj_elem = pass == 1 ? e % M : e % rt.N1 + rt.N1 * (e / (rt.N1 * rt.N2));
+}
+
+// Three passes over chunks of whole signals, each out of place: x -> ws0
+// (column pass of N1), ws0 -> ws1 (column pass of N2 within each row), ws1
+// -> y (row pass of N3, transposed store).  Two intermediates of a chunk
+// each, so every pass keeps its input intact for the correction's re-read.
+template <class V>
+int transform3(const Route& rt, const void* x, void* y, long long N, long long batch, int conj,
+               double scale, tfft_ft_counts* counts, const Tuning& tu, const Inject& inj,
+               hipStream_t stream, bool may_alloc, const WsSource& wsrc) {
+    using R = typename RealOf<V>::type;
+    const int precision = sizeof(R) == 4 ? TFFT_FP32 : TFFT_FP64;
+    const long long N1 = rt.N1, N2 = rt.N2, N3 = rt.N3, M = N2 * N3;
+    SubTables *sa = nullptr, *sb = nullptr, *sc = nullptr;
+    PassTwiddle *ptN = nullptr, *ptM = nullptr;
+    int rc = get_sub(*rt.col, may_alloc, &sa);
+    if (rc == TFFT_OK) rc = get_sub(*rt.col3, may_alloc, &sb);
+    if (rc == TFFT_OK) rc = get_sub(*rt.row3, may_alloc, &sc);
+    if (rc == TFFT_OK) rc = get_pass(precision, N, may_alloc, &ptN);
+    if (rc == TFFT_OK) rc = get_pass(precision, M, may_alloc, &ptM);
+    if (rc != TFFT_OK) return rc;
+    const size_t sig_bytes = (size_t)N * sizeof(V);
+    long long chunk = chunk_signals(N, batch, sizeof(V), tu);
+    void* ws = nullptr;
+    const bool timed = wsrc.fixed == nullptr;
+    if (wsrc.fixed) {
+        if (2 * sig_bytes > wsrc.cap) return TFFT_ESCRATCH;
+        chunk = std::min(chunk, (long long)(wsrc.cap / (2 * sig_bytes)));
+        ws = wsrc.fixed;
+    } else {
+        rc = get_workspace(2 * (size_t)chunk * sig_bytes, stream, may_alloc, &ws);
+        if (rc != TFFT_OK) return rc;
+    }
+    char* ws0 = static_cast<char*>(ws);
+    char* ws1 = ws0 + (size_t)chunk * sig_bytes;
+
+    KArgs<V> A{}, B{}, C{};
+    fill_common(A, *rt.col, *sa, tu, counts);
+    fill_common(B, *rt.col3, *sb, tu, counts);
+    fill_common(C, *rt.row3, *sc, tu, counts);
+    for (KArgs<V>* k : {&A, &B, &C}) k->x_intact = 1;
+    // pass A: columns m of each signal, stride M
+    A.N = N; A.N1 = (int)N1; A.N2 = (int)M;
+    A.tiles = (int)(M / rt.col->slots_per_block);
+    A.conj_in = conj; A.conj_out = 0; A.scale = (R)1;
+    // pass B: rows (b, k1) of length M, columns n3 at stride N3
+    B.N = M; B.N1 = (int)N2; B.N2 = (int)N3;
+    B.p3_n1 = (int)N1;
+    B.tiles = (int)(N3 / rt.col3->slots_per_block);
+    B.tw_hi = static_cast<const V*>(ptN->hi);
+    B.tw_lo = static_cast<const V*>(ptN->lo);
+    B.tw_bits = ptN->bits;
+    B.conj_in = 0; B.conj_out = 0; B.scale = (R)1;
+    // pass C: pairs (b, k2), rows k1 at stride M, transposed store
+    C.N = N; C.N1 = (int)N1; C.N2 = (int)N3;
+    C.p3_n2 = (int)N2; C.p3_M = M;
+    C.tiles = (int)(N1 / rt.row3->slots_per_block);
+    C.tw_hi = static_cast<const V*>(ptM->hi);
+    C.tw_lo = static_cast<const V*>(ptM->lo);
+    C.tw_bits = ptM->bits;
+    C.conj_in = 0; C.conj_out = conj; C.scale = (R)scale;
+
+    const char* xb = static_cast<const char*>(x);
+    char* yb = static_cast<char*>(y);
+    for (long long c0 = 0; c0 < batch; c0 += chunk) {
+        const long long cnt = (batch - c0 < chunk) ? batch - c0 : chunk;
+        A.batch = cnt;
+        A.sig_base = c0;
+        B.batch = cnt * N1;
+        B.sig_base = c0 * N1;
+        C.batch = cnt * N2;
+        C.sig_base = c0 * N2;
+        arm_three(A, inj, 0, rt);
+        arm_three(B, inj, 1, rt);
+        arm_three(C, inj, 2, rt);
+        const bool hit = (inj.signal >= c0 && inj.signal < c0 + cnt) ||
+                         (inj.signal2 >= c0 && inj.signal2 < c0 + cnt);
+        if (!hit)
+            for (KArgs<V>* k : {&A, &B, &C}) k->inj_signal = k->inj_signal2 = -1;
+        rc = run<V>(*rt.col, xb + (size_t)c0 * sig_bytes, ws0, A, A.batch * A.tiles, stream, timed);
+        if (rc == TFFT_OK) rc = run<V>(*rt.col3, ws0, ws1, B, B.batch * B.tiles, stream, timed);
+        if (rc == TFFT_OK)
+            rc = run<V>(*rt.row3, ws1, yb + (size_t)c0 * sig_bytes, C, C.batch * C.tiles, stream, timed);
+        if (rc != TFFT_OK) return rc;
+    }
+    return TFFT_OK;
+}
+
 template <class V>
 int transform(const Route& rt, const void* x, void* y, long long N, long long batch, int dir,
               double scale, tfft_ft_counts* counts, const Tuning& tu_in, const Inject& inj,
               hipStream_t stream, bool may_alloc, const WsSource& wsrc = WsSource{}) {
     using R = typename RealOf<V>::type;
-    const Tuning tu = rt.single ? effective(tu_in, rt.single->ft, rt.single)
-                                : effective(tu_in, rt.col->ft, rt.col, rt.row);
+    const Tuning tu = effective(tu_in, rt.pass(0)->ft, rt);
     const int precision = sizeof(R) == 4 ? TFFT_FP32 : TFFT_FP64;
     const int conj = dir == TFFT_INVERSE ? 1 : 0;
     if (rt.single) {
@@ -504,6 +699,8 @@ int transform(const Route& rt, const void* x, void* y, long long N, long long ba
         return run<V>(*rt.single, x, y, a, (batch + per_block - 1) / per_block, stream,
                       wsrc.fixed == nullptr);
     }
+    if (rt.row3)
+        return transform3<V>(rt, x, y, N, batch, conj, scale, counts, tu, inj, stream, may_alloc, wsrc);
     // two passes over chunks of signals
     SubTables *sa = nullptr, *sb = nullptr;
     PassTwiddle* pt = nullptr;
@@ -1159,14 +1356,16 @@ int tfft_prepare(long long N, long long batch, int precision, int ft_mode, void*
         // the in-place correcting kernel shares the tables of its plan
         return rc;
     }
-    int rc = get_sub(*r.col, true, &st);
-    if (rc == TFFT_OK) rc = get_sub(*r.row, true, &st);
+    int rc = TFFT_OK;
+    for (int i = 0; i < r.passes() && rc == TFFT_OK; ++i) rc = get_sub(*r.pass(i), true, &st);
     PassTwiddle* pt = nullptr;
     if (rc == TFFT_OK) rc = get_pass(precision, N, true, &pt);
+    if (rc == TFFT_OK && r.row3) rc = get_pass(precision, r.N2 * r.N3, true, &pt);
     if (rc == TFFT_OK && batch > 0) {
         const size_t S = precision == TFFT_FP32 ? 8 : 16;
         void* ws = nullptr;
-        rc = get_workspace((size_t)chunk_signals(N, batch, S, tu) * (size_t)N * S,
+        // three passes hold two intermediates of a chunk
+        rc = get_workspace((size_t)(r.row3 ? 2 : 1) * (size_t)chunk_signals(N, batch, S, tu) * (size_t)N * S,
                            static_cast<hipStream_t>(hip_stream), true, &ws);
     }
     return rc;
@@ -1199,6 +1398,10 @@ int tfft_routes(long long N, int precision, int ft_mode, long long* codes, int c
         for (int va = 0; va < 8; ++va)
             for (int vb = 0; vb < 8; ++vb)
                 if (split_ok(precision, N, ft_mode, c, va, vb)) put_route(route_code(c, va, vb));
+    for (long long c = 2; c < N; c <<= 1)
+        for (long long b = 2; c * b < N; b <<= 1)
+            for (int va = 0; va < 8; ++va)
+                if (split3_ok(precision, N, ft_mode, c, b, va)) put_route(route_code(c, va, 0, lg2(b)));
     return n;
 }
 
@@ -1231,20 +1434,24 @@ int tfft_route_info(long long N, int precision, int ft_mode, long long* info, in
     const Tuning tu = get_tuning(precision, N, ft_mode);
     Route r;
     if (!route_for(precision, N, ft_mode, &r, tu.route)) return TFFT_EUNSUPPORTED;
-    long long v[9];
-    Tuning te;
-    if (r.single) {
-        v[0] = 1; v[1] = N; v[2] = 1; v[3] = r.single->n_stages; v[4] = 0;
-        v[7] = r.single->slots_per_block; v[8] = 0;
-        te = effective(tu, ft_mode, r.single);
-    } else {
-        v[0] = 2; v[1] = r.N1; v[2] = r.N2; v[3] = r.col->n_stages; v[4] = r.row->n_stages;
-        v[7] = r.col->slots_per_block; v[8] = r.row->slots_per_block;
-        te = effective(tu, ft_mode, r.col, r.row);
-    }
+    long long v[12] = {};
+    const KernelEntry* p0 = r.pass(0);
+    const KernelEntry* p1 = r.pass(1);
+    const KernelEntry* p2 = r.pass(2);
+    v[0] = r.passes();
+    v[1] = r.single ? N : r.N1;
+    v[2] = r.single ? 1 : r.N2;
+    v[3] = p0->n_stages;
+    v[4] = p1 ? p1->n_stages : 0;
+    v[7] = p0->slots_per_block;
+    v[8] = p1 ? p1->slots_per_block : 0;
+    v[9] = r.row3 ? r.N3 : 1;
+    v[10] = p2 ? p2->n_stages : 0;
+    v[11] = p2 ? p2->slots_per_block : 0;
+    const Tuning te = effective(tu, ft_mode, r);
     v[5] = te.T;
     v[6] = te.gran;
-    for (int i = 0; i < n && i < 9; ++i) info[i] = v[i];
+    for (int i = 0; i < n && i < 12; ++i) info[i] = v[i];
     return TFFT_OK;
 }
 
@@ -1263,8 +1470,7 @@ int tfft_get_route(long long N, int precision, int ft_mode, long long* code) {
     Route r;
     const long long c = get_tuning(precision, N, ft_mode).route;
     if (!route_for(precision, N, ft_mode, &r, c)) return TFFT_EUNSUPPORTED;
-    if (r.single) *code = route_code(1, r.single->variant, 0);
-    else *code = route_code(r.N1, r.col->variant, r.row->variant);
+    *code = code_of(r);
     return TFFT_OK;
 }
 
@@ -1307,11 +1513,15 @@ int tfft_load_tuning(const char* path) {
             Tuning tu = current(prec, N, ft);
             long long v = 0;
             if (e.get("split_n1")) {
-                long long va = 0, vb = 0;
+                long long va = 0, vb = 0, n2 = 0;
                 if (!json_int(e.get("split_n1"), &v) || v < 0 || v > 0xffffffffLL) return TFFT_EINVAL;
                 if (e.get("variant_a") && (!json_int(e.get("variant_a"), &va) || va < 0 || va > 255)) return TFFT_EINVAL;
                 if (e.get("variant_b") && (!json_int(e.get("variant_b"), &vb) || vb < 0 || vb > 255)) return TFFT_EINVAL;
-                const long long code = v == 0 ? 0 : route_code(v, (int)va, (int)vb);
+                // three passes: the second length, a power of two
+                if (e.get("split_n2") && (!json_int(e.get("split_n2"), &n2) || n2 < 0 || n2 > (1ll << 30) ||
+                                          (n2 != 0 && (n2 < 2 || (n2 & (n2 - 1))))))
+                    return TFFT_EINVAL;
+                const long long code = v == 0 ? 0 : route_code(v, (int)va, (int)vb, n2 ? lg2(n2) : 0);
                 Route r;
                 if (code != 0 && !route_for(prec, N, ft, &r, code)) return TFFT_EUNSUPPORTED;
                 tu.route = code;
@@ -1367,7 +1577,7 @@ int tfft_profile(int on) {
 }
 
 int tfft_profile_only(int precision, int kind, int Ns, int ft) {
-    if (precision < -1 || precision > TFFT_FP64 || kind < -1 || kind > 3 || Ns < -1 || ft < -1 || ft > 3)
+    if (precision < -1 || precision > TFFT_FP64 || kind < -1 || kind > 5 || Ns < -1 || ft < -1 || ft > 3)
         return TFFT_EINVAL;
     std::lock_guard<std::mutex> lk(g_mu);
     g_prof_sel[0] = precision;
@@ -1394,7 +1604,7 @@ int tfft_profile_read(char* buf, long long buflen) {
         (void)hipEventDestroy(r.stop);
     }
     g_prof_log.clear();
-    static const char* kinds[] = {"single", "colpass", "rowpass", "ragged"};
+    static const char* kinds[] = {"single", "colpass", "rowpass", "ragged", "colpass3", "rowpass3"};
     for (auto& kv : agg) {
         char line[256];
         snprintf(line, sizeof(line), "%s %s %d %d %lld %.6f %.1f\n",
@@ -1422,7 +1632,7 @@ int tfft_inject_arm_desc(const tfft_inject_desc* d) {
     if (check_precision(d->precision) != TFFT_OK) return TFFT_EINVAL;
     const int width = d->precision == TFFT_FP32 ? 32 : 64;
     if (d->bit < 0 || d->bit >= width) return TFFT_EINVAL;
-    if (d->pass < -1 || d->pass > 1 || d->stage < -1) return TFFT_EINVAL;
+    if (d->pass < -1 || d->pass > 2 || d->stage < -1) return TFFT_EINVAL;
     if (d->two != 0 && (d->two != 1 || d->signal2 < 0 || d->signal2 == d->signal)) return TFFT_EINVAL;
     std::lock_guard<std::mutex> lk(g_mu);
     g_inj.armed = true;
@@ -1515,7 +1725,7 @@ int c2c_impl(const void* x, void* y, long long N, long long batch, int dir, int 
     }
     Inject inj = g_inj;
     if (inj.armed && (inj.precision != precision || inj.signal >= batch || inj.signal2 >= batch || inj.element >= N ||
-                      !inject_fits(inj, rt.single ? rt.single : rt.col, rt.single ? nullptr : rt.row)))
+                      !inject_fits(inj, rt.pass(0), rt.pass(1), rt.pass(2))))
         return TFFT_EINVAL;
     WsSource wsrc;
     if (noalloc) {
@@ -1572,7 +1782,7 @@ int tfft_c2c_offline(const void* x, void* y, long long N, long long batch, int d
     if (!route_for(precision, N, TFFT_FT_OFF, &rt, tu.route)) return TFFT_EUNSUPPORTED;
     if (g_inj.armed && (g_inj.precision != precision || g_inj.signal >= batch || g_inj.signal2 >= batch ||
                         g_inj.element >= N ||
-                        !inject_fits(g_inj, rt.single ? rt.single : rt.col, rt.single ? nullptr : rt.row)))
+                        !inject_fits(g_inj, rt.pass(0), rt.pass(1), rt.pass(2))))
         return TFFT_EINVAL;
     const bool may_alloc = !capturing(stream);
     const int dev = current_device();

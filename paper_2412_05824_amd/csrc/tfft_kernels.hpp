@@ -69,7 +69,10 @@ struct FtCounts {   // mirrors tfft_ft_counts in the public header
     unsigned long long fallback;       // detections located by re-encoding the group
 };
 
-enum Kind { kSingle = 0, kColPass = 1, kRowPass = 2 };
+// kColPass3 / kRowPass3: the second and third pass of a three-pass
+// transform N = N1 N2 N3 (M = N2 N3), see Geo.  Kind 3 labels the ragged
+// persistent launches in the launch-timing log.
+enum Kind { kSingle = 0, kColPass = 1, kRowPass = 2, kColPass3 = 4, kRowPass3 = 5 };
 
 // Kernel arguments shared by all transform kernels.
 // Per-call arguments: direction, scaling, counters and the injection hook.
@@ -99,6 +102,14 @@ template <class V> struct KArgs : KCall<typename RealOf<V>::type> {
     long long batch;      // number of signals
     long long N;          // full transform length (signal stride in elements)
     int N1, N2;           // two-pass split, N = N1 * N2
+    // Three-pass transforms (N = N1 N2 N3, M = N2 N3): column pass B runs
+    // over rows of length M (a.N = M, a.N2 = N3) and multiplies element
+    // n2 N3 + n3 of row k1 by w_N^{k1 (n2 N3 + n3)} at load (p3_n1 = N1,
+    // full-length table in tw_hi / tw_lo); row pass C runs over (signal,
+    // k2) pairs (p3_n2 = N2, p3_M = M, a.N = N, a.N1 = N1), multiplies by
+    // w_M^{k2 n3} (tw_hi / tw_lo of length M) and writes k1 + N1 (k2 + N2 k3).
+    int p3_n1, p3_n2;
+    long long p3_M;
     int T;                // transactions (signals) per slot
     long long sig_base;   // global index of local signal 0 (counters only)
     R tau_coef;           // kappa * u * sqrt(Ns log2 Ns); tau = tau_coef * sqrt(nu)
@@ -128,6 +139,10 @@ template <int KIND_, int Ns_, int E_, int WC_, int B_, int... Rs> struct Plan {
     static constexpr int E = E_;
     static constexpr int P = Ns / E;                           // lanes per slot
     static constexpr bool TILE = KIND != kSingle;
+    static constexpr bool IS_COL = KIND == kColPass || KIND == kColPass3;
+    static constexpr bool IS_ROW = KIND == kRowPass || KIND == kRowPass3;
+    // a per-element twiddle at load, folded into the left vector
+    static constexpr bool HAS_TW = KIND == kRowPass || KIND == kColPass3 || KIND == kRowPass3;
     static constexpr int C = TILE ? WC_ : 1;                    // sub-signals per tile
     static constexpr int THREADS = TILE ? P * C : (P > kWave ? P : WC_ * kWave);
     static constexpr bool MULTI_WAVE = THREADS > kWave && (TILE || P > kWave);
@@ -385,12 +400,15 @@ template <class V, class PL, bool IND> struct Geo {
                 sig_step = G / a.tiles;   // signal groups in the launch
             }
             sig_u0 = sig0;
-            if constexpr (PL::KIND == kColPass) {
+            if constexpr (PL::IS_COL) {
                 lane_in = (unsigned)t * (unsigned)a.N2 + (unsigned)slot;
                 lane_out = lane_in;
-            } else {
+            } else if constexpr (PL::KIND == kRowPass) {
                 lane_in = (unsigned)slot * (unsigned)a.N2 + (unsigned)t;
                 lane_out = (unsigned)slot + (unsigned)a.N1 * (unsigned)t;
+            } else {   // kRowPass3: rows k1 at stride M, outputs k1 + N1 N2 k3
+                lane_in = (unsigned)slot * (unsigned)a.p3_M + (unsigned)t;
+                lane_out = (unsigned)slot + (unsigned)a.N1 * (unsigned)a.p3_n2 * (unsigned)t;
             }
         }
     }
@@ -399,49 +417,71 @@ template <class V, class PL, bool IND> struct Geo {
     // plus this lane's 32-bit offset (lane_in / lane_out): loads and stores
     // then take a scalar base and one vector offset shared by all E elements.
     // Lane offsets stay below 2^32 bytes: at most a tile's span of a signal.
+    // three-pass row pass: signal s is the pair (b, k2) = (s / N2, s % N2);
+    // its row k1 starts at b N + k2 N3 + k1 M, its outputs at b N + k2 N1 + k1
+    __device__ __forceinline__ static long long p3_in_base(const KArgs<V>& a, long long s) {
+        return (s / a.p3_n2) * a.N + (s % a.p3_n2) * (long long)Ns;
+    }
+    __device__ __forceinline__ static long long p3_out_base(const KArgs<V>& a, long long s) {
+        return (s / a.p3_n2) * a.N + (s % a.p3_n2) * (long long)a.N1;
+    }
     __device__ __forceinline__ long long in_uni(const KArgs<V>& a, int b) const {
         const long long su = sig_u0 + (long long)b * sig_step;
         if constexpr (PL::KIND == kSingle) return su * a.N;
-        else if constexpr (PL::KIND == kColPass) return su * a.N + (long long)tile * C;
-        else return su * a.N + (long long)tile * C * a.N2;
+        else if constexpr (PL::IS_COL) return su * a.N + (long long)tile * C;
+        else if constexpr (PL::KIND == kRowPass) return su * a.N + (long long)tile * C * a.N2;
+        else return p3_in_base(a, su) + (long long)tile * C * a.p3_M;
     }
     __device__ __forceinline__ long long out_uni(const KArgs<V>& a, int b) const {
         const long long su = sig_u0 + (long long)b * sig_step;
         if constexpr (PL::KIND == kSingle) return su * a.N;
+        else if constexpr (PL::KIND == kRowPass3) return p3_out_base(a, su) + (long long)tile * C;
         else return su * a.N + (long long)tile * C;
     }
     __device__ __forceinline__ long long in_step(const KArgs<V>& a) const {
-        if constexpr (PL::KIND == kColPass) return (long long)P * a.N2;
+        if constexpr (PL::IS_COL) return (long long)P * a.N2;
         else return P;
     }
     __device__ __forceinline__ long long out_step(const KArgs<V>& a) const {
         if constexpr (PL::KIND == kSingle) return P;
-        else if constexpr (PL::KIND == kColPass) return (long long)P * a.N2;
-        else return (long long)P * a.N1;
+        else if constexpr (PL::IS_COL) return (long long)P * a.N2;
+        else if constexpr (PL::KIND == kRowPass) return (long long)P * a.N1;
+        else return (long long)P * a.N1 * a.p3_n2;
     }
     __device__ __forceinline__ long long sig(int b) const { return sig0 + (long long)b * sig_step; }
     // element offsets of input element m / output element k of signal s
     __device__ __forceinline__ long long in_base(const KArgs<V>& a, long long s) const {
         if constexpr (IND) return a.in_tab[s];
+        else if constexpr (PL::KIND == kRowPass3) return p3_in_base(a, s);
         else return s * a.N;
     }
     __device__ __forceinline__ long long out_base(const KArgs<V>& a, long long s) const {
         if constexpr (IND) return a.out_tab[s];
+        else if constexpr (PL::KIND == kRowPass3) return p3_out_base(a, s);
         else return s * a.N;
     }
     __device__ __forceinline__ long long gid(const KArgs<V>& a, long long s) const {
         if constexpr (IND) return a.id_tab[s];
         else return a.sig_base + s;
     }
+    // the caller's signal a fault of local signal s is reported against: the
+    // passes of a three-pass transform number rows (b, k1) or pairs (b, k2)
+    __device__ __forceinline__ long long rid(const KArgs<V>& a, long long s) const {
+        if constexpr (PL::KIND == kColPass3) return gid(a, s) / a.p3_n1;
+        else if constexpr (PL::KIND == kRowPass3) return gid(a, s) / a.p3_n2;
+        else return gid(a, s);
+    }
     __device__ __forceinline__ long long in_off(const KArgs<V>& a, long long s, int m) const {
         if constexpr (PL::KIND == kSingle) return in_base(a, s) + m;
-        else if constexpr (PL::KIND == kColPass) return in_base(a, s) + (long long)m * a.N2 + line;
-        else return in_base(a, s) + (long long)line * a.N2 + m;
+        else if constexpr (PL::IS_COL) return in_base(a, s) + (long long)m * a.N2 + line;
+        else if constexpr (PL::KIND == kRowPass) return in_base(a, s) + (long long)line * a.N2 + m;
+        else return in_base(a, s) + (long long)line * a.p3_M + m;
     }
     __device__ __forceinline__ long long out_off(const KArgs<V>& a, long long s, int k) const {
         if constexpr (PL::KIND == kSingle) return out_base(a, s) + k;
-        else if constexpr (PL::KIND == kColPass) return out_base(a, s) + (long long)k * a.N2 + line;
-        else return out_base(a, s) + line + (long long)a.N1 * k;
+        else if constexpr (PL::IS_COL) return out_base(a, s) + (long long)k * a.N2 + line;
+        else if constexpr (PL::KIND == kRowPass) return out_base(a, s) + line + (long long)a.N1 * k;
+        else return out_base(a, s) + line + (long long)a.N1 * a.p3_n2 * k;
     }
     // which of this lane's values t + P r is the injected one: r, or -1 (test
     // hook).  inj_elem numbers a value of position k of a sub-sequence as k
@@ -452,7 +492,7 @@ template <class V, class PL, bool IND> struct Geo {
         long long k = -1;   // index of the target in this slot's numbering
         if constexpr (PL::KIND == kSingle) {
             k = kc.inj_elem;
-        } else if constexpr (PL::KIND == kColPass) {
+        } else if constexpr (PL::IS_COL) {
             if (kc.inj_elem % a.N2 == line) k = kc.inj_elem / a.N2;
         } else {
             if (kc.inj_elem % a.N1 == line) k = kc.inj_elem / a.N1;
@@ -486,11 +526,20 @@ template <class V, class PL, bool IND> struct Geo {
             tw_step = steps;
         }
     }
-    // inter-pass twiddle of element t + P r (1 outside the row pass); the
-    // LDS steps must be visible (barrier after twiddle_setup)
-    __device__ __forceinline__ V twiddle(const KArgs<V>& a, int r) const {
+    // inter-pass twiddle of element t + P r of local signal s (1 where a
+    // pass has none); the row pass's LDS steps must be visible (barrier after
+    // twiddle_setup).  Three-pass passes form it from the table per element.
+    __device__ __forceinline__ V twiddle(const KArgs<V>& a, long long s, int r) const {
         if constexpr (PL::KIND == kRowPass) {
             return cmul(tw_base, tw_step[slot * E + r]);
+        } else if constexpr (PL::KIND == kColPass3) {
+            // w_N^{k1 (n2 N3 + n3)}, k1 = s mod N1, n2 = t + P r, n3 = line (< N)
+            const unsigned k1 = (unsigned)(s % a.p3_n1);
+            return twiddle_at(a, k1 * ((unsigned)(t + P * r) * (unsigned)a.N2 + (unsigned)line));
+        } else if constexpr (PL::KIND == kRowPass3) {
+            // w_M^{k2 n3}, k2 = s mod N2, n3 = t + P r (< M)
+            const unsigned k2 = (unsigned)(s % a.p3_n2);
+            return twiddle_at(a, k2 * (unsigned)(t + P * r));
         } else {
             return V{(R)1, (R)0};
         }
@@ -655,7 +704,7 @@ template <class V, class PL, int FT, bool IND = false> struct Smem {
     // up to 2048 points); row passes keep reading the cached table, which
     // costs them no registers and saves the staging
     static constexpr bool AW_LDS =
-        FT != 0 && (PL::KIND == kColPass || (PL::KIND == kSingle && PL::SLOTS >= 2 && PL::Ns <= 2048) ||
+        FT != 0 && (PL::IS_COL || (PL::KIND == kSingle && PL::SLOTS >= 2 && PL::Ns <= 2048) ||
                     kResident<V, PL, FT, IND>);
     static constexpr int AW = AW_LDS ? PL::Ns : 0;
     // per-transaction checking: wave parts of the kept partials (3 values)
@@ -860,15 +909,15 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
             for (int r = 0; r < E; ++r) {
                 const V z = reg[r];   // raw loaded value
                 V tw = V{(R)1, (R)0};
-                if constexpr (PL::KIND == kRowPass) {
-                    tw = g.twiddle(a, r);
+                if constexpr (PL::HAS_TW) {
+                    tw = g.twiddle(a, s, r);
                     reg[r] = cmul(z, tw);
                 }
                 if constexpr (FT != 0) {
                     V av;
                     if constexpr (kAwEarly) av = aw[r];
                     else av = left_at(r);
-                    if constexpr (PL::KIND == kRowPass) av = cmul(av, tw);
+                    if constexpr (PL::HAS_TW) av = cmul(av, tw);
                     p = cmac(p, av, z);
                     nub = fmad(z.x, z.x, fmad(z.y, z.y, nub));
                     if constexpr (KEEP_XS) xs[r] = cadd(xs[r], z);
@@ -991,7 +1040,9 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
                         acc = cadd(acc, xv);
                     }
                 }
-                if constexpr (PL::KIND == kRowPass) acc = cmul(acc, g.twiddle(a, r));
+                // every transaction of a group shares the twiddle (row pass:
+                // same rows; three-pass passes run one transaction per group)
+                if constexpr (PL::HAS_TW) acc = cmul(acc, g.twiddle(a, g.sig(0), r));
                 reg[r] = acc;
             }
             NoHook nohook;
@@ -1065,7 +1116,7 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
                 if (!ok) atomicAdd(&kc.counts->uncorrectable, 1ull);
                 else if (act == 1) atomicAdd(&kc.counts->corrected, 1ull);
                 else atomicAdd(&kc.counts->rebuilt, 1ull);
-                atomicExch(&kc.counts->last_signal, (unsigned long long)g.gid(a, sstar));
+                atomicExch(&kc.counts->last_signal, (unsigned long long)g.rid(a, sstar));
             }
             // the next correction of this group re-reads these outputs
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -1100,7 +1151,7 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
                     for (unsigned f = F; f != 0u; f &= f - 1u) {
                         atomicAdd(&kc.counts->detected, 1ull);
                         atomicExch(&kc.counts->last_signal,
-                                   (unsigned long long)g.gid(a, g.sig(__builtin_ctz(f))));
+                                   (unsigned long long)g.rid(a, g.sig(__builtin_ctz(f))));
                     }
                 }
             } else {
@@ -1193,7 +1244,7 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
                             V xv = ld_x<COH>(x, g.in_off(a, sb, t + P * r));
                             if (kc.conj_in) xv.y = -xv.y;
                             V av = left[t + P * r];
-                            if constexpr (PL::KIND == kRowPass) av = cmul(av, g.twiddle(a, r));
+                            if constexpr (PL::HAS_TW) av = cmul(av, g.twiddle(a, sb, r));
                             p = cadd(p, cmul(av, xv));
                             V yv = ld_y<COH>(y, g.out_off(a, sb, t + P * r));
                             if (kc.conj_out) yv.y = -yv.y;
@@ -1221,7 +1272,7 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
                 if (action != 0 && t == 0) {
                     atomicAdd(&kc.counts->detected, 1ull);
                     if (action == 3) atomicAdd(&kc.counts->uncorrectable, 1ull);
-                    else atomicExch(&kc.counts->last_signal, (unsigned long long)g.gid(a, sstar));
+                    else atomicExch(&kc.counts->last_signal, (unsigned long long)g.rid(a, sstar));
                 }
             } else {
                 if (action == 1 || action == 2) {

@@ -16,7 +16,7 @@ constexpr int kMaxStages = 12;   // radix stages a registered plan may have
 
 struct KernelEntry {
     int precision;          // 0 fp32, 1 fp64
-    int kind;               // kSingle, kColPass, kRowPass
+    int kind;               // kSingle, kColPass, kRowPass, kColPass3, kRowPass3
     int Ns;                 // (sub-)transform length
     int ft;                 // 0 off, 1 detect, 2 correct, 3 correct in place
     int E, P, threads;      // elements per lane, lanes per slot, lanes per workgroup
@@ -100,5 +100,6 @@ void register_fp32_tiles_narrow(std::vector<KernelEntry>& out);
 void register_fp32_tiles_e8(std::vector<KernelEntry>& out);
 void register_fp64_single(std::vector<KernelEntry>& out);
 void register_fp64_tiles(std::vector<KernelEntry>& out);
+void register_fp32_three(std::vector<KernelEntry>& out);
 
 }  // namespace tfft

@@ -137,12 +137,13 @@ def inject_arm(signal: int, element: int, part: int, bit: int, dtype=torch.compl
 
 
 def route_info(N: int, dtype=torch.complex64, ft_mode: int = 2) -> dict:
-    """The route a call takes now: passes, N1, N2, stages of each pass, T,
-    granularity and sub-signals per workgroup of each pass."""
+    """The route a call takes now: passes, N1, N2, N3, stages of each pass,
+    T, granularity and sub-signals per workgroup of each pass."""
     import ctypes
-    buf = (ctypes.c_longlong * 9)()
-    _lib.check(_lib.load().tfft_route_info(N, _precision(dtype), ft_mode, buf, 9), f"tfft_route_info(N={N})")
-    keys = ("passes", "N1", "N2", "stages0", "stages1", "T", "gran", "slots0", "slots1")
+    buf = (ctypes.c_longlong * 12)()
+    _lib.check(_lib.load().tfft_route_info(N, _precision(dtype), ft_mode, buf, 12), f"tfft_route_info(N={N})")
+    keys = ("passes", "N1", "N2", "stages0", "stages1", "T", "gran", "slots0", "slots1",
+            "N3", "stages2", "slots2")
     return {k: int(buf[i]) for i, k in enumerate(keys)}
 
 
@@ -276,15 +277,23 @@ def fft_c2c_ragged(packed: torch.Tensor, sizes, dir: int = -1, ft_mode: int = 2,
 
 
 # ---- routes and the tuning table ----
-def route_code(n1: int, variant_a: int = 0, variant_b: int = 0) -> int:
+def route_code(n1: int, variant_a: int = 0, variant_b: int = 0, n2: int = 0) -> int:
     """Route code: n1 = 1 single pass (plan variant_a), n1 > 1 column pass of n1
-    points (variant_a) then row pass of N/n1 (variant_b)."""
-    return int(n1) | (int(variant_a) << 32) | (int(variant_b) << 40)
+    points (variant_a) then row pass of N/n1 (variant_b); with n2 (a power of
+    two) the three passes n1, n2, N/(n1 n2)."""
+    lg = int(n2).bit_length() - 1 if n2 else 0
+    return int(n1) | (int(variant_a) << 32) | (int(variant_b) << 40) | (lg << 48)
 
 
 def route_parts(code: int):
     """(n1, variant_a, variant_b) of a route code."""
     return code & 0xFFFFFFFF, (code >> 32) & 0xFF, (code >> 40) & 0xFF
+
+
+def route_n2(code: int) -> int:
+    """The second length of a three-pass route code (0 below three passes)."""
+    lg = (code >> 48) & 0x3F
+    return 1 << lg if lg else 0
 
 
 def routes(N: int, dtype=torch.complex64, ft_mode: int = 2) -> list:

@@ -55,8 +55,12 @@ def test_invalid_arguments_rejected_on_host():
     assert lib.tfft_inject_arm(0, 0, 2, 3, 0) == _lib.TFFT_EINVAL
     assert lib.tfft_inject_arm(0, 0, 0, 63, 1) == _lib.TFFT_OK
     assert lib.tfft_inject_disarm() == _lib.TFFT_OK
-    d = _lib.InjectDesc(signal=0, element=0, part=0, bit=3, precision=0, pass_=2, stage=-1)
-    assert lib.tfft_inject_arm_desc(ctypes.byref(d)) == _lib.TFFT_EINVAL      # no third pass
+    d = _lib.InjectDesc(signal=0, element=0, part=0, bit=3, precision=0, pass_=3, stage=-1)
+    assert lib.tfft_inject_arm_desc(ctypes.byref(d)) == _lib.TFFT_EINVAL      # no fourth pass
+    d.pass_ = 2
+    assert lib.tfft_inject_arm_desc(ctypes.byref(d)) == _lib.TFFT_OK
+    # 2^20 runs as two passes: a flip armed for a third pass does not fit
+    assert c2c(dummy, dummy + (1 << 24), 1 << 20, 1, -1, 0, 0, 0.0, None, None) == _lib.TFFT_EINVAL
     d.pass_, d.stage = 0, -2
     assert lib.tfft_inject_arm_desc(ctypes.byref(d)) == _lib.TFFT_EINVAL      # stage below -1
     assert lib.tfft_inject_arm_desc(None) == _lib.TFFT_EINVAL
@@ -72,7 +76,7 @@ def test_invalid_arguments_rejected_on_host():
     assert lib.tfft_prepare(100, 0, 0, 0, None) == _lib.TFFT_EUNSUPPORTED
     # launch-timing filter: fields in range or -1 (any)
     assert lib.tfft_profile_only(2, -1, -1, -1) == _lib.TFFT_EINVAL
-    assert lib.tfft_profile_only(-1, 4, -1, -1) == _lib.TFFT_EINVAL
+    assert lib.tfft_profile_only(-1, 6, -1, -1) == _lib.TFFT_EINVAL
     assert lib.tfft_profile_only(-1, -1, -2, -1) == _lib.TFFT_EINVAL
     assert lib.tfft_profile_only(-1, -1, -1, 4) == _lib.TFFT_EINVAL
     assert lib.tfft_profile_only(0, 2, 2048, 2) == _lib.TFFT_OK
@@ -310,3 +314,66 @@ def test_granularity_and_second_target_validated_on_host():
     dummy = 4096
     assert lib.tfft_c2c(dummy, dummy + (1 << 20), 256, 4, -1, 0, 0, 0.0, None, None) == _lib.TFFT_EINVAL
     assert lib.tfft_inject_disarm() == _lib.TFFT_OK
+
+
+def test_three_pass_routes():
+    """Lengths beyond the two-pass limit run as three passes (Sec. 3.3 launch
+    rule: three launches for 2^23..2^29) in single precision; the route
+    code carries the second length; three-pass routes can be forced on a
+    two-pass length and read back; tuning tables name them by split_n2."""
+    import paper_2412_05824_amd as tff
+    lib = _lib.load()
+    FP32 = _lib.FP32
+    buf = (ctypes.c_longlong * 12)()
+    for lg in range(23, 30):
+        N = 1 << lg
+        assert lib.tfft_supported(N, FP32) == 1, lg
+        assert lib.tfft_route_info(N, FP32, 2, buf, 12) == 0
+        assert buf[0] == 3 and buf[1] * buf[2] * buf[9] == N, (lg, list(buf))
+        assert buf[5] == 1                      # groups of one signal per pass
+        assert min(buf[3], buf[4], buf[10]) >= 1 and min(buf[7], buf[8], buf[11]) >= 1
+        # the most balanced split: no length beyond the cube root's power of two by more than 2x
+        assert max(buf[1], buf[2], buf[9]) <= 2 * (1 << -(-lg // 3)), (lg, list(buf))
+    assert lib.tfft_supported(1 << 30, FP32) == 0
+    # the two-pass lengths keep two passes by default
+    assert lib.tfft_route_info(1 << 22, FP32, 2, buf, 12) == 0 and buf[0] == 2 and buf[9] == 1
+    # codes round-trip through the Python helpers
+    code = tff.route_code(64, 0, 0, 256)
+    assert tff.route_n2(code) == 256 and tff.route_parts(code) == (64, 0, 0)
+    three = [c for c in tff.routes(1 << 22) if tff.route_n2(c)]
+    assert three, "a three-pass split of 2^22 is built"
+    try:
+        assert lib.tfft_set_route(1 << 22, FP32, three[0]) == _lib.TFFT_OK
+        v = ctypes.c_longlong()
+        assert lib.tfft_get_route(1 << 22, FP32, 2, ctypes.byref(v)) == 0 and v.value == three[0]
+        assert lib.tfft_route_info(1 << 22, FP32, 2, buf, 12) == 0 and buf[0] == 3
+        assert buf[2] == tff.route_n2(three[0])
+        # a row-pass variant has no meaning on three passes; n2 must divide
+        assert lib.tfft_set_route(1 << 22, FP32, three[0] | (1 << 40)) == _lib.TFFT_EUNSUPPORTED
+        assert lib.tfft_set_route(1 << 22, FP32, tff.route_code(64, 0, 0, 1 << 17)) == _lib.TFFT_EUNSUPPORTED
+        assert lib.tfft_set_route(1 << 22, FP32, 1 << 54) == _lib.TFFT_EUNSUPPORTED
+    finally:
+        lib.tfft_set_route(1 << 22, FP32, 0)
+        if os.path.exists(_lib.TUNING_PATH):
+            lib.tfft_load_tuning(_lib.TUNING_PATH.encode())
+
+
+def test_three_pass_tuning_entries(tmp_path):
+    lib = _lib.load()
+    FP32 = _lib.FP32
+    p = tmp_path / "t3.json"
+    p.write_text(json.dumps({"entries": [
+        {"precision": "fp32", "N": 1 << 23, "split_n1": 64, "split_n2": 512, "T": 1}]}))
+    v = ctypes.c_longlong()
+    try:
+        assert lib.tfft_load_tuning(str(p).encode()) == 1
+        assert lib.tfft_get_route(1 << 23, FP32, 2, ctypes.byref(v)) == 0
+        assert v.value == 64 | (9 << 48)
+        for bad in ({"split_n1": 64, "split_n2": 300}, {"split_n1": 64, "split_n2": 1 << 20},
+                    {"split_n1": 64, "split_n2": -2}):
+            p.write_text(json.dumps({"entries": [dict(precision="fp32", N=1 << 23, **bad)]}))
+            assert lib.tfft_load_tuning(str(p).encode()) < 0, bad
+    finally:
+        lib.tfft_set_route(1 << 23, FP32, 0)
+        if os.path.exists(_lib.TUNING_PATH):
+            lib.tfft_load_tuning(_lib.TUNING_PATH.encode())
