@@ -20,6 +20,7 @@ void register_fp32_tiles(std::vector<KernelEntry>& out) {
     add_kind<kRowPass>(out);
     register_fp32_tiles_narrow(out);
     register_fp32_tiles_e8(out);
+    register_fp32_tiles_wide(out);
 }
 
 }  // namespace tfft

@@ -703,13 +703,20 @@ template <class V, class PL, int FT, bool IND = false> struct Smem {
     // signals share it and it is small (column tiles; single-pass groups of
     // up to 2048 points); row passes keep reading the cached table, which
     // costs them no registers and saves the staging
-    static constexpr bool AW_LDS =
-        FT != 0 && (PL::IS_COL || (PL::KIND == kSingle && PL::SLOTS >= 2 && PL::Ns <= 2048) ||
-                    kResident<V, PL, FT, IND>);
-    static constexpr int AW = AW_LDS ? PL::Ns : 0;
     // per-transaction checking: wave parts of the kept partials (3 values)
     using G = Geo<V, PL, IND>;
     static constexpr int TXR = (FT != 0 && G::TX_PARTS > 1) ? 3 * G::TX_MAX * G::TX_PARTS * (PL::TILE ? PL::C : 1) : 0;
+    static constexpr int REST = PL::LDS_DATA * (int)sizeof(V) + TWS * (int)sizeof(V) +
+                                (RED + TXR) * (int)sizeof(R);
+    // (and only where it costs no workgroup per CU: a column tile of 1024 or
+    // 2048 points would otherwise drop from two to one; resident kernels
+    // always stage it)
+    static constexpr int CU_LDS = 160 * 1024;
+    static constexpr bool AW_FITS = CU_LDS / (REST + PL::Ns * (int)sizeof(V)) == CU_LDS / REST;
+    static constexpr bool AW_LDS =
+        FT != 0 && (kResident<V, PL, FT, IND> ||
+                    ((PL::IS_COL || (PL::KIND == kSingle && PL::SLOTS >= 2 && PL::Ns <= 2048)) && AW_FITS));
+    static constexpr int AW = AW_LDS ? PL::Ns : 0;
     static constexpr int TWS_OFF = PL::LDS_DATA * (int)sizeof(V);
     static constexpr int AW_OFF = TWS_OFF + TWS * (int)sizeof(V);
     static constexpr int RED_OFF = AW_OFF + AW * (int)sizeof(V);
@@ -1343,6 +1350,8 @@ template <class V, class PL, int FT, bool IND> struct Occupancy {
 template <class V, class PL, int FT, bool IND, int... Rs>
 __global__ __launch_bounds__(PL::THREADS) __attribute__((amdgpu_waves_per_eu(Occupancy<V, PL, FT, IND>::WAVES)))
 void k_fft(const V* __restrict__ x, V* __restrict__ y, KArgs<V> a) {
+    static_assert(Smem<V, PL, FT, IND>::BYTES <= 160 * 1024, "LDS of a workgroup exceeds a CU's");
+    static_assert(!kResident<V, PL, FT, IND> || Smem<V, PL, FT, IND>::AW_LDS, "resident kernels stage e^T W");
     __shared__ __align__(16) char smem[Smem<V, PL, FT, IND>::BYTES];
     if constexpr (kResident<V, PL, FT, IND>) {
         // e^T W into LDS once; every exchange and reduction of the first
