@@ -150,6 +150,10 @@ template <int KIND_, int Ns_, int E_, int WC_, int B_, int... Rs> struct Plan {
     static constexpr int SPW = (!TILE && P <= kWave) ? kWave / P : 1;   // slots per wave
     static constexpr int SLOTS = TILE ? C : (P > kWave ? 1 : WAVES * SPW);
     static constexpr int B = B_;
+    // a single pass of more than one wave per signal with WC = 1: the
+    // streaming form, which reads e^T W from the cached table instead of
+    // staging it in LDS, so that two workgroups share a CU
+    static constexpr bool STREAM = !TILE && P > kWave && WC_ == 1;
     static constexpr int LDS_DATA = TILE ? Ns * C : padded_size<B_>(P > kWave ? Ns : WAVES * SPW * Ns);
     static constexpr int M = (Ns % 3 == 0) ? 5 : 3;            // encoding period
     static_assert(Ns % E == 0, "E must divide Ns");
@@ -689,7 +693,7 @@ template <class V, class PL, bool IND> struct Geo {
 // 8 elements per lane, or 8192 points and up; complex double: 4096 points
 // and up).
 template <class V, class PL, int FT, bool IND> constexpr bool kResident =
-    FT != 0 && !IND && PL::KIND == kSingle && PL::SLOTS == 1 &&
+    FT != 0 && !IND && PL::KIND == kSingle && PL::SLOTS == 1 && !PL::STREAM &&
     (sizeof(V) == 8 ? (PL::E == 8 || PL::Ns >= 8192) : PL::Ns >= 4096);
 
 // LDS of one workgroup of a plan: exchange buffer, then reduction scratch
@@ -1332,8 +1336,8 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
     }
 }
 
-// Occupancy the checking kernels are held to: what their LDS allows, at
-// most four waves per SIMD (three in place).  The error path (correction) needs more registers
+// Occupancy the checking tile and streaming single-pass kernels are held
+// to: what their LDS allows, at most four waves per SIMD (three in place).  The error path (correction) needs more registers
 // than the transform; without the floor the compiler lowers the occupancy of
 // the whole kernel for it and then spends the registers in the hot loop too.
 // With it, the error path spills instead, which costs nothing when no fault
@@ -1344,7 +1348,7 @@ template <class V, class PL, int FT, bool IND> struct Occupancy {
     static constexpr int LDS_WAVES = WG_PER_CU * PL::WAVES / 4;   // per SIMD
     // in place, the right-side input sum stays in registers through the group
     static constexpr int CAP = FT == 3 ? 3 : 4;
-    static constexpr int WAVES = FT == 0 || !PL::TILE ? 1 : (LDS_WAVES < 1 ? 1 : (LDS_WAVES > CAP ? CAP : LDS_WAVES));
+    static constexpr int WAVES = FT == 0 || !(PL::TILE || PL::STREAM) ? 1 : (LDS_WAVES < 1 ? 1 : (LDS_WAVES > CAP ? CAP : LDS_WAVES));
 };
 
 template <class V, class PL, int FT, bool IND, int... Rs>
