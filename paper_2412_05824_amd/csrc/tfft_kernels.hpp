@@ -660,6 +660,9 @@ template <class V, class PL, bool IND> struct Geo {
                     v[k] = acc;
                 }
             }
+            // the space may be the exchange buffer, which the next group
+            // writes next
+            __syncthreads();
         }
     }
     // bit b set when lane tx_lane(b) of this wave has f set (b < T_)
@@ -703,20 +706,29 @@ template <class V, class PL, int FT, bool IND = false> struct Smem {
     static constexpr int RED = FT ? 2 * (PL::TILE ? PL::C : 1) * PL::WAVES * NRED : 1;
     // row pass: the C x E inter-pass twiddle steps of the workgroup's rows
     static constexpr int TWS = PL::KIND == kRowPass ? PL::C * PL::E : 0;
+    // per-transaction checking: wave parts of the kept partials (3 values)
+    using G = Geo<V, PL, IND>;
+    static constexpr int TXR = (FT != 0 && G::TX_PARTS > 1) ? 3 * G::TX_MAX * G::TX_PARTS * (PL::TILE ? PL::C : 1) : 0;
+    // The kept partials are exchanged at the end of a group, when the
+    // exchange buffer is idle (the last exchange of the group's last
+    // transaction has passed its closing barrier, and a barrier follows the
+    // partials' reads): they share its space, so per-transaction checking
+    // costs no LDS.  (Single precision only: the double-precision tiles,
+    // which check per group by default, keep their measured occupancy.)
+    static constexpr bool TXR_ALIAS = sizeof(R) == 4 && TXR * (int)sizeof(R) <= PL::LDS_DATA * (int)sizeof(V);
+    static constexpr int REST = PL::LDS_DATA * (int)sizeof(V) + TWS * (int)sizeof(V) +
+                                (RED + (TXR_ALIAS ? 0 : TXR)) * (int)sizeof(R);
     // ABFT: the left vector e^T W staged once per workgroup where several
     // signals share it and it is small (column tiles; single-pass groups of
     // up to 2048 points); row passes keep reading the cached table, which
     // costs them no registers and saves the staging
-    // per-transaction checking: wave parts of the kept partials (3 values)
-    using G = Geo<V, PL, IND>;
-    static constexpr int TXR = (FT != 0 && G::TX_PARTS > 1) ? 3 * G::TX_MAX * G::TX_PARTS * (PL::TILE ? PL::C : 1) : 0;
-    static constexpr int REST = PL::LDS_DATA * (int)sizeof(V) + TWS * (int)sizeof(V) +
-                                (RED + TXR) * (int)sizeof(R);
     // (and only where it costs no workgroup per CU: a column tile of 1024 or
     // 2048 points would otherwise drop from two to one; resident kernels
     // always stage it)
     static constexpr int CU_LDS = 160 * 1024;
-    static constexpr bool AW_FITS = CU_LDS / (REST + PL::Ns * (int)sizeof(V)) == CU_LDS / REST;
+    static constexpr int WG_CAP = PL::WAVES >= 16 ? 1 : 16 / PL::WAVES;   // four waves per SIMD
+    static constexpr int wg_fit(int bytes) { return CU_LDS / bytes < WG_CAP ? CU_LDS / bytes : WG_CAP; }
+    static constexpr bool AW_FITS = wg_fit(REST + PL::Ns * (int)sizeof(V)) == wg_fit(REST);
     static constexpr bool AW_LDS =
         FT != 0 && (kResident<V, PL, FT, IND> ||
                     ((PL::IS_COL || (PL::KIND == kSingle && PL::SLOTS >= 2 && PL::Ns <= 2048)) && AW_FITS));
@@ -724,8 +736,8 @@ template <class V, class PL, int FT, bool IND = false> struct Smem {
     static constexpr int TWS_OFF = PL::LDS_DATA * (int)sizeof(V);
     static constexpr int AW_OFF = TWS_OFF + TWS * (int)sizeof(V);
     static constexpr int RED_OFF = AW_OFF + AW * (int)sizeof(V);
-    static constexpr int TXR_OFF = RED_OFF + RED * (int)sizeof(R);
-    static constexpr int BYTES = TXR_OFF + TXR * (int)sizeof(R);
+    static constexpr int TXR_OFF = TXR_ALIAS ? 0 : RED_OFF + RED * (int)sizeof(R);
+    static constexpr int BYTES = RED_OFF + RED * (int)sizeof(R) + (TXR_ALIAS ? 0 : TXR * (int)sizeof(R));
 };
 
 // Buffers that other workgroups of the same launch read back (the persistent
