@@ -20,12 +20,14 @@ within twice the precision's tolerance (two correct transforms differ by at
 most the sum of their errors).
 
 Accuracy bounds on T.  Checked once per group, a flip just below the
-detection threshold changes one signal by about kappa * u * sqrt(T * log2 Ns)
-of its norm (Ns the longest pass), which must stay under the acceptance
-tolerance (2e-6 fp32, 1e-13 fp64), so T <= (tol / (kappa * u))^2 / log2 Ns.
+detection threshold changes one signal by about kappa * u * sqrt(T * s) of its
+norm, s the rounding steps per element the threshold counts (log2 Ns, plus 3
+in a pass with an inter-pass twiddle; the largest over the route's passes),
+which must stay under the acceptance tolerance (2e-6 fp32, 1e-13 fp64), so
+T <= (tol / (kappa * u))^2 / s.
 Checked per transaction, each signal has its own threshold; T then only sets
 how many signals share the right-side sums of a correction, whose rounding
-(about u * sqrt(T * log2 Ns) of one signal's norm) stays far below the
+(about u * sqrt(T * s) of one signal's norm) stays far below the
 tolerance up to T = 16, the most a plan keeps; the library reduces a larger
 T to what the plan keeps, and the tuner skips such duplicates.
 
@@ -48,8 +50,18 @@ GRANS = {"fp32": (1, 0), "fp64": (0, 1)}   # per transaction, per group
 CHUNKS_MIB = (16, 32, 64, 128, 256, 512)
 
 
-def max_T(prec: str, longest_pass: int, kappa: float) -> int:
-    lim = (TOL[prec] / (kappa * UNIT[prec])) ** 2 / max(1.0, math.log2(longest_pass))
+def steps(N: int, n1: int, n2: int = 0) -> float:
+    """Rounding steps per element the threshold counts, the largest over the
+    passes of the route (single pass: n1 = 1; two passes: n1, N / n1; three:
+    n1, n2, N / (n1 n2)); passes after the first carry an inter-pass twiddle."""
+    if n1 <= 1:
+        return math.log2(N)
+    rest = [n2, N // (n1 * n2)] if n2 else [N // n1]
+    return max([math.log2(n1)] + [math.log2(m) + 3 for m in rest])
+
+
+def max_T(prec: str, s: float, kappa: float) -> int:
+    lim = (TOL[prec] / (kappa * UNIT[prec])) ** 2 / max(1.0, s)
     return max(1, int(lim))
 
 
@@ -109,12 +121,12 @@ def tune(precisions, logs, modes=(2, 0), reps=5, warmup=2, total_bytes=1 << 30, 
                 for code in codes:
                     n1, va, vb = tf.route_parts(code)
                     n2 = tf.route_n2(code)
-                    longest = N if n1 == 1 else (max(n1, n2, N // (n1 * n2)) if n2 else max(n1, N // n1))
+                    s_route = steps(N, n1, n2)
                     chunks = [None] if n1 == 1 else [c << 20 for c in CHUNKS_MIB]
                     cands = []
                     for gran in (GRANS[prec] if ft else (0,)):
                         # without ABFT, T only sets the signals per workgroup
-                        tmax = 4 if not ft else (16 if gran else max_T(prec, longest, KAPPA[prec]))
+                        tmax = 4 if not ft else (16 if gran else max_T(prec, s_route, KAPPA[prec]))
                         seen = set()
                         for T in [t for t in T_CHOICES if t <= tmax]:
                             tf.set_route(N, dtype, code)

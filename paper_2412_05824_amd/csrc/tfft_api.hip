@@ -530,7 +530,13 @@ void fill_common(KArgs<V>& a, const KernelEntry& e, const SubTables& st, const T
     a.gran = tu.gran;
     const double u = e.precision == TFFT_FP32 ? 0x1p-24 : 0x1p-53;
     const double Ns = (double)e.Ns;
-    a.tau_coef = (R)(tu.kappa * u * std::sqrt(Ns * std::log2(Ns)));
+    // rounding steps per element behind the checked difference: log2 Ns
+    // for the butterflies, and three more where a pass multiplies its input
+    // by an inter-pass twiddle (the twiddle, a product of two table values,
+    // then its products with the value and with the left vector)
+    const bool tw = e.kind == kRowPass || e.kind == kColPass3 || e.kind == kRowPass3;
+    const double steps = std::log2(Ns) + (tw ? 3.0 : 0.0);
+    a.tau_coef = (R)(tu.kappa * u * std::sqrt(Ns * steps));
     a.cap = e.precision == TFFT_FP32 ? (R)0x1p64 : (R)0x1p512;
     a.counts = reinterpret_cast<FtCounts*>(counts);
     a.inj_signal = -1;

@@ -112,7 +112,8 @@ template <class V> struct KArgs : KCall<typename RealOf<V>::type> {
     long long p3_M;
     int T;                // transactions (signals) per slot
     long long sig_base;   // global index of local signal 0 (counters only)
-    R tau_coef;           // kappa * u * sqrt(Ns log2 Ns); tau = tau_coef * sqrt(nu)
+    R tau_coef;           // kappa * u * sqrt(Ns s), s = log2 Ns (+ 3 with an inter-pass
+                          // twiddle); tau = tau_coef * sqrt(nu)
     R cap;                // magnitude cap: larger outputs mark their signal corrupted
     int gran;             // detection granularity: 0 once per group of T transactions
                           // (location by D1/D0), 1 per transaction (note and continue)

@@ -231,12 +231,11 @@ def test_shipped_tuning_table_is_complete_and_consistent():
             route = lambda e: (e.get("split_n1", 1), e.get("variant_a", 0), e.get("variant_b", 0))
             assert route(on) == route(off), (prec, N)
             n1 = on.get("split_n1", 1)
-            longest = N if n1 <= 1 else max(n1, N // n1)
             gran = on.get("gran", 0)
             assert gran in (0, 1), (prec, N, gran)
             # checked per transaction, each signal has its own threshold: T
             # only sets the sums a correction uses (at most 16 per group)
-            tmax = 16 if gran else autotune.max_T(prec, longest, on["kappa"])
+            tmax = 16 if gran else autotune.max_T(prec, autotune.steps(N, n1, on.get("split_n2", 0)), on["kappa"])
             assert 1 <= on["T"] <= tmax, (prec, N, on["T"], gran)
             assert math.isfinite(on["kappa"]) and on["kappa"] > 0
     lib = _lib.load()
