@@ -304,7 +304,7 @@ int tfft_set_chunk(long long N, int precision, long long chunk_bytes);
  *     code = n1 | va << 32 | vb << 40 | log2(n2) << 48
  * with n1 = 1 for a single pass of plan variant va; n1 > 1 and no n2 for a
  * column pass of variant va and a row pass of variant vb; n1 > 1 and n2 for
- * three passes, column pass variant va (vb = 0).  Code 0 is the default
+ * three passes, first column pass variant va and last row pass variant vb.  Code 0 is the default
  * policy (single pass when built, else the most balanced two-pass split,
  * else the three-pass split with the smallest largest length, variants 0).
  * The passes of three-pass routes check groups of one signal (T = 1).

@@ -12,6 +12,9 @@ void register_fp32_three(std::vector<KernelEntry>& out) {
     add_plan<float2, kColPass3, 512, 16, 16, 0, 2, 16, 16>(out, 0);
     add_plan<float2, kRowPass3, 256, 16, 8, 0, 16, 16>(out, 0);
     add_plan<float2, kRowPass3, 512, 16, 8, 0, 2, 16, 16>(out, 0);
+    // variant 1: 16 rows per tile, 128-byte output runs
+    add_plan<float2, kRowPass3, 256, 16, 16, 0, 16, 16>(out, 0, 1);
+    add_plan<float2, kRowPass3, 512, 16, 16, 0, 2, 16, 16>(out, 0, 1);
 }
 
 }  // namespace tfft

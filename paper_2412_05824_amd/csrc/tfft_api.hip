@@ -205,7 +205,8 @@ struct Route {
 // Route codes: n1 | va << 32 | vb << 40 | lg2(n2) << 48.  n1 = 1: single
 // pass, plan variant va; n1 > 1 with no n2: column pass of n1 points
 // (variant va), then row pass of N/n1 (variant vb); n1 > 1 with n2: the
-// three passes N = n1 n2 (N / (n1 n2)), column pass variant va; code 0: the
+// three passes N = n1 n2 (N / (n1 n2)), first column pass variant va, last
+// row pass variant vb; code 0: the
 // default policy (single pass when built, else the most balanced two-pass
 // split, else the most balanced three-pass split, variants 0).
 constexpr long long route_code(long long n1, int va, int vb, int lg_n2 = 0) {
@@ -233,14 +234,14 @@ constexpr long long kMaxThreePassBytes = 1ll << 32;
 // a three-pass split N = n1 n2 n3 with compiled kernels whose tiles divide
 // the lengths they walk: M = n2 n3 columns of pass 1, n3 columns of pass 2,
 // n1 rows of pass 3
-bool split3_ok(int precision, long long N, int ft, long long n1, long long n2, int va = 0) {
+bool split3_ok(int precision, long long N, int ft, long long n1, long long n2, int va = 0, int vb = 0) {
     if (n1 < 2 || n2 < 2 || N % (n1 * n2)) return false;
     const size_t S = precision == TFFT_FP32 ? 8 : 16;
     if ((double)N * (double)S > (double)kMaxThreePassBytes) return false;
     const long long n3 = N / (n1 * n2);
     const KernelEntry* a = find_entry(precision, kColPass, n1, ft, va);
     const KernelEntry* b = find_entry(precision, kColPass3, n2, ft, 0);
-    const KernelEntry* c = find_entry(precision, kRowPass3, n3, ft, 0);
+    const KernelEntry* c = find_entry(precision, kRowPass3, n3, ft, vb);
     return a && b && c && (n2 * n3) % a->slots_per_block == 0 && n3 % b->slots_per_block == 0 &&
            n1 % c->slots_per_block == 0;
 }
@@ -264,7 +265,7 @@ bool route_for(int precision, long long N, int ft, Route* r, long long code = 0)
     long long n1 = 0, n2 = 0;
     if (code != 0) {
         if (lgn2 != 0) {
-            if (vb != 0 || !split3_ok(precision, N, ft, n1c, 1ll << lgn2, va)) return false;
+            if (!split3_ok(precision, N, ft, n1c, 1ll << lgn2, va, vb)) return false;
             n2 = 1ll << lgn2;
         } else if (!split_ok(precision, N, ft, n1c, va, vb)) {
             return false;
@@ -292,7 +293,7 @@ bool route_for(int precision, long long N, int ft, Route* r, long long code = 0)
         r->N3 = N / (n1 * n2);
         r->col = find_entry(precision, kColPass, n1, ft, code ? va : 0);
         r->col3 = find_entry(precision, kColPass3, n2, ft, 0);
-        r->row3 = find_entry(precision, kRowPass3, r->N3, ft, 0);
+        r->row3 = find_entry(precision, kRowPass3, r->N3, ft, code ? vb : 0);
         return true;
     }
     r->N2 = N / n1;
@@ -304,7 +305,7 @@ bool route_for(int precision, long long N, int ft, Route* r, long long code = 0)
 // the route's code (what route_for reproduces it from)
 long long code_of(const Route& r) {
     if (r.single) return route_code(1, r.single->variant, 0);
-    if (r.row3) return route_code(r.N1, r.col->variant, 0, lg2(r.N2));
+    if (r.row3) return route_code(r.N1, r.col->variant, r.row3->variant, lg2(r.N2));
     return route_code(r.N1, r.col->variant, r.row->variant);
 }
 
@@ -1407,7 +1408,8 @@ int tfft_routes(long long N, int precision, int ft_mode, long long* codes, int c
     for (long long c = 2; c < N; c <<= 1)
         for (long long b = 2; c * b < N; b <<= 1)
             for (int va = 0; va < 8; ++va)
-                if (split3_ok(precision, N, ft_mode, c, b, va)) put_route(route_code(c, va, 0, lg2(b)));
+                for (int vb = 0; vb < 8; ++vb)
+                    if (split3_ok(precision, N, ft_mode, c, b, va, vb)) put_route(route_code(c, va, vb, lg2(b)));
     return n;
 }
 

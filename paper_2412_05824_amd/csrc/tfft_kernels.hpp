@@ -345,8 +345,8 @@ template <class V, class PL, bool IND> struct Geo {
     long long sig_u0;    // wave-uniform signal of transaction 0 (slot 0 of the wave)
     unsigned lane_in;    // this lane's element offset within a transaction's input
     unsigned lane_out;   // and within its output
-    V tw_base{(R)1, (R)0};       // row pass: w_N^{t k1} of this lane
-    const V* tw_step = nullptr;  // row pass: LDS table w_N^{P r k1} of the tile's rows
+    V tw_base{(R)1, (R)0};       // passes with a twiddle: this lane's w^{k (b + D t)}
+    const V* tw_step = nullptr;  // and the LDS table of the steps w^{k D P r}
 
     __device__ __forceinline__ Geo(const KArgs<V>& a, long long block, long long nblocks, int tid_)
         : tid(tid_) {
@@ -529,22 +529,31 @@ template <class V, class PL, bool IND> struct Geo {
             }
             tw_base = twiddle_at(a, (unsigned)t * (unsigned)line);          // t k1 < N
             tw_step = steps;
+        } else if constexpr (PL::KIND == kColPass3 || PL::KIND == kRowPass3) {
+            // Three-pass passes run one signal per workgroup (groups of one
+            // transaction), whose k (k1 = s mod N1 or k2 = s mod N2) every
+            // lane shares: w^{k (b + D t)} w^{k D P r} with D = N3 (pass 1,
+            // b = n3 = line, table of N) or D = 1 (pass 2, b = 0, table of M);
+            // both exponents stay below the table's length.
+            constexpr bool P1 = PL::KIND == kColPass3;
+            const unsigned k = (unsigned)(sig0 % (P1 ? a.p3_n1 : a.p3_n2));
+            const unsigned D = P1 ? (unsigned)a.N2 : 1u;
+            for (int i = tid; i < E; i += PL::THREADS) steps[i] = twiddle_at(a, k * D * (unsigned)P * (unsigned)i);
+            tw_base = twiddle_at(a, k * ((P1 ? (unsigned)line : 0u) + D * (unsigned)t));
+            tw_step = steps;
         }
     }
     // inter-pass twiddle of element t + P r of local signal s (1 where a
-    // pass has none); the row pass's LDS steps must be visible (barrier after
-    // twiddle_setup).  Three-pass passes form it from the table per element.
+    // pass has none); the LDS steps must be visible (barrier after
+    // twiddle_setup).  A three-pass pass's steps belong to the workgroup's
+    // one signal: s is that signal.
     __device__ __forceinline__ V twiddle(const KArgs<V>& a, long long s, int r) const {
+        (void)a;
+        (void)s;
         if constexpr (PL::KIND == kRowPass) {
             return cmul(tw_base, tw_step[slot * E + r]);
-        } else if constexpr (PL::KIND == kColPass3) {
-            // w_N^{k1 (n2 N3 + n3)}, k1 = s mod N1, n2 = t + P r, n3 = line (< N)
-            const unsigned k1 = (unsigned)(s % a.p3_n1);
-            return twiddle_at(a, k1 * ((unsigned)(t + P * r) * (unsigned)a.N2 + (unsigned)line));
-        } else if constexpr (PL::KIND == kRowPass3) {
-            // w_M^{k2 n3}, k2 = s mod N2, n3 = t + P r (< M)
-            const unsigned k2 = (unsigned)(s % a.p3_n2);
-            return twiddle_at(a, k2 * (unsigned)(t + P * r));
+        } else if constexpr (PL::KIND == kColPass3 || PL::KIND == kRowPass3) {
+            return cmul(tw_base, tw_step[r]);
         } else {
             return V{(R)1, (R)0};
         }
@@ -705,8 +714,9 @@ template <class V, class PL, int FT, bool IND = false> struct Smem {
     using R = typename RealOf<V>::type;
     static constexpr int NRED = 6;
     static constexpr int RED = FT ? 2 * (PL::TILE ? PL::C : 1) * PL::WAVES * NRED : 1;
-    // row pass: the C x E inter-pass twiddle steps of the workgroup's rows
-    static constexpr int TWS = PL::KIND == kRowPass ? PL::C * PL::E : 0;
+    // row pass: the C x E inter-pass twiddle steps of the workgroup's rows;
+    // three-pass passes: the E steps of the workgroup's one signal
+    static constexpr int TWS = PL::KIND == kRowPass ? PL::C * PL::E : (PL::HAS_TW ? PL::E : 0);
     // per-transaction checking: wave parts of the kept partials (3 values)
     using G = Geo<V, PL, IND>;
     static constexpr int TXR = (FT != 0 && G::TX_PARTS > 1) ? 3 * G::TX_MAX * G::TX_PARTS * (PL::TILE ? PL::C : 1) : 0;
@@ -846,12 +856,12 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
         }
         left = awl;
     }
-    if constexpr (PL::KIND == kRowPass)
+    if constexpr (PL::HAS_TW)
         g.twiddle_setup(a, reinterpret_cast<V*>(smem + Smem<V, PL, FT, IND>::TWS_OFF));
     // these tables are written by some waves and read by all: a workgroup
     // barrier whenever the workgroup has more than one wave (sub-wave slots
     // otherwise only synchronise within their wave)
-    if constexpr (PL::KIND == kRowPass || (Smem<V, PL, FT, IND>::AW_LDS && !kResident<V, PL, FT, IND>))
+    if constexpr (PL::HAS_TW || (Smem<V, PL, FT, IND>::AW_LDS && !kResident<V, PL, FT, IND>))
         lds_sync<(PL::THREADS > kWave)>();
     const auto li = g.lidx();
     constexpr bool KEEP_XS = FT == 3;   // in place: inputs are gone after the store

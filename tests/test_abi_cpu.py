@@ -347,8 +347,8 @@ def test_three_pass_routes():
         assert lib.tfft_get_route(1 << 22, FP32, 2, ctypes.byref(v)) == 0 and v.value == three[0]
         assert lib.tfft_route_info(1 << 22, FP32, 2, buf, 12) == 0 and buf[0] == 3
         assert buf[2] == tff.route_n2(three[0])
-        # a row-pass variant has no meaning on three passes; n2 must divide
-        assert lib.tfft_set_route(1 << 22, FP32, three[0] | (1 << 40)) == _lib.TFFT_EUNSUPPORTED
+        # an unbuilt last-pass variant; n2 must divide
+        assert lib.tfft_set_route(1 << 22, FP32, three[0] | (7 << 40)) == _lib.TFFT_EUNSUPPORTED
         assert lib.tfft_set_route(1 << 22, FP32, tff.route_code(64, 0, 0, 1 << 17)) == _lib.TFFT_EUNSUPPORTED
         assert lib.tfft_set_route(1 << 22, FP32, 1 << 54) == _lib.TFFT_EUNSUPPORTED
     finally:
