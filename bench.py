@@ -44,6 +44,14 @@ HBM_PEAK_GBS = 8000.0
 TOTAL_ELEMS = 1 << 27          # 1 GiB of complex64 per buffer
 
 
+def kernel_label(k: dict) -> str:
+    """Name of one plan's kernel in the launch-timing log, as the profile
+    summaries name it: precision, kind, length, E, width (C sub-signals of a
+    tile or W waves of a single pass), ABFT mode."""
+    w = "W" if k["kind"] in ("single", "ragged") else "C"
+    return f"{k['precision']} {k['kind']} Ns={k['Ns']} E={k['E']} {w}={k['width']} ft={k['ft']}"
+
+
 def kernel_fingerprint() -> str:
     """Hash of the kernel sources and the tuning table (which sets the bytes
     per launch), to match stored counter readings to the library being timed."""
@@ -52,7 +60,8 @@ def kernel_fingerprint() -> str:
     pkg = os.path.join(ROOT, "paper_2412_05824_amd")
     for f in ("csrc/tfft_device.hpp", "csrc/tfft_kernels.hpp", "csrc/inst_fp32_single.hip",
               "csrc/inst_fp32_single_e8.hip",
-              "csrc/inst_fp32_tiles.hip", "csrc/inst_fp32_tiles_narrow.hip", "csrc/inst_fp32_tiles_e8.hip",
+              "csrc/inst_fp32_single_stream.hip", "csrc/inst_fp32_tiles.hip", "csrc/inst_fp32_tiles_narrow.hip",
+              "csrc/inst_fp32_tiles_e8.hip", "csrc/inst_fp32_tiles_wide.hip", "csrc/inst_fp32_three.hip",
               "tuning/mi355x.json"):
         path = os.path.join(pkg, f)
         if os.path.exists(path):
@@ -191,7 +200,7 @@ def main():
     # table and the choice of the kernel that takes most of the step.  In the
     # timed steps only that kernel's launches are bracketed (events cost the
     # stream a few microseconds each: on every launch, 4 % of the step).
-    lib.tfft_profile_only(-1, -1, -1, -1)
+    lib.tfft_profile_only(-1, -1, -1, -1, -1)
     lib.tfft_profile(1)
     _lib.profile_read()
     for _ in range(args.warmup):
@@ -203,11 +212,11 @@ def main():
         k0 = max(kernels, key=lambda k: k["total_ms"])
         _lib.check(lib.tfft_profile_only(0 if k0["precision"] == "fp32" else 1,
                                          ("single", "colpass", "rowpass", "ragged", "colpass3", "rowpass3").index(k0["kind"]),
-                                         k0["Ns"], k0["ft"]), "tfft_profile_only")
+                                         k0["Ns"], k0["ft"], k0["variant"]), "tfft_profile_only")
     total_ms = time_sweep(tf.FT_CORRECT, args.steps, 0, per_kernel=per_kernel_ms)
     timed = [k for k in _lib.profile_read() if k["ft"] >= 2]
     lib.tfft_profile(0)
-    lib.tfft_profile_only(-1, -1, -1, -1)
+    lib.tfft_profile_only(-1, -1, -1, -1, -1)
     kernels_from = "warmup steps (every launch timed)"
     if not kernels:   # no warmup: every launch was timed in the timed steps
         kernels, kernels_from = timed, "timed steps"
@@ -246,7 +255,7 @@ def main():
 
     # ---- roofline of the kernel that takes most of the step (timed steps) ----
     dom = max(timed, key=lambda k: k["total_ms"])
-    dom_name = f"{dom['precision']} {dom['kind']} Ns={dom['Ns']} ft={dom['ft']}"
+    dom_name = kernel_label(dom)
     dom_avg_ms = dom["total_ms"] / dom["launches"]
     dom_bytes = dom["bytes"] / dom["launches"]
     achieved = dom_bytes / (dom_avg_ms * 1e-3) / 1e9
@@ -311,7 +320,7 @@ def main():
                      "avg_launch_us": round(dom_avg_ms * 1e3, 2),
                      "bytes_per_launch": dom_bytes,
                      "share_of_step": round(dom["total_ms"] / total_ms, 3)},
-        "kernels": [{**k, "avg_us": round(1e3 * k["total_ms"] / k["launches"], 2),
+        "kernels": [{"label": kernel_label(k), **k, "avg_us": round(1e3 * k["total_ms"] / k["launches"], 2),
                      "gbs": round(k["bytes"] / (k["total_ms"] * 1e-3) / 1e9, 1)} for k in
                     sorted(kernels, key=lambda k: -k["total_ms"])],
         "kernels_from": kernels_from,
@@ -453,13 +462,13 @@ def three_pass_sweep(tf, torch, np, dev, args, x1g):
             ms[ft] = a.elapsed_time(b) / reps
         clean = tf.counts_dict(counts)["detected"]
         # per-pass kernel times (every launch bracketed by events)
-        lib.tfft_profile_only(-1, -1, -1, -1)
+        lib.tfft_profile_only(-1, -1, -1, -1, -1)
         lib.tfft_profile(1)
         _lib.profile_read()
         for _ in range(reps):
             tf.fft_c2c(x, ft_mode=tf.FT_CORRECT, out=y, counts=counts)
         torch.cuda.synchronize()
-        passes = [{"kind": k["kind"], "Ns": k["Ns"], "launches": k["launches"],
+        passes = [{"kind": k["kind"], "Ns": k["Ns"], "E": k["E"], "width": k["width"], "launches": k["launches"],
                    "avg_us": round(1e3 * k["total_ms"] / k["launches"], 2),
                    "gbs": round(k["bytes"] / (k["total_ms"] * 1e-3) / 1e9, 1)}
                   for k in _lib.profile_read()]

@@ -360,19 +360,22 @@ int tfft_calibration(int on);
  * (host memory of buflen bytes), clears the log and returns the text length;
  * with buf == NULL it returns the size needed instead.  kind is single,
  * colpass, rowpass, ragged, colpass3 or rowpass3; algorithmic bytes count
- * each launch's input read and output write once. */
+ * each launch's input read and output write once.  Three more fields follow
+ * on each line: the plan variant, E (elements per lane) and the width (sub-
+ * signals per workgroup of a tile, waves per workgroup of a single pass), so
+ * variants of one length are reported apart. */
 int tfft_profile(int on);
 int tfft_profile_read(char* buf, long long buflen);
 
 /* Restrict the per-launch timing above to the launches of one kernel:
  * precision (TFFT_FP32 / TFFT_FP64), kind (0 single, 1 colpass, 2 rowpass,
  * 3 ragged persistent, 4 colpass3, 5 rowpass3: the second and third pass of
- * a three-pass length), sub-length Ns and ABFT mode ft; -1 in a field
+ * a three-pass length), sub-length Ns, ABFT mode ft and plan variant; -1 in a field
  * matches any value (all -1, the default, times every launch).  Events cost
  * the stream a few microseconds per launch, so a benchmark that times one
  * kernel live brackets only that kernel's launches.  Returns TFFT_EINVAL
  * for a value out of range. */
-int tfft_profile_only(int precision, int kind, int Ns, int ft);
+int tfft_profile_only(int precision, int kind, int Ns, int ft, int variant);
 
 const char* tfft_strerror(int status);
 int tfft_last_hip_error(void);

@@ -59,7 +59,7 @@ SIGNATURES = {
     "tfft_calibration": ([_I], _I),
     "tfft_profile": ([_I], _I),
     "tfft_profile_read": ([ctypes.c_char_p, _LL], _I),
-    "tfft_profile_only": ([_I, _I, _I, _I], _I),
+    "tfft_profile_only": ([_I, _I, _I, _I, _I], _I),
     "tfft_set_chunk": ([_LL, _I, _LL], _I),
     "tfft_routes": ([_LL, _I, _I, ctypes.POINTER(_LL), _I], _I),
     "tfft_set_route": ([_LL, _I, _LL], _I),
@@ -128,7 +128,8 @@ def profile_read() -> list:
         raise TfftError(rc, "tfft_profile_read")
     rows = []
     for line in buf.value.decode().splitlines():
-        prec, kind, ns, ft, n_l, ms, nbytes = line.split()
+        prec, kind, ns, ft, n_l, ms, nbytes, var, e, width = line.split()
         rows.append({"precision": prec, "kind": kind, "Ns": int(ns), "ft": int(ft),
-                     "launches": int(n_l), "total_ms": float(ms), "bytes": float(nbytes)})
+                     "launches": int(n_l), "total_ms": float(ms), "bytes": float(nbytes),
+                     "variant": int(var), "E": int(e), "width": int(width)})
     return rows

@@ -146,11 +146,11 @@ struct LaunchRec {
     double bytes;
 };
 bool g_prof = false;
-int g_prof_sel[4] = {-1, -1, -1, -1};   // precision, kind, Ns, ft of the timed kernel; -1: any
+int g_prof_sel[5] = {-1, -1, -1, -1, -1};   // precision, kind, Ns, ft, variant of the timed kernel; -1: any
 std::vector<LaunchRec> g_prof_log;
 bool prof_selected(const KernelEntry& e) {
-    const int v[4] = {e.precision, e.kind, e.Ns, e.ft};
-    for (int i = 0; i < 4; ++i)
+    const int v[5] = {e.precision, e.kind, e.Ns, e.ft, e.variant};
+    for (int i = 0; i < 5; ++i)
         if (g_prof_sel[i] >= 0 && g_prof_sel[i] != v[i]) return false;
     return true;
 }
@@ -1584,14 +1584,16 @@ int tfft_profile(int on) {
     return TFFT_OK;
 }
 
-int tfft_profile_only(int precision, int kind, int Ns, int ft) {
-    if (precision < -1 || precision > TFFT_FP64 || kind < -1 || kind > 5 || Ns < -1 || ft < -1 || ft > 3)
+int tfft_profile_only(int precision, int kind, int Ns, int ft, int variant) {
+    if (precision < -1 || precision > TFFT_FP64 || kind < -1 || kind > 5 || Ns < -1 || ft < -1 || ft > 3 ||
+        variant < -1 || variant > 255)
         return TFFT_EINVAL;
     std::lock_guard<std::mutex> lk(g_mu);
     g_prof_sel[0] = precision;
     g_prof_sel[1] = kind;
     g_prof_sel[2] = Ns;
     g_prof_sel[3] = ft;
+    g_prof_sel[4] = variant;
     return TFFT_OK;
 }
 
@@ -1599,11 +1601,14 @@ int tfft_profile_read(char* buf, long long buflen) {
     std::lock_guard<std::mutex> lk(g_mu);
     // aggregate the pending launches per kernel: launches, total ms, bytes
     struct Agg { long long n = 0; double ms = 0, bytes = 0; };
-    std::map<std::tuple<int, int, int, int>, Agg> agg;
+    // per plan: precision, kind, Ns, ft, variant, E, width (sub-signals of a
+    // tile, waves of a single-pass workgroup)
+    std::map<std::tuple<int, int, int, int, int, int, int>, Agg> agg;
     for (LaunchRec& r : g_prof_log) {
         float ms = 0.f;
         if (hipEventSynchronize(r.stop) == hipSuccess && hipEventElapsedTime(&ms, r.start, r.stop) == hipSuccess) {
-            Agg& g = agg[std::make_tuple(r.e->precision, r.e->kind, r.e->Ns, r.e->ft)];
+            const int width = r.e->kind == kSingle ? r.e->threads / 64 : r.e->slots_per_block;
+            Agg& g = agg[std::make_tuple(r.e->precision, r.e->kind, r.e->Ns, r.e->ft, r.e->variant, r.e->E, width)];
             g.n += 1;
             g.ms += ms;
             g.bytes += r.bytes;
@@ -1615,9 +1620,10 @@ int tfft_profile_read(char* buf, long long buflen) {
     static const char* kinds[] = {"single", "colpass", "rowpass", "ragged", "colpass3", "rowpass3"};
     for (auto& kv : agg) {
         char line[256];
-        snprintf(line, sizeof(line), "%s %s %d %d %lld %.6f %.1f\n",
+        snprintf(line, sizeof(line), "%s %s %d %d %lld %.6f %.1f %d %d %d\n",
                  std::get<0>(kv.first) == TFFT_FP32 ? "fp32" : "fp64", kinds[std::get<1>(kv.first)],
-                 std::get<2>(kv.first), std::get<3>(kv.first), kv.second.n, kv.second.ms, kv.second.bytes);
+                 std::get<2>(kv.first), std::get<3>(kv.first), kv.second.n, kv.second.ms, kv.second.bytes,
+                 std::get<4>(kv.first), std::get<5>(kv.first), std::get<6>(kv.first));
         g_prof_text += line;
     }
     if (!buf) return (int)g_prof_text.size() + 1;   // size query keeps the text

@@ -75,12 +75,13 @@ def test_invalid_arguments_rejected_on_host():
     assert lib.tfft_prepare(256, -1, 0, 0, None) == _lib.TFFT_EINVAL
     assert lib.tfft_prepare(100, 0, 0, 0, None) == _lib.TFFT_EUNSUPPORTED
     # launch-timing filter: fields in range or -1 (any)
-    assert lib.tfft_profile_only(2, -1, -1, -1) == _lib.TFFT_EINVAL
-    assert lib.tfft_profile_only(-1, 6, -1, -1) == _lib.TFFT_EINVAL
-    assert lib.tfft_profile_only(-1, -1, -2, -1) == _lib.TFFT_EINVAL
-    assert lib.tfft_profile_only(-1, -1, -1, 4) == _lib.TFFT_EINVAL
-    assert lib.tfft_profile_only(0, 2, 2048, 2) == _lib.TFFT_OK
-    assert lib.tfft_profile_only(-1, -1, -1, -1) == _lib.TFFT_OK
+    assert lib.tfft_profile_only(2, -1, -1, -1, -1) == _lib.TFFT_EINVAL
+    assert lib.tfft_profile_only(-1, 6, -1, -1, -1) == _lib.TFFT_EINVAL
+    assert lib.tfft_profile_only(-1, -1, -2, -1, -1) == _lib.TFFT_EINVAL
+    assert lib.tfft_profile_only(-1, -1, -1, 4, -1) == _lib.TFFT_EINVAL
+    assert lib.tfft_profile_only(-1, -1, -1, -1, -2) == _lib.TFFT_EINVAL
+    assert lib.tfft_profile_only(0, 2, 2048, 2, 3) == _lib.TFFT_OK
+    assert lib.tfft_profile_only(-1, -1, -1, -1, -1) == _lib.TFFT_OK
 
 
 def test_supported_sizes_and_tuning_roundtrip():
