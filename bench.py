@@ -99,10 +99,11 @@ def parse():
     p.add_argument("--ragged-signals", type=int, default=10000)
     p.add_argument("--copy-ref", action="store_true",
                    help="only run a plain 1 GiB device copy (reference for counter scaling)")
-    p.add_argument("--study", choices=("roc", "ablation", "offline"), default=None,
+    p.add_argument("--study", choices=("roc", "ablation", "offline", "stepwise"), default=None,
                    help="only run a study and print its JSON line: roc (detection vs false alarm over "
                         "the threshold), ablation (ABFT granularity x transactions per group), offline "
-                        "(fused vs unfused ABFT)")
+                        "(fused vs unfused ABFT), stepwise (the plain transform from per-stage radix-2 "
+                        "launches to the tuned plans)")
     return p.parse_args()
 
 
@@ -131,7 +132,8 @@ def main():
     if args.study:
         fn = {"roc": lambda: roc_study(tf, torch, np, dev),
               "ablation": lambda: ablation_study(tf, torch, dev),
-              "offline": lambda: offline_study(tf, torch, dev)}[args.study]
+              "offline": lambda: offline_study(tf, torch, dev),
+              "stepwise": lambda: stepwise_study(tf, torch, dev)}[args.study]
         print(json.dumps({"study": args.study, **fn()}), flush=True)
         return
     if args.copy_ref:
@@ -848,6 +850,49 @@ def ablation_study(tf, torch, dev, reps=5):
         torch.cuda.empty_cache()
     return {"workload": "1 GiB uniform batch per length, forward, tuned route; plain kernel at its best of T = 1, 2",
             "rows": rows}
+
+
+def stepwise_study(tf, torch, dev, reps=3):
+    """The plain transform (no ABFT) at the four levels of tfft_c2c_stepwise
+    (Sec. 5.1's v0 -> v3 chain): 0 one launch per radix-2 stage through
+    global memory, 1 all radix-2 stages in one launch through LDS (N <= 8192),
+    2 the default plans (radix-16 stages, untuned), 3 the tuned routes.
+    complex64 forward, batch 2^27 / N (1 GiB), N = 2^6..2^22; GB/s counts the
+    transform's input and output once, GFLOPS 5 N log2 N per signal."""
+    total = TOTAL_ELEMS
+    g = torch.Generator(device=dev)
+    g.manual_seed(2600)
+    x = (torch.rand(total, 2, device=dev, generator=g) * 2 - 1).view(torch.complex64).view(-1)
+    y = torch.empty_like(x)
+    out = {}
+    for lg in range(6, 23):
+        N = 1 << lg
+        xv, yv = x.view(-1, N), y.view(-1, N)
+        row = {}
+        for level in (0, 1, 2, 3):
+            if level == 1 and N > 8192:
+                continue
+            fn = lambda: tf.fft_c2c_stepwise(xv, level, out=yv)
+            fn()
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(reps):
+                fn()
+            b.record()
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b) / reps
+            row[f"v{level}"] = {"ms": round(ms, 4), "gbs": round(2 * total * 8 / (ms * 1e-3) / 1e9, 1),
+                                "gflops": round(5.0 * total * lg / (ms * 1e-3) / 1e9, 1)}
+        out[str(N)] = row
+        print(f"# stepwise N=2^{lg}: " + ", ".join(f"{k} {v['gbs']} GB/s" for k, v in row.items()),
+              file=sys.stderr, flush=True)
+    del x, y
+    torch.cuda.empty_cache()
+    return {"workload": "complex64 forward, batch 2^27/N (1 GiB), inputs U[-1,1), no ABFT; v0 per-stage "
+                        "radix-2 launches, v1 radix-2 stages in one launch, v2 default plans, v3 tuned",
+            "per_n": out}
 
 
 def offline_study(tf, torch, dev, reps=5):

@@ -99,6 +99,23 @@ int tfft_c2c(const void* x, void* y, long long N, long long batch, int dir, int 
 int tfft_c2c_offline(const void* x, void* y, long long N, long long batch, int dir, int precision,
                      double scale, tfft_ft_counts* counts, void* hip_stream);
 
+/* The transform without ABFT at four levels of the stepwise study of the
+ * transform itself (Sec. 5.1, versions v0..v3): single precision, N a power
+ * of two, out of place (x and y must not overlap; TFFT_EINVAL otherwise).
+ *   level 0  one kernel launch per radix-2 stage, each reading and writing
+ *            global memory (log2 N launches, a library workspace for the
+ *            intermediate);
+ *   level 1  one launch, every radix-2 stage exchanged through LDS
+ *            (N <= 8192, TFFT_EUNSUPPORTED beyond);
+ *   level 2  the library's default route and plans (radix-16 stages, no
+ *            tuning table);
+ *   level 3  the tuned route (the tuning table's plain-mode entry), as
+ *            tfft_c2c with TFFT_FT_OFF.
+ * dir as for tfft_c2c; the inverse is scaled by 1/N.  A measurement aid:
+ * all levels compute the same transform. */
+int tfft_c2c_stepwise(const void* x, void* y, long long N, long long batch, int dir, int level,
+                      void* hip_stream);
+
 /* Size of the static device scratch buffer of tfft_c2c_noalloc (bytes). */
 #define TFFT_NOALLOC_SCRATCH_BYTES (64ull << 20)
 

@@ -60,6 +60,7 @@ SIGNATURES = {
     "tfft_profile": ([_I], _I),
     "tfft_profile_read": ([ctypes.c_char_p, _LL], _I),
     "tfft_profile_only": ([_I, _I, _I, _I, _I], _I),
+    "tfft_c2c_stepwise": ([_VP, _VP, _LL, _LL, _I, _I, _VP], _I),
     "tfft_set_chunk": ([_LL, _I, _LL], _I),
     "tfft_routes": ([_LL, _I, _I, ctypes.POINTER(_LL), _I], _I),
     "tfft_set_route": ([_LL, _I, _LL], _I),

@@ -469,8 +469,8 @@ bool capturing(hipStream_t stream) {
 
 // Cached resources; built unless the stream is being captured.  Caller holds g_mu.
 long long radix_signature(const KernelEntry& e) {
-    long long sig = 0;
-    for (int s = 0; s < e.n_stages; ++s) sig = sig * 32 + e.radices[s];
+    long long sig = 0;   // radices <= 16, at most 14 stages: 17^14 < 2^63
+    for (int s = 0; s < e.n_stages; ++s) sig = sig * 17 + e.radices[s];
     return sig;
 }
 
@@ -1770,6 +1770,79 @@ int tfft_c2c(const void* x, void* y, long long N, long long batch, int dir, int 
 int tfft_c2c_noalloc(const void* x, void* y, long long N, long long batch, int dir, int precision,
                      int ft_mode, double scale, tfft_ft_counts* counts, void* hip_stream) {
     return c2c_impl(x, y, N, batch, dir, precision, ft_mode, scale, counts, hip_stream, true);
+}
+
+int tfft_c2c_stepwise(const void* x, void* y, long long N, long long batch, int dir, int level,
+                      void* hip_stream) {
+    if (N < 2 || batch < 0 || (dir != TFFT_FORWARD && dir != TFFT_INVERSE) || level < 0 || level > 3)
+        return TFFT_EINVAL;
+    if (!is_pow2(N)) return TFFT_EUNSUPPORTED;
+    if (batch == 0) return TFFT_OK;
+    if (!x || !y) return TFFT_EINVAL;
+    if (((uintptr_t)x % 8) || ((uintptr_t)y % 8)) return TFFT_EALIGN;
+    const size_t bytes = (size_t)N * (size_t)batch * 8;
+    const char* xb = static_cast<const char*>(x);
+    const char* yb = static_cast<const char*>(y);
+    if (xb < yb + bytes && yb < xb + bytes) return TFFT_EINVAL;   // out of place only
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    const double scale = dir == TFFT_INVERSE ? 1.0 / (double)N : 1.0;
+    std::lock_guard<std::mutex> lk(g_mu);
+    ensure_registry();
+    const bool may_alloc = !capturing(stream);
+    if (level == 0) {
+        // one launch per radix-2 stage, ping-pong so the last lands in y
+        int S = 0;
+        while ((1ll << S) < N) ++S;
+        PassTwiddle* pt = nullptr;
+        int rc = get_pass(TFFT_FP32, N, may_alloc, &pt);
+        if (rc != TFFT_OK) return rc;
+        void* ws = nullptr;
+        if (S > 1) {
+            rc = get_workspace(bytes, stream, may_alloc, &ws);
+            if (rc != TFFT_OK) return rc;
+        }
+        const void* in = x;
+        for (int st = 0; st < S; ++st) {
+            void* out = ((S - 1 - st) % 2 == 0) ? y : ws;
+            const hipError_t err =
+                radix2_stage_launch(in, out, N, batch, 1ll << st, pt->hi, pt->lo, pt->bits,
+                                    dir == TFFT_INVERSE ? 1 : 0, st == S - 1 ? (float)scale : 1.0f, stream);
+            if (err != hipSuccess) return hip_fail(err);
+            in = out;
+        }
+        return TFFT_OK;
+    }
+    if (level == 1) {
+        static std::vector<KernelEntry>* r2 = nullptr;
+        if (!r2) {
+            r2 = new std::vector<KernelEntry>();
+            register_fp32_stepwise(*r2);
+        }
+        const KernelEntry* e = nullptr;
+        for (const KernelEntry& k : *r2)
+            if (k.Ns == N) e = &k;
+        if (!e) return TFFT_EUNSUPPORTED;
+        SubTables* st = nullptr;
+        int rc = get_sub(*e, may_alloc, &st);
+        if (rc != TFFT_OK) return rc;
+        Tuning tu = default_tuning(TFFT_FP32, N);
+        tu.T = 1;
+        tu.gran = 0;
+        KArgs<float2> a{};
+        fill_common(a, *e, *st, tu, nullptr);
+        a.batch = batch;
+        a.N = N;
+        a.conj_in = a.conj_out = dir == TFFT_INVERSE ? 1 : 0;
+        a.scale = (float)scale;
+        a.x_intact = 1;
+        return run<float2>(*e, x, y, a, (batch + e->slots_per_block - 1) / e->slots_per_block, stream);
+    }
+    // the library's plans without ABFT: level 2 the default route with the
+    // default tuning, level 3 the tuned route
+    const Tuning tu = level == 2 ? default_tuning(TFFT_FP32, N) : get_tuning(TFFT_FP32, N, TFFT_FT_OFF);
+    Route rt;
+    if (!route_for(TFFT_FP32, N, TFFT_FT_OFF, &rt, level == 2 ? 0 : tu.route)) return TFFT_EUNSUPPORTED;
+    return transform<float2>(rt, x, y, N, batch, dir, scale, nullptr, tu, Inject{}, stream, may_alloc);
 }
 
 int tfft_c2c_offline(const void* x, void* y, long long N, long long batch, int dir, int precision,

@@ -12,7 +12,7 @@ namespace tfft {
 using LaunchFn = hipError_t (*)(const void* x, void* y, const void* kargs, long long grid,
                                 hipStream_t stream);
 
-constexpr int kMaxStages = 12;   // radix stages a registered plan may have
+constexpr int kMaxStages = 14;   // radix stages a registered plan may have
 
 struct KernelEntry {
     int precision;          // 0 fp32, 1 fp64
@@ -104,5 +104,11 @@ void register_fp64_single(std::vector<KernelEntry>& out);
 void register_fp64_single_stream(std::vector<KernelEntry>& out);
 void register_fp64_tiles(std::vector<KernelEntry>& out);
 void register_fp32_three(std::vector<KernelEntry>& out);
+// the stepwise study's radix-2 plans (not in the route registry) and its
+// per-stage kernel
+void register_fp32_stepwise(std::vector<KernelEntry>& out);
+hipError_t radix2_stage_launch(const void* x, void* y, long long N, long long batch, long long L,
+                               const void* hi, const void* lo, int bits, int conj, float scale,
+                               hipStream_t s);
 
 }  // namespace tfft

@@ -108,6 +108,24 @@ def fft_c2c_offline(x: torch.Tensor, dir: int = -1, out: torch.Tensor | None = N
     return out, counts
 
 
+def fft_c2c_stepwise(x: torch.Tensor, level: int, dir: int = -1, out: torch.Tensor | None = None):
+    """tfft_c2c_stepwise: the plain complex64 transform at a level of the
+    stepwise study (0 per-stage radix-2 launches, 1 radix-2 stages in one
+    launch, 2 default plans, 3 tuned); out of place."""
+    if not x.is_cuda or x.dim() != 2 or not x.is_contiguous() or x.dtype != torch.complex64:
+        raise ValueError("x must be a contiguous [batch, N] complex64 device tensor")
+    batch, N = x.shape
+    if out is None:
+        out = torch.empty_like(x)
+    elif out.shape != x.shape or out.dtype != x.dtype or not out.is_contiguous() or out.device != x.device:
+        raise ValueError("out must match x in shape, dtype, device and be contiguous")
+    with torch.cuda.device(x.device):
+        st = _lib.load().tfft_c2c_stepwise(x.data_ptr(), out.data_ptr(), N, batch, dir, int(level),
+                                           _stream_ptr(x.device))
+    _lib.check(st, f"tfft_c2c_stepwise(N={N}, batch={batch}, level={level})")
+    return out
+
+
 def prepare(N: int, dtype=torch.complex64, ft_mode: int = 2, batch: int = 0, device=None) -> None:
     """Build the tables of length N and, for batch > 0, reserve the two-pass
     workspace for up to `batch` signals on torch's current stream (call

@@ -377,3 +377,16 @@ def test_three_pass_tuning_entries(tmp_path):
         lib.tfft_set_route(1 << 23, FP32, 0)
         if os.path.exists(_lib.TUNING_PATH):
             lib.tfft_load_tuning(_lib.TUNING_PATH.encode())
+
+
+def test_stepwise_validates_on_host():
+    lib = _lib.load()
+    f = lib.tfft_c2c_stepwise
+    dummy = 4096   # never dereferenced: validation fails first
+    assert f(dummy, dummy + (1 << 20), 256, 4, -1, 4, None) == _lib.TFFT_EINVAL      # level
+    assert f(dummy, dummy + (1 << 20), 256, 4, 0, 0, None) == _lib.TFFT_EINVAL       # dir
+    assert f(dummy, dummy + (1 << 20), 96, 4, -1, 0, None) == _lib.TFFT_EUNSUPPORTED # not 2^k
+    assert f(dummy, dummy + 8, 256, 4, -1, 0, None) == _lib.TFFT_EINVAL              # overlap
+    assert f(dummy, dummy, 256, 4, -1, 0, None) == _lib.TFFT_EINVAL                  # in place
+    assert f(dummy + 4, dummy + (1 << 20), 256, 4, -1, 0, None) == _lib.TFFT_EALIGN
+    assert f(dummy, dummy + (1 << 20), 256, 0, -1, 0, None) == _lib.TFFT_OK          # empty batch
