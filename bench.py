@@ -779,10 +779,10 @@ def roc_study(tf, torch, np, dev, N=1024, n_clean=2000, n_inj=1000, kappas=ROC_K
 
 def ablation_study(tf, torch, dev, reps=5):
     """ABFT granularity x transactions per group (Sec. 4.2-4.3; Table 2's
-    stepwise comparison, with this library's two fused forms): overhead of
-    the correcting kernels over the plain ones on a 1 GiB batch, per length,
-    for the check once per group (location code) at T = 1..32 and per
-    transaction at T = 1..16.  The route of each length stays the tuned one;
+    stepwise comparison): overhead of the correcting kernels over the plain
+    ones on a 1 GiB batch, per length, for the thread level (every radix-R
+    DFT checked in registers; single-pass lengths), the check once per group
+    (location code) at T = 1..32 and per transaction at T = 1..16.  The route of each length stays the tuned one;
     rows whose group size breaks the accuracy bound are marked (those
     settings are never chosen by the autotuner)."""
     from paper_2412_05824_amd import autotune
@@ -825,7 +825,16 @@ def ablation_study(tf, torch, dev, reps=5):
                     tf.set_tuning(N, dtype, T, 0)
                     offs.append(tm(tf.FT_OFF))
                 off = min(offs)
-                longest = N if info0["passes"] == 1 else max(info0["N1"], info0["N2"])
+                s_route = autotune.steps(N, 1 if info0["passes"] == 1 else info0["N1"])
+                if info0["passes"] == 1:
+                    # thread level: every radix-R DFT checked in registers
+                    counts.zero_()
+                    ms = tm(tf.FT_THREAD)
+                    rows.append({"precision": prec, "N": N, "granularity": "thread", "T": 1,
+                                 "ft_ms": round(ms, 4), "off_ms": round(off, 4),
+                                 "overhead_pct": round(100 * (ms / off - 1), 1),
+                                 "within_accuracy_bound": True,
+                                 "detected": tf.counts_dict(counts)["detected"]})
                 for gran, Ts in ((0, (1, 2, 4, 8, 16, 32)), (1, (1, 2, 4, 8, 16))):
                     tf.set_granularity(N, dtype, gran)
                     seen = set()
@@ -837,7 +846,7 @@ def ablation_study(tf, torch, dev, reps=5):
                         seen.add(teff)
                         counts.zero_()
                         ms = tm(tf.FT_CORRECT)
-                        within = gran == 1 or teff <= autotune.max_T(prec, longest, k0)
+                        within = gran == 1 or teff <= autotune.max_T(prec, s_route, k0)
                         rows.append({"precision": prec, "N": N, "granularity": "transaction" if gran else "group",
                                      "T": teff, "ft_ms": round(ms, 4), "off_ms": round(off, 4),
                                      "overhead_pct": round(100 * (ms / off - 1), 1),

@@ -50,7 +50,7 @@ typedef enum {
 
 enum { TFFT_FORWARD = -1, TFFT_INVERSE = +1 };       /* sign of the exponent */
 enum { TFFT_FP32 = 0, TFFT_FP64 = 1 };
-enum { TFFT_FT_OFF = 0, TFFT_FT_DETECT = 1, TFFT_FT_CORRECT = 2 };
+enum { TFFT_FT_OFF = 0, TFFT_FT_DETECT = 1, TFFT_FT_CORRECT = 2, TFFT_FT_THREAD = 3 };
 
 /* Device-resident counters, accumulated by every call that is given them
  * (the caller zeroes them).  detected: faulty signals found (a checksum
@@ -74,7 +74,17 @@ typedef struct {
  *   dir       TFFT_FORWARD or TFFT_INVERSE.
  *   precision TFFT_FP32 or TFFT_FP64.
  *   ft_mode   TFFT_FT_OFF, TFFT_FT_DETECT (one-side check with location) or
- *             TFFT_FT_CORRECT (two-side check, location and correction).
+ *             TFFT_FT_CORRECT (two-side check, location and correction), or
+ *             TFFT_FT_THREAD: thread-level two-side ABFT (Sec. 4.2), the
+ *             granularity study's finest form: every radix-R DFT a lane
+ *             computes in registers is checked, located and corrected on
+ *             its own (threshold kappa u sqrt(R (log2 R + 3)) |v|, kappa of the
+ *             length's tuning); the LDS exchanges and twiddle products
+ *             between them are not covered.  Single-pass lengths only (the
+ *             correcting mode's route; TFFT_EUNSUPPORTED otherwise).  An
+ *             armed injection (pass 0) flips output (element / P) mod R of
+ *             the first DFT of lane t = element mod P (P lanes per signal)
+ *             at stage `stage`, between the DFT and its check.
  *   scale     multiplies every output; 0 selects 1 (forward) or 1/N (inverse).
  *   counts    device tfft_ft_counts, required unless ft_mode is TFFT_FT_OFF.
  * N must be 2^k or 3*2^k within the sizes the library supports

@@ -3,7 +3,7 @@
 The transform runs in hand-written HIP kernels (libtfft.so, gfx950) behind the
 C ABI of include/tfft.h; this package is a thin binding over it.
 """
-from ._lib import (FORWARD, INVERSE, FP32, FP64, FT_OFF, FT_DETECT, FT_CORRECT,  # noqa: F401
+from ._lib import (FORWARD, INVERSE, FP32, FP64, FT_OFF, FT_DETECT, FT_CORRECT, FT_THREAD,  # noqa: F401
                    TfftError)
 from .fft import (fft_c2c, fft_c2c_noalloc, fft_c2c_offline, fft_c2c_stepwise, prepare, supported, inject_arm, inject_disarm, route_info,  # noqa: F401
                   set_tuning, set_granularity, get_tuning, new_counts, counts_dict, RaggedPlan, fft_c2c_ragged,

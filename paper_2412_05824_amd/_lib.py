@@ -30,6 +30,7 @@ FP64 = 1
 FT_OFF = 0
 FT_DETECT = 1
 FT_CORRECT = 2
+FT_THREAD = 3
 
 # exported symbols and their signatures, as declared in include/tfft.h
 _LL = ctypes.c_longlong

@@ -498,6 +498,43 @@ int get_pass(int precision, long long N, bool may_alloc, PassTwiddle** out) {
     return TFFT_OK;
 }
 
+// Thread-level ABFT table of a precision: for each radix R of 2, 4, 8, 16
+// (at offset 2 (R - 2)), a = e^T W_R then a1 = e1^T W_R, e_k = w_3^k and
+// e1_k = (k + 1) w_3^k, w = exp(-2 pi i / .), computed in long double.
+template <class R> int build_thread_table(void** out) {
+    std::vector<R> t;
+    for (int Rr : {2, 4, 8, 16}) {
+        for (int weighted = 0; weighted < 2; ++weighted)
+            for (int n = 0; n < Rr; ++n) {
+                long double re = 0, im = 0;
+                for (int k = 0; k < Rr; ++k) {
+                    long double c1, s1, c2, s2;
+                    cis_neg(k % 3, 3, &c1, &s1);              // w_3^k
+                    cis_neg((long long)k * n % Rr, Rr, &c2, &s2);   // w_R^{kn}
+                    const long double w = weighted ? (long double)(k + 1) : 1.0L;
+                    re += w * (c1 * c2 - s1 * s2);
+                    im += w * (c1 * s2 + s1 * c2);
+                }
+                put(t, re, im);
+            }
+    }
+    return upload(t, out);
+}
+
+std::map<std::tuple<int, int>, void*> g_thr;   // (precision, device) -> thread-level table
+
+int get_thread_table(int precision, bool may_alloc, void** out) {
+    auto key = std::make_tuple(precision, current_device());
+    auto it = g_thr.find(key);
+    if (it != g_thr.end()) { *out = it->second; return TFFT_OK; }
+    if (!may_alloc) return TFFT_ECAPTURE;
+    void* d = nullptr;
+    int rc = precision == TFFT_FP32 ? build_thread_table<float>(&d) : build_thread_table<double>(&d);
+    if (rc != TFFT_OK) return rc;
+    *out = g_thr[key] = d;
+    return TFFT_OK;
+}
+
 int get_workspace(size_t bytes, hipStream_t stream, bool may_alloc, void** out) {
     switch (g_ws.get(current_device(), stream, bytes, may_alloc, out)) {
         case WsResult::kOk: return TFFT_OK;
@@ -701,6 +738,13 @@ int transform(const Route& rt, const void* x, void* y, long long N, long long ba
         a.scale = (R)scale;
         a.sig_base = 0;
         a.x_intact = x != y ? 1 : 0;
+        if (rt.single->ft == 4) {
+            void* tt = nullptr;
+            rc = get_thread_table(precision, may_alloc, &tt);
+            if (rc != TFFT_OK) return rc;
+            a.thr_tab = static_cast<const V*>(tt);
+            a.thr_ku = (R)(tu.kappa * (precision == TFFT_FP32 ? 0x1p-24 : 0x1p-53));
+        }
         arm_launch(a, inj, 0, 1, rt.single->n_stages);
         const long long per_block = (long long)rt.single->slots_per_block * tu.T;
         return run<V>(*rt.single, x, y, a, (batch + per_block - 1) / per_block, stream,
@@ -1710,7 +1754,7 @@ int c2c_impl(const void* x, void* y, long long N, long long batch, int dir, int 
     if (N < 1 || batch < 0) return TFFT_EINVAL;
     if (dir != TFFT_FORWARD && dir != TFFT_INVERSE) return TFFT_EINVAL;
     if (check_precision(precision) != TFFT_OK) return TFFT_EINVAL;
-    if (ft_mode < TFFT_FT_OFF || ft_mode > TFFT_FT_CORRECT) return TFFT_EINVAL;
+    if (ft_mode < TFFT_FT_OFF || ft_mode > TFFT_FT_THREAD) return TFFT_EINVAL;
     if (!(is_pow2(N) || (N % 3 == 0 && is_pow2(N / 3)))) return TFFT_EUNSUPPORTED;
     if (batch == 0) return TFFT_OK;
     if (!x || !y) return TFFT_EINVAL;
@@ -1729,9 +1773,12 @@ int c2c_impl(const void* x, void* y, long long N, long long batch, int dir, int 
 
     std::lock_guard<std::mutex> lk(g_mu);
     ensure_registry();
-    const Tuning tu = get_tuning(precision, N, ft_mode);
+    // thread-level checking runs the kernels of ABFT mode 4 on the
+    // correcting mode's route (single-pass lengths only)
+    const bool thread_level = ft_mode == TFFT_FT_THREAD;
+    const Tuning tu = get_tuning(precision, N, thread_level ? TFFT_FT_CORRECT : ft_mode);
     Route rt;
-    if (!route_for(precision, N, ft_mode, &rt, tu.route)) return TFFT_EUNSUPPORTED;
+    if (!route_for(precision, N, thread_level ? 4 : ft_mode, &rt, tu.route)) return TFFT_EUNSUPPORTED;
     if (rt.single && ft_mode == TFFT_FT_CORRECT && x == y) {
         // in place: the kernel variant that keeps the right-side input sum
         rt.single = find_entry(precision, kSingle, N, 3, rt.single->variant);

@@ -96,6 +96,7 @@ template <class V> struct KArgs : KCall<typename RealOf<V>::type> {
     using R = typename RealOf<V>::type;
     const V* tw;          // stage twiddle tables of the sub-length, concatenated
     const V* left;        // e^T W of the sub-length (ABFT only)
+    const V* thr_tab;     // thread-level ABFT: e^T W_R and e1^T W_R per radix (see ThreadGuard)
     const V* tw_hi;       // row pass: w_N^m = tw_hi[m >> tw_bits] * tw_lo[m & mask]
     const V* tw_lo;
     int tw_bits;
@@ -112,6 +113,7 @@ template <class V> struct KArgs : KCall<typename RealOf<V>::type> {
     long long p3_M;
     int T;                // transactions (signals) per slot
     long long sig_base;   // global index of local signal 0 (counters only)
+    R thr_ku;             // thread-level ABFT: kappa * u
     R tau_coef;           // kappa * u * sqrt(Ns s), s = log2 Ns (+ 3 with an inter-pass
                           // twiddle); tau = tau_coef * sqrt(nu)
     R cap;                // magnitude cap: larger outputs mark their signal corrupted
@@ -217,9 +219,14 @@ template <int C> struct LdsCol {    // tile [m][c]: C sub-signals interleaved
 // One Stockham stage.  LAST: results stay in registers (output layout),
 // otherwise they go to LDS at their autosorted positions.
 // ---------------------------------------------------------------------------
-template <class V, int E, int P, int R, int L, bool LAST, class LI>
+// BF guards each radix-R DFT of the stage (thread-level ABFT; NoGuard: none).
+struct NoGuard {
+    template <int R, class V> __device__ __forceinline__ void before(const V (&)[R]) {}
+    template <int R, class V> __device__ __forceinline__ void after(V (&)[R], int, int) {}
+};
+template <class V, int E, int P, int R, int L, bool LAST, int S, class LI, class BF>
 __device__ __forceinline__ void stockham_stage(V (&reg)[E], const V* __restrict__ tw_s, int t,
-                                               V* __restrict__ lds, const LI& li) {
+                                               V* __restrict__ lds, const LI& li, BF& bf) {
     constexpr int NB = E / R;
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
@@ -235,7 +242,9 @@ __device__ __forceinline__ void stockham_stage(V (&reg)[E], const V* __restrict_
 #pragma unroll
             for (int j = 1; j < R; ++j) v[j] = cmul(v[j], w[j]);
         }
+        bf.template before<R>(v);
         dft<R>(v);
+        bf.template after<R>(v, S, i);
         if constexpr (LAST) {
 #pragma unroll
             for (int j = 0; j < R; ++j) reg[i + j * NB] = v[j];
@@ -261,11 +270,11 @@ __device__ __forceinline__ void stockham_stage(V (&reg)[E], const V* __restrict_
 struct NoHook {
     template <class A> __device__ __forceinline__ void operator()(int, A&) const {}
 };
-template <class V, int E, int P, bool BLOCK, class LI, class H, int S, int L, int R, int... Rest>
+template <class V, int E, int P, bool BLOCK, class LI, class H, class BF, int S, int L, int R, int... Rest>
 __device__ __forceinline__ void slot_fft(V (&reg)[E], const V* __restrict__ tw, int t,
-                                         V* __restrict__ lds, const LI& li, H& hook) {
+                                         V* __restrict__ lds, const LI& li, H& hook, BF& bf) {
     constexpr bool LAST = sizeof...(Rest) == 0;
-    stockham_stage<V, E, P, R, L, LAST>(reg, tw, t, lds, li);
+    stockham_stage<V, E, P, R, L, LAST, S>(reg, tw, t, lds, li, bf);
     if constexpr (!LAST) {
         lds_sync<BLOCK>();
         if constexpr (LI::template SPLIT<P, 1>) {
@@ -278,7 +287,7 @@ __device__ __forceinline__ void slot_fft(V (&reg)[E], const V* __restrict__ tw, 
         }
         lds_sync<BLOCK>();
         hook(S, reg);
-        slot_fft<V, E, P, BLOCK, LI, H, S + 1, L * R, Rest...>(reg, tw + L * R, t, lds, li, hook);
+        slot_fft<V, E, P, BLOCK, LI, H, BF, S + 1, L * R, Rest...>(reg, tw + L * R, t, lds, li, hook, bf);
     } else {
         hook(S, reg);
     }
@@ -307,6 +316,118 @@ template <class V, int M> __device__ __forceinline__ V wM(int j) {
         }
     }
 }
+
+// Thread-level two-side ABFT (Sec. 4.2, thread level): every radix-R DFT a
+// lane computes in registers is checked on its own.  Before it, p = a^T v
+// and p1 = a1^T v with a = e^T W_R and a1 = e1^T W_R (e_k = w_3^k,
+// e1_k = (k + 1) w_3^k; host table, radix R at offset 2 (R - 2), a then a1)
+// and nu = |v|^2; after it, q = e^T v and q1 = e1^T v.  |q - p| above
+// kappa u sqrt(R (log2 R + 3)) sqrt(nu) flags the DFT; its faulty output
+// k* = round(Re((q1 - p1) / (q - p))) - 1 is repaired by subtracting
+// (q - p) / e_{k*}; a difference beyond 32 |v| (or not finite) marks the
+// largest output, which is rebuilt from the left checksum
+// (e_{k*} y_{k*} = p - the others).  The test hook flips output j of the first DFT of one
+// lane at one stage, between the DFT and its check.
+template <class V> struct ThreadGuard {
+    using R = typename RealOf<V>::type;
+    const V* tab;
+    R kappa_u;
+    FtCounts* counts;
+    int inj_stage, inj_j, inj_part, inj_bit;   // inj_stage < 0: no flip in this lane
+    long long sig;
+    V p, p1;
+    R nu;
+    template <int RR> __device__ __forceinline__ void before(const V (&v)[RR]) {
+        const V* a = tab + 2 * (RR - 2);
+        p = V{0, 0};
+        p1 = V{0, 0};
+        nu = 0;
+#pragma unroll
+        for (int j = 0; j < RR; ++j) {
+            p = cmac(p, a[j], v[j]);
+            p1 = cmac(p1, a[RR + j], v[j]);
+            nu = fmad(v[j].x, v[j].x, fmad(v[j].y, v[j].y, nu));
+        }
+    }
+    template <int RR> __device__ __forceinline__ void after(V (&v)[RR], int stage, int i) {
+        if (inj_stage == stage && i == 0) {
+#pragma unroll
+            for (int j = 0; j < RR; ++j)
+                if (j == inj_j % RR) {
+                    if (inj_part == 0) v[j].x = flip_bit(v[j].x, inj_bit);
+                    else v[j].y = flip_bit(v[j].y, inj_bit);
+                }
+        }
+        V q = V{0, 0}, q1 = V{0, 0};
+#pragma unroll
+        for (int k = 0; k < RR; ++k) {
+            const V ek = wM<V, 3>(k);
+            const V t = cmul(ek, v[k]);
+            q = cadd(q, t);
+            q1 = V{fmad((R)(k + 1), t.x, q1.x), fmad((R)(k + 1), t.y, q1.y)};
+        }
+        // rounding steps: log2 R for the DFT, three for the checksum products
+        constexpr int LG = RR == 2 ? 1 : RR == 4 ? 2 : RR == 8 ? 3 : 4;
+        const R tau = kappa_u * (R)__builtin_sqrt((R)(RR * (LG + 3))) * __builtin_sqrt(nu);
+        const V d = csub(q, p);
+        // |d| scaled by its larger component, so that a large finite
+        // difference does not overflow to infinity
+        const R ax = __builtin_fabs(d.x), ay = __builtin_fabs(d.y);
+        const bool fin = ax < (R)INFINITY && ay < (R)INFINITY;
+        const R m = ax > ay ? ax : ay;
+        R d0 = (R)INFINITY;
+        if (fin) d0 = m > (R)0 ? m * __builtin_sqrt((d.x / m) * (d.x / m) + (d.y / m) * (d.y / m)) : (R)0;
+        if (!(d0 <= tau)) {
+            // locate: Re(d1 / d) = Re(d1 conj(d / |d|)) / |d|; a non-finite
+            // difference: the non-finite output, else the largest one
+            const V d1 = csub(q1, p1);
+            int ks = -1;
+            // An error up to a few times the DFT's inputs is subtracted (its
+            // rounding stays at the data's scale); a larger or non-finite one
+            // would leave its own rounding behind: the largest output, which
+            // carries it, is rebuilt instead.
+            if (fin && d0 <= (R)32 * __builtin_sqrt(nu)) {
+                const R re = (d1.x * (d.x / d0) + d1.y * (d.y / d0)) / d0;
+                if (re == re && re > (R)0.5 && re < (R)RR + (R)0.5) ks = (int)__builtin_floor(re + (R)0.5) - 1;
+            }
+            const bool add = ks >= 0;
+            if (!add) {
+                // a NaN counts as the largest (and stays chosen)
+                R big = (R)-1;
+#pragma unroll
+                for (int k = 0; k < RR; ++k) {
+                    R mk = __builtin_fabs(v[k].x) + __builtin_fabs(v[k].y);
+                    if (!(mk < (R)INFINITY)) mk = (R)INFINITY;
+                    if (mk > big) {
+                        big = mk;
+                        ks = k;
+                    }
+                }
+            }
+            bool ok = false;
+#pragma unroll
+            for (int k = 0; k < RR; ++k)
+                if (k == ks) {
+                    const V ek = wM<V, 3>(k);
+                    if (add) {
+                        // v_k -= d / e_k = d conj(e_k)  (|e_k| = 1)
+                        v[k] = csub(v[k], cmul(d, V{ek.x, -ek.y}));
+                    } else {
+                        // rebuild from the left checksum: e_k v_k = p - sum of the others
+                        V o = p;
+#pragma unroll
+                        for (int m = 0; m < RR; ++m)
+                            if (m != k) o = csub(o, cmul(wM<V, 3>(m), v[m]));
+                        v[k] = cmul(o, V{ek.x, -ek.y});
+                    }
+                    ok = true;
+                }
+            atomicAdd(&counts->detected, 1ull);
+            atomicAdd(!ok ? &counts->uncorrectable : (add ? &counts->corrected : &counts->rebuilt), 1ull);
+            atomicExch(&counts->last_signal, (unsigned long long)sig);
+        }
+    }
+};
 
 // sum_r w_M^{(P r) mod M} v[r]: e^T v for a lane whose positions are t + P r,
 // up to the lane factor w_M^{t mod M} applied by the caller.
@@ -819,7 +940,7 @@ template <class V> __device__ __forceinline__ void buf_store(const V& v, __amdgp
 }
 
 // One workgroup's share of a transform: block `block` of `nblocks`.
-template <class V, class PL, int FT, bool IND, int COH, int... Rs>
+template <class V, class PL, int FT, bool IND, int COH, bool TL, int... Rs>
 __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict__ y, const KArgs<V>& a,
                                          const KCall<typename RealOf<V>::type>& kc, long long block,
                                          long long nblocks, char* smem) {
@@ -981,7 +1102,24 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
                 }
             }
         };
-        slot_fft<V, E, P, BLOCK, decltype(li), decltype(inject), 0, 1, Rs...>(reg, a.tw, t, lds, li, inject);
+        if constexpr (TL) {
+            ThreadGuard<V> tg;
+            tg.tab = a.thr_tab;
+            tg.kappa_u = a.thr_ku;
+            tg.counts = kc.counts;
+            tg.sig = g.gid(a, s);
+            tg.inj_stage = (kc.inj_signal >= 0 && valid && (tg.sig == kc.inj_signal || tg.sig == kc.inj_signal2) &&
+                            (long long)t == kc.inj_elem % P) ? kc.inj_stage : -1;
+            tg.inj_j = (int)((kc.inj_elem / P) & 15);
+            tg.inj_part = kc.inj_part;
+            tg.inj_bit = kc.inj_bit;
+            NoHook nh;
+            slot_fft<V, E, P, BLOCK, decltype(li), NoHook, ThreadGuard<V>, 0, 1, Rs...>(reg, a.tw, t, lds, li, nh, tg);
+        } else {
+            NoGuard ng;
+            slot_fft<V, E, P, BLOCK, decltype(li), decltype(inject), NoGuard, 0, 1, Rs...>(reg, a.tw, t, lds, li,
+                                                                                        inject, ng);
+        }
 
         if constexpr (FT != 0) {
             const V q = encode_out<V, E, P, M>(reg);
@@ -1080,7 +1218,8 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
                 reg[r] = acc;
             }
             NoHook nohook;
-            slot_fft<V, E, P, BLOCK, decltype(li), NoHook, 0, 1, Rs...>(reg, a.tw, t, lds, li, nohook);   // W x_s
+            NoGuard ng;
+            slot_fft<V, E, P, BLOCK, decltype(li), NoHook, NoGuard, 0, 1, Rs...>(reg, a.tw, t, lds, li, nohook, ng);   // W x_s
             // c = W x_s - Y e, element by element, Y e summed from the stored
             // outputs (internal domain); skip: leave out b*
             auto corr_elem = [&](int r, int skip) -> V {
@@ -1374,22 +1513,28 @@ template <class V, class PL, int FT, bool IND> struct Occupancy {
     static constexpr int WAVES = FT == 0 || !(PL::TILE || PL::STREAM) ? 1 : (LDS_WAVES < 1 ? 1 : (LDS_WAVES > CAP ? CAP : LDS_WAVES));
 };
 
+// FT = 4: thread-level ABFT only (the workgroup-level checks of FT 0).
+template <int FT> constexpr int kGroupFt = FT == 4 ? 0 : FT;
+
 template <class V, class PL, int FT, bool IND, int... Rs>
-__global__ __launch_bounds__(PL::THREADS) __attribute__((amdgpu_waves_per_eu(Occupancy<V, PL, FT, IND>::WAVES)))
+__global__ __launch_bounds__(PL::THREADS)
+__attribute__((amdgpu_waves_per_eu(Occupancy<V, PL, kGroupFt<FT>, IND>::WAVES)))
 void k_fft(const V* __restrict__ x, V* __restrict__ y, KArgs<V> a) {
-    static_assert(Smem<V, PL, FT, IND>::BYTES <= 160 * 1024, "LDS of a workgroup exceeds a CU's");
-    static_assert(!kResident<V, PL, FT, IND> || Smem<V, PL, FT, IND>::AW_LDS, "resident kernels stage e^T W");
-    __shared__ __align__(16) char smem[Smem<V, PL, FT, IND>::BYTES];
-    if constexpr (kResident<V, PL, FT, IND>) {
+    constexpr int GF = kGroupFt<FT>;
+    constexpr bool TL = FT == 4;
+    static_assert(Smem<V, PL, GF, IND>::BYTES <= 160 * 1024, "LDS of a workgroup exceeds a CU's");
+    static_assert(!kResident<V, PL, GF, IND> || Smem<V, PL, GF, IND>::AW_LDS, "resident kernels stage e^T W");
+    __shared__ __align__(16) char smem[Smem<V, PL, GF, IND>::BYTES];
+    if constexpr (kResident<V, PL, GF, IND>) {
         // e^T W into LDS once; every exchange and reduction of the first
         // group passes a workgroup barrier before it is read
-        V* awl = reinterpret_cast<V*>(smem + Smem<V, PL, FT, IND>::AW_OFF);
+        V* awl = reinterpret_cast<V*>(smem + Smem<V, PL, GF, IND>::AW_OFF);
         for (int i = threadIdx.x; i < PL::Ns; i += PL::THREADS) awl[i] = a.left[i];
         __syncthreads();
         for (long long g = blockIdx.x; g < a.nblk; g += gridDim.x)
-            fft_body<V, PL, FT, IND, 0, Rs...>(x, y, a, a, g, a.nblk, smem);
+            fft_body<V, PL, GF, IND, 0, TL, Rs...>(x, y, a, a, g, a.nblk, smem);
     } else {
-        fft_body<V, PL, FT, IND, 0, Rs...>(x, y, a, a, blockIdx.x, gridDim.x, smem);
+        fft_body<V, PL, GF, IND, 0, TL, Rs...>(x, y, a, a, blockIdx.x, gridDim.x, smem);
     }
 }
 

@@ -148,7 +148,7 @@ __device__ __forceinline__ void ragged_step(const RaggedCall& c, const RaggedDes
     const int nblocks = cl->nblocks;
     for (int b = blk; b < blk + nblk; ++b) {
         if (b != blk) __syncthreads();   // the previous block is done with the LDS buffer
-        fft_body<float2, PL, FT, true, COH, Rs...>(src, dst, ka, kc, b, nblocks,
+        fft_body<float2, PL, FT, true, COH, false, Rs...>(src, dst, ka, kc, b, nblocks,
                                                    tfft_ragged_smem + kRaggedSlotBytes);
     }
     if constexpr (PL::KIND == kColPass) {

@@ -18,7 +18,7 @@ struct KernelEntry {
     int precision;          // 0 fp32, 1 fp64
     int kind;               // kSingle, kColPass, kRowPass, kColPass3, kRowPass3
     int Ns;                 // (sub-)transform length
-    int ft;                 // 0 off, 1 detect, 2 correct, 3 correct in place
+    int ft;                 // 0 off, 1 detect, 2 correct, 3 correct in place, 4 thread-level
     int E, P, threads;      // elements per lane, lanes per slot, lanes per workgroup
     int slots_per_block;    // sub-signals per workgroup per transaction
     int n_stages;
@@ -36,7 +36,7 @@ hipError_t launch_fft(const void* x, void* y, const void* ka, long long grid, hi
     KArgs<V> a = *static_cast<const KArgs<V>*>(ka);
     a.nblk = grid;
     long long g = grid;
-    if constexpr (kResident<V, PL, FT, IND>) {
+    if constexpr (kResident<V, PL, kGroupFt<FT>, IND>) {
         static const int per_cu = [] {
             int n = 0;
             if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fft<V, PL, FT, IND, Rs...>, PL::THREADS, 0) !=
@@ -82,11 +82,15 @@ template <class V, class PL, int FT, bool IND, int... Rs> KernelEntry make_entry
 template <class V, int KIND, int Ns, int E, int WC, int B, int... Rs>
 void add_plan(std::vector<KernelEntry>& out, int precision, int variant = 0) {
     using PL = Plan<KIND, Ns, E, WC, B, Rs...>;
-    KernelEntry e[4] = {make_entry<V, PL, 0, false, Rs...>(precision),
+    KernelEntry e[5] = {make_entry<V, PL, 0, false, Rs...>(precision),
                         make_entry<V, PL, 1, false, Rs...>(precision),
-                        make_entry<V, PL, 2, false, Rs...>(precision), {}};
+                        make_entry<V, PL, 2, false, Rs...>(precision), {}, {}};
     int n = 3;
-    if constexpr (KIND == kSingle) e[n++] = make_entry<V, PL, 3, false, Rs...>(precision);
+    // single pass: the in-place correcting form, and thread-level ABFT
+    if constexpr (KIND == kSingle) {
+        e[n++] = make_entry<V, PL, 3, false, Rs...>(precision);
+        e[n++] = make_entry<V, PL, 4, false, Rs...>(precision);
+    }
     for (int i = 0; i < n; ++i) {
         e[i].variant = variant;
         out.push_back(e[i]);
