@@ -25,6 +25,8 @@ Readings taken where the paper is silent:
     (abft_group), or per transaction with its own threshold and delayed
     correction from the right-side sums so far (abft_group_per_transaction).
 
+Also the thread-level check of one radix-R DFT (thread_dft_check).
+
 Parity unpinned: the threshold constant kappa (no worked value in the paper);
 the tests pin every decision for faults well away from the threshold.
 """
@@ -257,3 +259,60 @@ def grad_sum_w_abs2(x, w) -> np.ndarray:
     (dL/dRe + i dL/dIm): 2 * conj(W)^T (w * y) = 2 * (unscaled inverse DFT)(w * y)."""
     y = _oracle_fft(x, dir=-1, scale=1.0)
     return _oracle_fft(2.0 * np.asarray(w) * y, dir=+1, scale=1.0)
+
+
+# ---------------------------------------------------------------------------
+# Thread-level two-side ABFT (Sec. 4.2, thread level): one radix-R DFT held
+# by one lane is checked, located and corrected on its own.
+# ---------------------------------------------------------------------------
+
+def thread_left_vectors(R: int) -> tuple[np.ndarray, np.ndarray]:
+    """(a, a1) with a = e^T W_R and a1 = e1^T W_R, e_k = w_3^k and
+    e1_k = (k + 1) w_3^k (the location weights), W_R the forward R-point DFT
+    matrix; computed as the transforms of e and e1 (W_R is symmetric)."""
+    e = encoding_vector(R, 3)
+    e1 = e * (np.arange(R) + 1)
+    return _oracle_fft(e, dir=-1, scale=1.0), _oracle_fft(e1, dir=-1, scale=1.0)
+
+
+def thread_dft_check(v, R: int, precision: str = "fp32", kappa: float = 8.0, fault=None):
+    """Run one radix-R DFT of v under the thread-level check.
+
+    Steps in the order of the scheme: encode the inputs (p = a^T v,
+    p1 = a1^T v, nu = |v|^2); transform (y = W_R v); optionally add a fault
+    (k, delta) to output k; encode the outputs (q = e^T y, q1 = e1^T y);
+    detect with |q - p| > tau, tau = kappa u sqrt(R (log2 R + 3)) sqrt(nu);
+    locate k* = round(Re((q1 - p1) / (q - p))) - 1; correct y_{k*} -= (q - p)
+    / e_{k*} when |q - p| <= 32 sqrt(nu), else rebuild the largest output
+    from the left checksum, e_{k*} y_{k*} = p - sum_{k != k*} e_k y_k.
+    Returns (y, detected, k_star, mode) with mode None, "add" or "rebuild"."""
+    v = np.asarray(v, dtype=np.complex128)
+    a, a1 = thread_left_vectors(R)
+    e = encoding_vector(R, 3)
+    e1 = e * (np.arange(R) + 1)
+    p, p1 = a @ v, a1 @ v
+    nu = float(np.vdot(v, v).real)
+    y = _oracle_fft(v, dir=-1, scale=1.0)
+    if fault is not None:
+        k, delta = fault
+        y = y.copy()
+        y[k] += delta
+    with np.errstate(invalid="ignore", over="ignore"):   # a non-finite fault
+        q, q1 = e @ y, e1 @ y
+    d = q - p
+    tau = kappa * UNIT_ROUNDOFF[precision] * math.sqrt(R * (math.log2(R) + 3)) * math.sqrt(nu)
+    if not (abs(d) <= tau):
+        if np.isfinite(d) and abs(d) <= 32 * math.sqrt(nu):
+            ks = int(round(((q1 - p1) / d).real)) - 1
+            if 0 <= ks < R:
+                y = y.copy()
+                y[ks] -= d / e[ks]
+                return y, True, ks, "add"
+        with np.errstate(invalid="ignore"):
+            mags = np.where(np.isfinite(np.abs(y)), np.abs(y.real) + np.abs(y.imag), np.inf)
+        ks = int(np.argmax(mags))
+        y = y.copy()
+        others = sum(e[m] * y[m] for m in range(R) if m != ks)
+        y[ks] = (p - others) / e[ks]
+        return y, True, ks, "rebuild"
+    return y, False, None, None

@@ -397,3 +397,54 @@ def test_per_transaction_fp32_bit_flips_keep_each_signal_within_tolerance():
             else:
                 assert r["faulty"] == [b] and r["events"][0][1] in ("corrected", "rebuilt")
     assert worst_clean < tol
+
+
+# ---- thread-level check (Sec. 4.2, thread level) ----
+
+@pytest.mark.parametrize("R", [2, 4, 8, 16])
+def test_thread_left_vectors_closed_forms(R):
+    """a_n is the geometric series (1 - w3^R) / (1 - w3 w_R^n); a1_n is the
+    weighted series sum_k (k+1) z^k = (1 - (R+1) z^R + R z^(R+1)) / (1 - z)^2
+    with z = w3 w_R^n."""
+    a, a1 = am.thread_left_vectors(R)
+    w3 = np.exp(-2j * np.pi / 3)
+    n = np.arange(R)
+    z = w3 * np.exp(-2j * np.pi * n / R)
+    np.testing.assert_allclose(a, (1 - w3 ** R) / (1 - z), rtol=0, atol=1e-12)
+    np.testing.assert_allclose(a1, (1 - (R + 1) * z ** R + R * z ** (R + 1)) / (1 - z) ** 2, rtol=0, atol=1e-11)
+
+
+@pytest.mark.parametrize("R", [2, 4, 8, 16])
+def test_thread_check_locates_and_corrects_every_output(R):
+    rng = np.random.default_rng(R)
+    v = rng.standard_normal(R) + 1j * rng.standard_normal(R)
+    y0 = np.fft.fft(v)
+    y, det, ks, mode = am.thread_dft_check(v, R)
+    assert not det and ks is None
+    for k in range(R):
+        for delta in (0.3 * abs(y0[k]) + 0.1, -2.0j, 1e-3 * np.linalg.norm(v)):
+            y, det, ks, mode = am.thread_dft_check(v, R, fault=(k, delta))
+            assert det and ks == k and mode == "add", (k, delta)
+            np.testing.assert_allclose(y, y0, rtol=0, atol=1e-12 * np.linalg.norm(v))
+        # an exponent-sized error and a non-finite one are rebuilt
+        for delta in (1e30, complex(np.inf, 0)):
+            y, det, ks, mode = am.thread_dft_check(v, R, fault=(k, delta))
+            assert det and ks == k and mode == "rebuild", (k, delta)
+            np.testing.assert_allclose(y, y0, rtol=0, atol=1e-12 * np.linalg.norm(v))
+
+
+def test_thread_check_no_false_alarm_in_fp32_rounding():
+    """fp32 rounding of the transform and of the checksum products stays
+    below the threshold (kappa = 8) over many random DFTs of every radix."""
+    rng = np.random.default_rng(77)
+    for R in (2, 4, 8, 16):
+        a, a1 = am.thread_left_vectors(R)
+        e = am.encoding_vector(R, 3)
+        for _ in range(2000):
+            v = (rng.uniform(-1, 1, R) + 1j * rng.uniform(-1, 1, R)).astype(np.complex64)
+            p = np.complex64(np.sum(a.astype(np.complex64) * v))
+            y = np.fft.fft(v.astype(np.complex128)).astype(np.complex64)
+            q = np.complex64(np.sum(e.astype(np.complex64) * y))
+            nu = float(np.vdot(v, v).real)
+            tau = 8 * 2.0 ** -24 * np.sqrt(R * (np.log2(R) + 3)) * np.sqrt(nu)
+            assert abs(complex(q) - complex(p)) <= tau, R
