@@ -366,7 +366,9 @@ int tfft_get_route(long long N, int precision, int ft_mode, long long* code);
  *                 "split_n2": n2 (three passes; absent or 0: two),
  *                 "T": t, "kappa": k, "chunk_bytes": b, ...}, ...]}
  * Each entry sets the fields it names for (N, precision) in ABFT mode f, or
- * in every mode when ft_mode is absent; other keys are ignored.  All
+ * in every mode when ft_mode is absent; other keys are ignored.  An optional
+ * top-level "ragged": {"item_elems": n, "waves": 0 | 3} sets the schedule
+ * of ragged plans created afterwards (as tfft_ragged_set_schedule).  All
  * entries are checked before any is applied.  Returns the number of entries
  * applied, or TFFT_EINVAL (unreadable file, malformed JSON or value out of
  * range) / TFFT_EUNSUPPORTED (a route not built). */

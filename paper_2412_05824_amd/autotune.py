@@ -14,6 +14,9 @@ Per (precision, N) it sweeps, with ABFT correction on:
     the workspace;
 then, without ABFT, T and the chunk again on the same route (a shared plan
 keeps outputs bit-identical whether ABFT is on or off).
+With --ragged-only it tunes the ragged batch's schedule instead (elements
+per work item, register budget of the persistent ABFT kernel) on a seeded
+batch drawn from the ragged menu, and stores it under "ragged".
 Each candidate runs on a 1 GiB seeded batch; it must count no detection on
 fault-free data and agree with the default configuration's output to
 within twice the precision's tolerance (two correct transforms differ by at
@@ -177,13 +180,78 @@ def tune(precisions, logs, modes=(2, 0), reps=5, warmup=2, total_bytes=1 << 30, 
     return entries
 
 
+RAGGED_ITEMS = (8192, 16384, 32768, 65536)
+RAGGED_WAVES = (3, 0)
+
+
+def tune_ragged(signals=10000, seed=5, reps=5, log=print):
+    """The ragged batch's schedule: elements per work item and the ABFT
+    kernels' register budget, on a seeded batch of `signals` lengths drawn
+    uniformly from the ragged menu (2^k and 3 * 2^k, 6 <= k <= 16), forward,
+    ABFT correct, one persistent launch; the fastest setting that counts no
+    detection and matches the per-size launches bit for bit."""
+    import numpy as np
+    import torch
+
+    import paper_2412_05824_amd as tf
+
+    dev = torch.device("cuda:0")
+    menu = [n for k in range(6, 17) for n in (1 << k, 3 << k) if tf.ragged_supported(n)]
+    rng = np.random.default_rng(seed)
+    sizes = [int(n) for n in rng.choice(menu, size=signals)]
+    total = int(sum(sizes))
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    x = (torch.rand(total, 2, device=dev, generator=g) * 2 - 1).view(torch.complex64).view(-1)
+    y = torch.empty_like(x)
+    ref = torch.empty_like(x)
+    counts = tf.new_counts(dev)
+    best = None
+    first = True
+    for waves in RAGGED_WAVES:
+        for item in RAGGED_ITEMS:
+            tf.ragged_set_schedule(0, item, waves)
+            plan = tf.RaggedPlan(sizes, device=dev)
+            try:
+                if first:
+                    plan(x, out=ref, ft_mode=tf.FT_CORRECT, counts=counts, mode="per_size")
+                    first = False
+                run = lambda: plan(x, out=y, ft_mode=tf.FT_CORRECT, counts=counts, mode="persistent")
+                counts.zero_()
+                ms = _time(run, torch, reps, 2)
+                ok = tf.counts_dict(counts)["detected"] == 0 and bool(torch.equal(y, ref))
+            finally:
+                plan.close()
+            log(f"ragged item={item} waves={waves}: {ms:.4f} ms{'' if ok else ' REJECTED'}")
+            if ok and (best is None or ms < best["ms"]):
+                best = {"item_elems": item, "waves": waves, "ms": round(ms, 5),
+                        "workload": f"{signals} signals, ragged menu, seed {seed}, {total} elements"}
+    tf.ragged_set_schedule(0, 32768, 3)
+    del x, y, ref
+    torch.cuda.empty_cache()
+    return best
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", required=True)
     ap.add_argument("--precision", default="fp32,fp64")
     ap.add_argument("--sizes", default="6-22", help="log2 N range lo-hi or comma list")
     ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--ragged-only", action="store_true",
+                    help="tune only the ragged schedule and store it in the existing table --out")
     args = ap.parse_args(argv)
+    if args.ragged_only:
+        with open(args.out) as f:
+            doc = json.load(f)
+        best = tune_ragged(reps=args.reps, log=lambda s: print(s, flush=True))
+        if best:
+            doc["ragged"] = best
+        with open(args.out, "w") as f:
+            json.dump(doc, f, indent=1)
+        import paper_2412_05824_amd as tf
+        print(f"wrote {args.out}: ragged {best}, {tf.load_tuning(args.out)} entries", flush=True)
+        return 0
     if "-" in args.sizes:
         lo, hi = (int(v) for v in args.sizes.split("-"))
         logs = list(range(lo, hi + 1))

@@ -1600,7 +1600,19 @@ int tfft_load_tuning(const char* path) {
             if (!found) pending.emplace_back(std::make_tuple(prec, N, ft), tu);
         }
     }
+    // the ragged schedule of plans created afterwards: elements per work item
+    // and the ABFT kernels' register budget (waves 0 or 3)
+    long long r_item = 0, r_waves = -1;
+    if (const JVal* rg = root.get("ragged")) {
+        if (rg->kind != JVal::kObj) return TFFT_EINVAL;
+        if (rg->get("item_elems") && (!json_int(rg->get("item_elems"), &r_item) || r_item < 1 || r_item > (1ll << 30)))
+            return TFFT_EINVAL;
+        if (rg->get("waves") && (!json_int(rg->get("waves"), &r_waves) || (r_waves != 0 && r_waves != 3)))
+            return TFFT_EINVAL;
+    }
     for (auto& q : pending) g_tuning[q.first] = q.second;
+    if (r_item > 0) g_ragged_item = r_item;
+    if (r_waves >= 0) g_ragged_waves = (int)r_waves;
     return (int)entries->arr.size();
 }
 

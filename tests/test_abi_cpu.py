@@ -390,3 +390,19 @@ def test_stepwise_validates_on_host():
     assert f(dummy, dummy, 256, 4, -1, 0, None) == _lib.TFFT_EINVAL                  # in place
     assert f(dummy + 4, dummy + (1 << 20), 256, 4, -1, 0, None) == _lib.TFFT_EALIGN
     assert f(dummy, dummy + (1 << 20), 256, 0, -1, 0, None) == _lib.TFFT_OK          # empty batch
+
+
+def test_tuning_table_ragged_schedule_validated(tmp_path):
+    lib = _lib.load()
+    for bad in ({"item_elems": 0}, {"waves": 2}, {"item_elems": "x"}, []):
+        p = tmp_path / "r.json"
+        p.write_text(json.dumps({"entries": [], "ragged": bad}))
+        assert lib.tfft_load_tuning(str(p).encode()) == _lib.TFFT_EINVAL, bad
+    p = tmp_path / "r.json"
+    p.write_text(json.dumps({"entries": [], "ragged": {"item_elems": 16384, "waves": 3}}))
+    try:
+        assert lib.tfft_load_tuning(str(p).encode()) == 0
+    finally:
+        lib.tfft_ragged_set_schedule(0, 32768, 3)
+        if os.path.exists(_lib.TUNING_PATH):
+            lib.tfft_load_tuning(_lib.TUNING_PATH.encode())
