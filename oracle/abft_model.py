@@ -23,7 +23,9 @@ Readings taken where the paper is silent:
     as W(Xe) - sum of the other outputs;
   * two detection granularities: once per group with location encoding
     (abft_group), or per transaction with its own threshold and delayed
-    correction from the right-side sums so far (abft_group_per_transaction).
+    correction from the right-side sums so far (abft_group_per_transaction);
+  * location fallback (abft_group, fallback=True): when D1/D0 is not an
+    index, each signal is re-encoded on its own and the largest |d_b| taken.
 
 Also the thread-level check of one radix-R DFT (thread_dft_check).
 
@@ -110,13 +112,18 @@ def group_checksums(X: np.ndarray, Y: np.ndarray, M: int, dir: int = -1):
 
 
 def abft_group(X, Yp, precision: str = "fp32", kappa: float = 32.0, dir: int = -1,
-               M: int | None = None, rho: float = 0.25):
+               M: int | None = None, rho: float = 0.25, fallback: bool = False):
     """Detect, locate and correct one group (Sec. 4.1-4.3).
 
     X  : [G, N] inputs of the group's signals.
     Yp : [G, N] unscaled transforms as produced, possibly with one fault.
+    fallback: when D1/D0 is not an index (an error just above the threshold,
+    where the rounding of the weighted sum dominates), re-encode every
+    signal of the group on its own, d_b = e^T y_b - a^T x_b, and take the one
+    with the largest |d_b| (the inputs being intact) instead of giving up.
     Returns a dict: action in {"clean", "corrected", "rebuilt", "uncorrectable",
-    "unchecked"}, located index b (or None), corrected outputs Y, D0, D1, tau.
+    "unchecked"}, located index b (or None), corrected outputs Y, D0, D1, tau,
+    and "fallback" (the location came from the re-encoding).
     """
     X = np.asarray(X, dtype=np.complex128)
     Y = np.array(Yp, dtype=np.complex128, copy=True)
@@ -125,7 +132,7 @@ def abft_group(X, Yp, precision: str = "fp32", kappa: float = 32.0, dir: int = -
         M = choose_M(N)
     cs = group_checksums(X, Y, M, dir)
     nu = cs["nu"]
-    res = {"action": "clean", "b": None, "Y": Y, "tau": None, "D0": None, "D1": None}
+    res = {"action": "clean", "b": None, "Y": Y, "tau": None, "D0": None, "D1": None, "fallback": False}
     if not math.isfinite(nu):
         res["action"] = "unchecked"      # non-finite input: nothing to protect
         return res
@@ -146,8 +153,14 @@ def abft_group(X, Yp, precision: str = "fp32", kappa: float = 32.0, dir: int = -
         r = D1 / D0
         b = int(round(r.real)) - 1
         if not (0 <= b < G and abs(r - (b + 1)) <= rho):
-            res["action"] = "uncorrectable"
-            return res
+            if not fallback:
+                res["action"] = "uncorrectable"
+                return res
+            a = left_vector(N, M, dir)
+            e = encoding_vector(N, M)
+            d = Y @ e - X @ a
+            b = int(np.argmax(np.abs(d)))
+            res["fallback"] = True
     else:
         return res
     res["b"] = b

@@ -448,3 +448,37 @@ def test_thread_check_no_false_alarm_in_fp32_rounding():
             nu = float(np.vdot(v, v).real)
             tau = 8 * 2.0 ** -24 * np.sqrt(R * (np.log2(R) + 3)) * np.sqrt(nu)
             assert abs(complex(q) - complex(p)) <= tau, R
+
+
+def test_location_fallback_finds_the_signal_when_the_code_is_noisy():
+    """A fault above the threshold in a group of 32 whose outputs carry
+    rounding-like noise (each signal's own checksum noise about 0.06 tau):
+    the weighted sum D1 gathers the noise of every signal with weights up to
+    32, so D1/D0 misses the index in most cases; the re-encoding fallback
+    then still finds the faulty signal, and where the code does give an
+    index the fallback is not consulted (brute force over seeds)."""
+    G, N = 32, 256
+    misses = 0
+    for seed in range(40):
+        rng = np.random.default_rng(1000 + seed)
+        X = rng.uniform(-1, 1, (G, N)) + 1j * rng.uniform(-1, 1, (G, N))
+        Y = np.fft.fft(X, axis=1)
+        M = am.choose_M(N)
+        tau = am.threshold(N, am.group_checksums(X, Y, M)["nu"], "fp32", 8.0)
+        s = 0.35 * tau / np.sqrt(N * G)
+        Y = Y + s * (rng.standard_normal((G, N)) + 1j * rng.standard_normal((G, N))) / np.sqrt(2)
+        b0, k0 = int(rng.integers(0, G)), int(rng.integers(0, N))
+        e = am.encoding_vector(N, M)
+        Yf = Y.copy()
+        Yf[b0, k0] += 2.0 * tau / abs(e[k0])
+        plain = am.abft_group(X, Yf, "fp32", kappa=8.0)
+        fb = am.abft_group(X, Yf, "fp32", kappa=8.0, fallback=True)
+        assert plain["action"] != "clean", seed
+        if plain["action"] == "uncorrectable":
+            misses += 1
+            assert fb["fallback"] and fb["b"] == b0 and fb["action"] in ("corrected", "rebuilt"), seed
+        else:
+            # the code gave an index (with this much noise not always the
+            # right one): the fallback is not consulted
+            assert fb["b"] == plain["b"] and not fb["fallback"], seed
+    assert misses >= 10, misses
