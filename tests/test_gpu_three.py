@@ -189,3 +189,53 @@ def test_noalloc_rejects_three_pass(dev):
     out = torch.empty_like(xd)
     with pytest.raises(RuntimeError):
         tf.fft_c2c_noalloc(xd, out, ft_mode=tf.FT_OFF)
+
+
+def test_capture_after_prepare(dev):
+    """tfft_prepare reserves the two intermediates of a three-pass chunk, so
+    a captured call allocates nothing; replays with new data match the eager
+    result bit for bit (eager work between replays)."""
+    N, batch = 1 << 23, 2
+    s = torch.cuda.Stream(device=dev)
+    x = torch.empty(batch, N, dtype=DT, device=dev)
+    y = torch.empty_like(x)
+    counts = tf.new_counts(dev)
+    with torch.cuda.stream(s):
+        tf.prepare(N, DT, tf.FT_CORRECT, batch=batch)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        tf.fft_c2c(x, ft_mode=tf.FT_CORRECT, out=y, counts=counts)
+    torch.cuda.synchronize()
+    for r in range(3):
+        fresh = synth.signals(batch, N, seed=7500 + r)
+        x.copy_(torch.from_numpy(fresh).to(dev))
+        with torch.cuda.stream(s):
+            eager, _ = tf.fft_c2c(x, ft_mode=tf.FT_CORRECT)
+        torch.cuda.synchronize()
+        counts.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(y, eager), r
+        assert tf.counts_dict(counts)["detected"] == 0
+    ref = oracle.fft(fresh[[1]], threads=8)
+    assert _per_signal_rel(y.cpu().numpy()[[1]], ref).max() <= TOL
+
+
+def test_offline_abft_on_three_pass_length(dev):
+    """The unfused baseline runs on the three-pass transform too: clean
+    output equals the fused path's plain output; a flip in the last pass is
+    detected and the signal rebuilt."""
+    N, batch = 1 << 23, 2
+    x = synth.signals(batch, N, seed=7550)
+    xd = torch.from_numpy(x).to(dev)
+    y0, _ = tf.fft_c2c(xd, ft_mode=tf.FT_OFF)
+    y, counts = tf.fft_c2c_offline(xd)
+    assert tf.counts_dict(counts)["detected"] == 0
+    assert torch.equal(y, y0)
+    tf.inject_arm(1, 4321, 0, 30, dtype=DT, pass_=2)
+    y, counts = tf.fft_c2c_offline(xd)
+    c = tf.counts_dict(counts)
+    assert c["detected"] == 1 and c["rebuilt"] == 1 and c["last_signal"] == 1, c
+    assert oracle.rel_l2(y[1].cpu().numpy(), y0[1].cpu().numpy()) <= TOL
+    assert torch.equal(y[0], y0[0])
