@@ -863,7 +863,7 @@ template <class V, class PL, int FT, bool IND = false> struct Smem {
     static constexpr bool AW_FITS = wg_fit(REST + PL::Ns * (int)sizeof(V)) == wg_fit(REST);
     static constexpr bool AW_LDS =
         FT != 0 && (kResident<V, PL, FT, IND> ||
-                    ((PL::IS_COL || (PL::KIND == kSingle && PL::SLOTS >= 2 && PL::Ns <= 2048)) && AW_FITS));
+                    ((PL::TILE || (PL::KIND == kSingle && PL::SLOTS >= 2 && PL::Ns <= 2048)) && AW_FITS));
     static constexpr int AW = AW_LDS ? PL::Ns : 0;
     static constexpr int TWS_OFF = PL::LDS_DATA * (int)sizeof(V);
     static constexpr int AW_OFF = TWS_OFF + TWS * (int)sizeof(V);
