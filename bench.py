@@ -60,7 +60,8 @@ def kernel_fingerprint() -> str:
     pkg = os.path.join(ROOT, "paper_2412_05824_amd")
     for f in ("csrc/tfft_device.hpp", "csrc/tfft_kernels.hpp", "csrc/inst_fp32_single.hip",
               "csrc/inst_fp32_single_e8.hip",
-              "csrc/inst_fp32_single_stream.hip", "csrc/inst_fp32_tiles.hip", "csrc/inst_fp32_tiles_narrow.hip",
+              "csrc/inst_fp32_single_stream.hip", "csrc/inst_fp32_single_16k.hip",
+              "csrc/inst_fp32_tiles.hip", "csrc/inst_fp32_tiles_narrow.hip",
               "csrc/inst_fp32_tiles_e8.hip", "csrc/inst_fp32_tiles_wide.hip", "csrc/inst_fp32_three.hip",
               "tuning/mi355x.json"):
         path = os.path.join(pkg, f)

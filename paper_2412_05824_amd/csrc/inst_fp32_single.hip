@@ -16,6 +16,7 @@ void register_fp32_single(std::vector<KernelEntry>& out) {
     add_plan<float2, kSingle, 8192, 16, 4, 4, 2, 16, 16, 16>(out, 0);
     register_fp32_single_e8(out);
     register_fp32_single_stream(out);
+    register_fp32_single_16k(out);
 }
 
 }  // namespace tfft

@@ -100,6 +100,7 @@ void add_plan(std::vector<KernelEntry>& out, int precision, int variant = 0) {
 void register_fp32_single(std::vector<KernelEntry>& out);
 void register_fp32_single_e8(std::vector<KernelEntry>& out);
 void register_fp32_single_stream(std::vector<KernelEntry>& out);
+void register_fp32_single_16k(std::vector<KernelEntry>& out);
 void register_fp32_tiles(std::vector<KernelEntry>& out);
 void register_fp32_tiles_narrow(std::vector<KernelEntry>& out);
 void register_fp32_tiles_e8(std::vector<KernelEntry>& out);
