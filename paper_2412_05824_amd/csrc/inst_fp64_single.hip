@@ -13,6 +13,7 @@ void register_fp64_single(std::vector<KernelEntry>& out) {
     add_plan<double2, kSingle, 2048, 8, 4, 3, 4, 8, 8, 8>(out, 1);
     add_plan<double2, kSingle, 4096, 8, 4, 3, 8, 8, 8, 8>(out, 1);
     register_fp64_single_stream(out);
+    register_fp64_single_8k(out);
 }
 
 }  // namespace tfft

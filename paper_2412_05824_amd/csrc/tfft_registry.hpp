@@ -107,6 +107,7 @@ void register_fp32_tiles_e8(std::vector<KernelEntry>& out);
 void register_fp32_tiles_wide(std::vector<KernelEntry>& out);
 void register_fp64_single(std::vector<KernelEntry>& out);
 void register_fp64_single_stream(std::vector<KernelEntry>& out);
+void register_fp64_single_8k(std::vector<KernelEntry>& out);
 void register_fp64_tiles(std::vector<KernelEntry>& out);
 void register_fp32_three(std::vector<KernelEntry>& out);
 // the stepwise study's radix-2 plans (not in the route registry) and its
