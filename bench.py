@@ -98,6 +98,8 @@ def parse():
     p.add_argument("--ragged-only", action="store_true",
                    help="only run the ragged-batch comparison (for profiling its kernels)")
     p.add_argument("--ragged-signals", type=int, default=10000)
+    p.add_argument("--no-ragged-small", action="store_true",
+                   help="skip the small-signal ragged batch (profiles of the 10,000-signal workload alone)")
     p.add_argument("--copy-ref", action="store_true",
                    help="only run a plain 1 GiB device copy (reference for counter scaling)")
     p.add_argument("--study", choices=("roc", "ablation", "offline", "stepwise"), default=None,
@@ -634,6 +636,8 @@ def ragged_compare(tf, synth, np, torch, dev, args):
                      [int(n) for n in synth.ragged_sizes(args.ragged_signals, seed=5)],
                      f"{args.ragged_signals} fp32 signals, lengths uniform over 2^k and 3*2^k, "
                      f"6<=k<=16 (seed 5)")
+    if args.no_ragged_small:
+        return out
     small_menu = [n for n in synth.RAGGED_SIZES if n <= 3072]
     out["small_signals"] = ragged_one(
         tf, synth, np, torch, dev, args,
