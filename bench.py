@@ -44,6 +44,36 @@ HBM_PEAK_GBS = 8000.0
 TOTAL_ELEMS = 1 << 27          # 1 GiB of complex64 per buffer
 
 
+def streaming_reference(torch, stream, x, y, reps=20):
+    """GB/s (read + write bytes) of torch's own 1 GiB device copy and in-place
+    complex scale on the benchmark buffers: what a plain streaming kernel
+    reaches here, beside the 8 TB/s peak."""
+    nbytes = 2 * x.numel() * x.element_size()
+
+    def rate(fn):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        best = None
+        for _ in range(3):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(reps):
+                fn()
+            b.record(stream)
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b) / reps
+            best = ms if best is None else min(best, ms)
+        return round(nbytes / (best * 1e-3) / 1e9, 1)
+
+    copy_gbs = rate(lambda: y.copy_(x))
+    scale_gbs = rate(lambda: y.mul_(-1.0))
+    return {"copy_gbs": copy_gbs, "scale_in_place_gbs": scale_gbs, "bytes": nbytes,
+            "kernels": "torch Tensor.copy_ and Tensor.mul_ (in place) over the 1 GiB sweep buffers, best of 3x"
+                       f"{reps} launches, outside the timed region"}
+
+
 def kernel_label(k: dict) -> str:
     """Name of one plan's kernel in the launch-timing log, as the profile
     summaries name it: precision, kind, length, E, width (C sub-signals of a
@@ -249,6 +279,9 @@ def main():
                                 per_kernel_ms[N], rng, torch.complex64),
             })
 
+    # ---- what plain streaming kernels reach on this GPU (context) ----
+    stream_ref = None if args.no_extra else streaming_reference(torch, stream, x, y)
+
     # ---- ragged batch: one persistent launch vs one launch per length ----
     ragged = None
     if not args.no_ragged:
@@ -330,6 +363,7 @@ def main():
                     sorted(kernels, key=lambda k: -k["total_ms"])],
         "kernels_from": kernels_from,
         "cpu_baseline": cpu,
+        "streaming_reference": stream_ref,
         "clean_counts": c_clean,
         "sweep": {str(k): v for k, v in sweep.items()},
         "ragged": ragged,
