@@ -70,7 +70,12 @@ void cis_neg(long long num, long long den, long double* re, long double* im) {
     *im = neg ? s : -s;
 }
 
-struct SubTables { void* tw = nullptr; void* left = nullptr; };
+struct SubTables {
+    void* tw = nullptr;
+    void* left = nullptr;
+    void* cot = nullptr;             // cotangent form of the left vector (KernelEntry::cot)
+    long double c2[2] = {0, 0};      // its factor (1 - w_M^N) / 2
+};
 struct PassTwiddle { void* hi = nullptr; void* lo = nullptr; int bits = 0; };
 
 struct Tuning {
@@ -85,7 +90,7 @@ std::mutex g_mu;
 std::vector<KernelEntry>* g_entries = nullptr;
 std::map<std::tuple<int, int, int, int, int>, const KernelEntry*> g_by_key;   // (prec, kind, Ns, ft, variant)
 std::map<std::pair<int, int>, const KernelEntry*> g_ragged_by_key;      // (ragged plan id, ft)
-std::map<std::tuple<int, int, int, long long>, SubTables> g_sub;         // (prec, Ns, device, radices)
+std::map<std::tuple<int, int, int, long long, int>, SubTables> g_sub;    // (prec, Ns, device, radices, cot lanes)
 std::map<std::tuple<int, long long, int>, PassTwiddle> g_pass;           // (prec, N, device)
 struct DeviceAlloc {
     bool operator()(void** p, size_t bytes) const {
@@ -412,6 +417,32 @@ template <class R> int build_left(long long N, void** out) {
     return upload(left, out);
 }
 
+// The left vector in cotangent form.  With w_M w_N^n = exp(-i theta_n),
+// theta_n = 2 pi (N + M n) / (M N), 1 / (1 - exp(-i theta)) = (1 - i cot(theta / 2)) / 2,
+// so a_n = c2 (1 - i cot(theta_n / 2)) with c2 = (1 - w_M^N) / 2: one real value
+// per element.  Stored for lanes t < P holding elements t + P r (r < E), in
+// 16-byte runs of G = 16 / sizeof(R) consecutive r: value (t, r) at
+// ((r / G) P + t) G + r % G.
+template <class R> int build_cot(long long N, int P, int E, SubTables* out) {
+    const long long M = (N % 3 == 0) ? 5 : 3;
+    const int G = 16 / (int)sizeof(R);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    std::vector<R> cot((size_t)P * (size_t)E);
+    for (int r = 0; r < E; ++r)
+        for (int t = 0; t < P; ++t) {
+            const long long n = t + (long long)P * r;
+            // theta / 2 = pi k / (M N), k = (N + M n) mod (M N), never 0 (M does not divide N)
+            const long long k = (N + M * n) % (M * N);
+            const long double h = pi * (long double)k / (long double)(M * N);
+            cot[((size_t)(r / G) * P + t) * G + r % G] = (R)(cosl(h) / sinl(h));
+        }
+    long double wr, wi;
+    cis_neg(N, M, &wr, &wi);
+    out->c2[0] = (1.0L - wr) / 2.0L;
+    out->c2[1] = -wi / 2.0L;
+    return upload(cot, &out->cot);
+}
+
 // stage tables w_{L R}^{j k} (k < L, j < R per stage) and a = e^T W
 template <class R> int build_sub(const KernelEntry& e, SubTables* out) {
     const long long N = e.Ns;
@@ -429,7 +460,9 @@ template <class R> int build_sub(const KernelEntry& e, SubTables* out) {
     }
     int rc = upload(tw, &out->tw);
     if (rc != TFFT_OK) return rc;
-    return build_left<R>(N, &out->left);
+    rc = build_left<R>(N, &out->left);
+    if (rc != TFFT_OK || !e.cot) return rc;
+    return build_cot<R>(N, e.P, e.E, out);
 }
 
 // two-level table: w_N^m = hi[m >> bits] * lo[m & (2^bits - 1)]
@@ -475,7 +508,7 @@ long long radix_signature(const KernelEntry& e) {
 }
 
 int get_sub(const KernelEntry& e, bool may_alloc, SubTables** out) {
-    auto key = std::make_tuple(e.precision, e.Ns, current_device(), radix_signature(e));
+    auto key = std::make_tuple(e.precision, e.Ns, current_device(), radix_signature(e), e.cot ? e.P : 0);
     auto it = g_sub.find(key);
     if (it != g_sub.end()) { *out = &it->second; return TFFT_OK; }
     if (!may_alloc) return TFFT_ECAPTURE;
@@ -564,6 +597,8 @@ void fill_common(KArgs<V>& a, const KernelEntry& e, const SubTables& st, const T
     using R = typename RealOf<V>::type;
     a.tw = static_cast<const V*>(st.tw);
     a.left = static_cast<const V*>(st.left);
+    a.cot = static_cast<const R*>(st.cot);
+    a.cot_c2 = V{(R)st.c2[0], (R)st.c2[1]};
     a.T = tu.T;
     a.gran = tu.gran;
     const double u = e.precision == TFFT_FP32 ? 0x1p-24 : 0x1p-53;

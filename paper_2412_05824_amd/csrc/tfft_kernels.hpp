@@ -130,6 +130,13 @@ template <class V> struct KArgs : KCall<typename RealOf<V>::type> {
     const long long* in_tab;
     const long long* out_tab;
     const long long* id_tab;
+    // Left vector in cotangent form (streaming single passes): with
+    // w_M w_N^n = exp(-i theta_n), a_n = c2 (1 - i cot(theta_n / 2)),
+    // c2 = (1 - w_M^N) / 2, so p = c2 (sum_n x_n - i sum_n cot_n x_n) needs one
+    // real table value per element.  cot holds them lane by lane in runs of
+    // 16 bytes: value (t, r) at ((r / G) P + t) G + r % G, G = 16 / sizeof(R).
+    const R* cot;
+    V cot_c2;
 };
 
 // Compile-time plan: kind, sub-length Ns, E elements per lane, WC = waves per
@@ -830,6 +837,11 @@ template <class V, class PL, int FT, bool IND> constexpr bool kResident =
     FT != 0 && !IND && PL::KIND == kSingle && PL::SLOTS == 1 && !PL::STREAM &&
     (sizeof(V) == 8 ? (PL::E == 8 || PL::Ns >= 8192) : PL::Ns >= 4096);
 
+// Streaming single passes (e^T W from the cached table) read the left vector
+// in its cotangent form (KArgs::cot): half the bytes, and one 16-byte load
+// per 4 (fp32) or 2 (fp64) elements instead of one load per element.
+template <class V, class PL, int FT, bool IND> constexpr bool kCotLeft = FT != 0 && !IND && PL::STREAM;
+
 // LDS of one workgroup of a plan: exchange buffer, then reduction scratch
 template <class V, class PL, int FT, bool IND = false> struct Smem {
     using R = typename RealOf<V>::type;
@@ -968,8 +980,12 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
     // with clean checksums: the registers held the right values); two
     // 8-byte stores instead cost more than the flat store saves.
     constexpr bool kBufStore = kBufIO && sizeof(V) == 8;
+    constexpr bool kCot = kCotLeft<V, PL, FT, IND> && kBufIO;
+    constexpr int CG = 16 / (int)sizeof(R);   // cotangent values per 16-byte load
+    static_assert(!kCot || E % CG == 0, "whole 16-byte runs of the cotangent table");
     const V* left = a.left;
     const auto left_rs = buf_rsrc(a.left);
+    const auto cot_rs = buf_rsrc(a.cot);
     if constexpr (Smem<V, PL, FT, IND>::AW_LDS) {
         V* awl = reinterpret_cast<V*>(smem + Smem<V, PL, FT, IND>::AW_OFF);
         if constexpr (!kResident<V, PL, FT, IND>) {   // resident kernels staged it once
@@ -1025,11 +1041,20 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
             if constexpr (Smem<V, PL, FT, IND>::AW_LDS || !kBufIO) return left[t + P * r];
             else return buf_load<V>(left_rs, (unsigned)t * (unsigned)sizeof(V), (unsigned)(P * r * (int)sizeof(V)));
         };
-        constexpr bool kAwEarly = FT != 0 && PL::KIND == kSingle && kBufIO;
+        constexpr bool kAwEarly = FT != 0 && PL::KIND == kSingle && kBufIO && !kCot;
         V aw[kAwEarly ? E : 1];
         if constexpr (kAwEarly) {
 #pragma unroll
             for (int r = 0; r < E; ++r) aw[r] = left_at(r);
+        }
+        R cw[kCot ? E : 1];
+        if constexpr (kCot) {
+#pragma unroll
+            for (int j = 0; j < E / CG; ++j) {
+                const auto q = __builtin_amdgcn_raw_buffer_load_b128(cot_rs, (int)((unsigned)t * 16u),
+                                                                      j * P * 16, 0);
+                __builtin_memcpy(&cw[j * CG], &q, 16);
+            }
         }
         if (valid) {
             if constexpr (kBufIO) {
@@ -1060,6 +1085,7 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
         R nub = 0;   // input energy of this transaction
         {
             const R wb = (R)(b + 1);
+            V cs = V{0, 0};   // cotangent form: sum of the values, sum of cot_n x_n in p
 #pragma unroll
             for (int r = 0; r < E; ++r) {
                 const V z = reg[r];   // raw loaded value
@@ -1069,15 +1095,22 @@ __device__ __forceinline__ void fft_body(const V* __restrict__ x, V* __restrict_
                     reg[r] = cmul(z, tw);
                 }
                 if constexpr (FT != 0) {
-                    V av;
-                    if constexpr (kAwEarly) av = aw[r];
-                    else av = left_at(r);
-                    if constexpr (PL::HAS_TW) av = cmul(av, tw);
-                    p = cmac(p, av, z);
+                    if constexpr (kCot) {
+                        cs = cadd(cs, z);
+                        p = V{fmad(cw[r], z.x, p.x), fmad(cw[r], z.y, p.y)};
+                    } else {
+                        V av;
+                        if constexpr (kAwEarly) av = aw[r];
+                        else av = left_at(r);
+                        if constexpr (PL::HAS_TW) av = cmul(av, tw);
+                        p = cmac(p, av, z);
+                    }
                     nub = fmad(z.x, z.x, fmad(z.y, z.y, nub));
                     if constexpr (KEEP_XS) xs[r] = cadd(xs[r], z);
                 }
             }
+            // p = c2 (S - i C), S = sum x_n, C = sum cot_n x_n
+            if constexpr (kCot) p = cmul(a.cot_c2, V{cs.x + p.y, cs.y - p.x});
             if constexpr (FT != 0) {
                 if (!per_tx) {
                     ps = cadd(ps, p);

@@ -27,6 +27,7 @@ struct KernelEntry {
     int ragged_id;          // index in the ragged plan list (-1: regular plan)
     int variant;            // plans of one (kind, Ns): 0 default, 1.. alternatives
     int tx_max;             // per-transaction checking: most transactions per group
+    int cot;                // 1: reads the left vector in cotangent form (KArgs::cot)
 };
 
 // grid: workgroups' worth of work.  Resident kernels launch at most as many
@@ -74,6 +75,7 @@ template <class V, class PL, int FT, bool IND, int... Rs> KernelEntry make_entry
     e.ragged_id = -1;
     e.variant = 0;
     e.tx_max = Geo<V, PL, IND>::TX_MAX;
+    e.cot = kCotLeft<V, PL, kGroupFt<FT>, IND> ? 1 : 0;
     return e;
 }
 

@@ -26,6 +26,29 @@ def brute_left(N, M, dir=-1):
     return out
 
 
+@pytest.mark.parametrize("N", [8, 64, 96, 1024, 6144, 8192, 16384])
+def test_left_vector_cotangent_form(N):
+    """The streaming single-pass kernels encode with a real table: with
+    w_M w_N^n = exp(-i theta_n), 1 / (1 - exp(-i theta)) = (1 - i cot(theta/2)) / 2,
+    so a_n = c2 (1 - i cot(theta_n / 2)), c2 = (1 - w_M^N) / 2, and
+    p = a^T x = c2 (S - i C) with S = sum x_n, C = sum cot_n x_n.  Checked
+    against e^T W summed term by term (small N) and the oracle's transform
+    of e (large N); theta_n / 2 = pi k / (M N), k = (N + M n) mod (M N) > 0."""
+    M = am.choose_M(N)
+    n = np.arange(N)
+    k = (N + M * n) % (M * N)
+    assert k.min() > 0
+    cot = np.cos(np.pi * k / (M * N)) / np.sin(np.pi * k / (M * N))
+    c2 = (1 - np.exp(-2j * np.pi * N / M)) / 2
+    ref = brute_left(N, M) if N <= 1024 else am.left_vector(N, M)
+    np.testing.assert_allclose(c2 * (1 - 1j * cot), ref, rtol=0, atol=1e-10 * N)
+    rng = np.random.default_rng(N)
+    x = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    S, C = x.sum(), (cot * x).sum()
+    p = c2 * complex(S.real + C.imag, S.imag - C.real)
+    assert abs(p - ref @ x) <= 1e-10 * N * np.linalg.norm(x)
+
+
 @pytest.mark.parametrize("N,M", [(8, 3), (64, 3), (256, 3), (12, 5), (96, 5), (48, 7), (1024, 5)])
 def test_left_vector_closed_form_and_norm(N, M):
     for d in (-1, +1):
