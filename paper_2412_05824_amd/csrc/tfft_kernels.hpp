@@ -130,11 +130,12 @@ template <class V> struct KArgs : KCall<typename RealOf<V>::type> {
     const long long* in_tab;
     const long long* out_tab;
     const long long* id_tab;
-    // Left vector in cotangent form (streaming single passes): with
-    // w_M w_N^n = exp(-i theta_n), a_n = c2 (1 - i cot(theta_n / 2)),
-    // c2 = (1 - w_M^N) / 2, so p = c2 (sum_n x_n - i sum_n cot_n x_n) needs one
-    // real table value per element.  cot holds them lane by lane in runs of
-    // 16 bytes: value (t, r) at ((r / G) P + t) G + r % G, G = 16 / sizeof(R).
+    // Left vector in cotangent form (single passes that read it from the
+    // cached table): with w_M w_N^n = exp(-i theta_n),
+    // a_n = c2 (1 - i cot(theta_n / 2)), c2 = (1 - w_M^N) / 2, so
+    // p = c2 (sum_n x_n - i sum_n cot_n x_n) needs one real table value per
+    // element.  cot holds them lane by lane in runs of 16 bytes: value (t, r)
+    // at ((r / G) P + t) G + r % G, G = 16 / sizeof(R).
     const R* cot;
     V cot_c2;
 };
@@ -837,11 +838,6 @@ template <class V, class PL, int FT, bool IND> constexpr bool kResident =
     FT != 0 && !IND && PL::KIND == kSingle && PL::SLOTS == 1 && !PL::STREAM &&
     (sizeof(V) == 8 ? (PL::E == 8 || PL::Ns >= 8192) : PL::Ns >= 4096);
 
-// Streaming single passes (e^T W from the cached table) read the left vector
-// in its cotangent form (KArgs::cot): half the bytes, and one 16-byte load
-// per 4 (fp32) or 2 (fp64) elements instead of one load per element.
-template <class V, class PL, int FT, bool IND> constexpr bool kCotLeft = FT != 0 && !IND && PL::STREAM;
-
 // LDS of one workgroup of a plan: exchange buffer, then reduction scratch
 template <class V, class PL, int FT, bool IND = false> struct Smem {
     using R = typename RealOf<V>::type;
@@ -883,6 +879,12 @@ template <class V, class PL, int FT, bool IND = false> struct Smem {
     static constexpr int TXR_OFF = TXR_ALIAS ? 0 : RED_OFF + RED * (int)sizeof(R);
     static constexpr int BYTES = RED_OFF + RED * (int)sizeof(R) + (TXR_ALIAS ? 0 : TXR * (int)sizeof(R));
 };
+
+// Single passes that read e^T W from the cached table (not staged in LDS)
+// read it in its cotangent form (KArgs::cot): half the bytes, and one 16-byte
+// load per 4 (fp32) or 2 (fp64) elements instead of one load per element.
+template <class V, class PL, int FT, bool IND> constexpr bool kCotLeft =
+    FT != 0 && !IND && PL::KIND == kSingle && !Smem<V, PL, FT, IND>::AW_LDS;
 
 // Buffers that other workgroups of the same launch read back (the persistent
 // ragged kernel's workspace) are accessed coherently at device scope: each
