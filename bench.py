@@ -570,23 +570,30 @@ def fp64_sweep(tf, torch, dev, args):
         if not tf.supported(N, torch.complex128):
             continue
         xv, yv = x.view(-1, N), y.view(-1, N)
-        ms = {}
+        ms, ms_fwd, ms_inv = {}, {}, {}
         counts.zero_()   # the previous length's injected flips are counted already
         for ft in (tf.FT_OFF, tf.FT_CORRECT):
-            def step():
+            # a round trip per step (the in-place inverse brings the forward
+            # output back to the input's scale), each launch timed on its own
+            def step(ev=None):
+                if ev is not None:
+                    ev[0].record()
                 tf.fft_c2c(xv, dir=tf.FORWARD, ft_mode=ft, out=yv, counts=counts)
+                if ev is not None:
+                    ev[1].record()
                 tf.fft_c2c(yv, dir=tf.INVERSE, ft_mode=ft, out=yv, counts=counts)
+                if ev is not None:
+                    ev[2].record()
             for _ in range(max(1, args.warmup)):
                 step()
             torch.cuda.synchronize()
-            a = torch.cuda.Event(enable_timing=True)
-            b = torch.cuda.Event(enable_timing=True)
-            a.record()
-            for _ in range(reps):
-                step()
-            b.record()
+            evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(reps)]
+            for ev in evs:
+                step(ev)
             torch.cuda.synchronize()
-            ms[ft] = a.elapsed_time(b) / reps
+            ms_fwd[ft] = sum(ev[0].elapsed_time(ev[1]) for ev in evs) / reps
+            ms_inv[ft] = sum(ev[1].elapsed_time(ev[2]) for ev in evs) / reps
+            ms[ft] = ms_fwd[ft] + ms_inv[ft]
         # the fault-free runs above must not have counted anything
         clean = tf.counts_dict(counts)
         # seeded flips: one in a forward and one in an inverse launch; the hit
@@ -611,17 +618,23 @@ def fp64_sweep(tf, torch, dev, args):
                           "hit_signal_rel_after": after, "hit_signal_within_tol": after <= 1e-13})
         torch.cuda.synchronize()
         c = tf.counts_dict(counts)
-        bytes_step = 2 * 2 * total * 16              # forward + inverse, read + write
-        out[str(N)] = {"ft_gbs": round(bytes_step / (ms[2] * 1e-3) / 1e9, 1),
-                       "off_gbs": round(bytes_step / (ms[0] * 1e-3) / 1e9, 1),
-                       "ft_overhead_pct": round(100.0 * (ms[2] / ms[0] - 1.0), 1),
+        bytes_one = 2 * total * 16                   # one transform: read + write
+        gbs = lambda t: round(bytes_one / (t * 1e-3) / 1e9, 1)
+        out[str(N)] = {"ft_gbs": gbs(ms_fwd[2]),
+                       "off_gbs": gbs(ms_fwd[0]),
+                       "ft_overhead_pct": round(100.0 * (ms_fwd[2] / ms_fwd[0] - 1.0), 1),
+                       "inverse_in_place": {"ft_gbs": gbs(ms_inv[2]), "off_gbs": gbs(ms_inv[0]),
+                                            "ft_overhead_pct": round(100.0 * (ms_inv[2] / ms_inv[0] - 1.0), 1)},
+                       "round_trip_ft_overhead_pct": round(100.0 * (ms[2] / ms[0] - 1.0), 1),
                        "clean_detected": clean["detected"],
                        "flips": flips,
                        "counts": {k: c[k] for k in ("detected", "corrected", "rebuilt", "uncorrectable")}}
     del x, y
     torch.cuda.empty_cache()
-    return {"workload": "complex128 forward+inverse, N=2^6..2^20, batch=2^26/N (1 GiB), inputs N(0,1) "
-                        "from a device generator (seed 3000), ABFT correct vs off, 2 seeded flips per N",
+    return {"workload": "complex128 forward (out of place; ft_gbs, off_gbs, ft_overhead_pct) then inverse "
+                        "(in place, the in-place correcting kernels; inverse_in_place), N=2^6..2^20, batch=2^26/N "
+                        "(1 GiB), inputs N(0,1) from a device generator (seed 3000), ABFT correct vs off, "
+                        "each launch timed with HIP events, 2 seeded flips per N",
             "per_n": out}
 
 
