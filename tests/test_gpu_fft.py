@@ -106,6 +106,42 @@ def test_in_place_and_explicit_scale(dev, dtype):
     assert oracle.rel_l2(y.cpu().numpy(), 0.5 * oracle.fft(x)) <= TOL[dtype]
 
 
+@pytest.mark.parametrize("dtype,N", [(torch.complex64, 8192), (torch.complex64, 16384),
+                                     (torch.complex128, 2048), (torch.complex128, 4096),
+                                     (torch.complex128, 8192)],
+                         ids=["fp32-8192", "fp32-16384", "fp64-2048", "fp64-4096", "fp64-8192"])
+def test_in_place_correction_on_table_encoded_single_passes(dev, dtype, N):
+    """In place, the correcting kernels keep the group's input sums in
+    registers (the inputs are overwritten); these lengths encode with the
+    cotangent form of e^T W read from the table.  Clean: equal to the
+    out-of-place output, within tolerance of the oracle; one exponent flip:
+    detected, the signal repaired to the clean output's tolerance, the others
+    untouched."""
+    batch = _batch_for(N)
+    x = synth.signals(batch, N, seed=2600 + N, dtype=NPDT[dtype])
+    ref = oracle.fft(x, threads=8)
+    y0, _ = tf.fft_c2c(torch.from_numpy(x).to(dev), ft_mode=tf.FT_CORRECT)
+    xd = torch.from_numpy(x).to(dev)
+    y, counts = tf.fft_c2c(xd, ft_mode=tf.FT_CORRECT, out=xd)
+    assert y.data_ptr() == xd.data_ptr()
+    assert tf.counts_dict(counts)["detected"] == 0
+    assert torch.equal(xd, y0)
+    assert _per_signal_rel(xd.cpu().numpy(), ref).max() <= TOL[dtype]
+    sig, elem = batch // 2, N // 3
+    bit = 28 if dtype == torch.complex64 else 60
+    xd = torch.from_numpy(x).to(dev)
+    tf.inject_arm(sig, elem, 0, bit, dtype=dtype)
+    y, counts = tf.fft_c2c(xd, ft_mode=tf.FT_CORRECT, out=xd)
+    c = tf.counts_dict(counts)
+    assert c["detected"] == 1 and c["uncorrectable"] == 0 and c["last_signal"] == sig, c
+    assert c["corrected"] + c["rebuilt"] == 1, c
+    yh, y0h = xd.cpu().numpy(), y0.cpu().numpy()
+    assert oracle.rel_l2(yh[sig], y0h[sig]) <= TOL[dtype]
+    others = np.ones(batch, bool)
+    others[sig] = False
+    assert np.array_equal(yh[others], y0h[others])
+
+
 def test_empty_batch_and_single_signal(dev):
     x = torch.zeros(0, 256, dtype=torch.complex64, device=dev)
     y, _ = tf.fft_c2c(x, ft_mode=tf.FT_OFF)
