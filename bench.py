@@ -271,10 +271,13 @@ def main():
         time_sweep(tf.FT_OFF, max(3, args.steps // 2), 1, per_kernel=off_ms)
         rng = np.random.default_rng(2024)
         for N in sizes:
+            ab_ft, ab_off = ab_overhead(tf, torch, stream, launch, N)
             sweep[N].update({
                 "off_ms": off_ms[N],
                 "off_gbs": 2 * TOTAL_ELEMS * 8 / (off_ms[N] * 1e-3) / 1e9,
-                "ft_overhead_pct": 100.0 * (per_kernel_ms[N] / off_ms[N] - 1.0),
+                "ft_overhead_pct": 100.0 * (ab_ft / ab_off - 1.0),
+                "ab_ft_ms": ab_ft, "ab_off_ms": ab_off,
+                "sweep_overhead_pct": 100.0 * (per_kernel_ms[N] / off_ms[N] - 1.0),
                 **injection_run(tf, torch, np, stream, counts, launch, y, N, TOTAL_ELEMS // N,
                                 per_kernel_ms[N], rng, torch.complex64),
             })
@@ -351,6 +354,10 @@ def main():
         "config": {"workload": "fp32 complex64 forward C2C FFT sweep N=2^6..2^22, "
                                "batch=2^27/N (1 GiB/buffer), two-side ABFT on",
                    "sizes": sizes, "sizes_missing": skipped, "ft_mode": "correct",
+                   "overhead": "sweep[N].ft_overhead_pct: ABFT correct vs off on the length's own tuned "
+                               "routes, alternating rounds of 10 launches, best round of each "
+                               "(ab_ft_ms, ab_off_ms); sweep_overhead_pct: the timed ABFT sweep's "
+                               "launch time over the later plain sweep's",
                    "pct_hbm_peak": round(100 * value / HBM_PEAK_GBS, 2)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -382,6 +389,28 @@ def flip_value(v: complex, part: int, bit: int, real_dtype) -> complex:
     u = a.view(np.uint32 if real_dtype == np.float32 else np.uint64)
     u[part] ^= (1 << bit)
     return complex(float(a[0]), float(a[1]))
+
+
+def ab_overhead(tf, torch, stream, launch, N, rounds=3, reps=10):
+    """ABFT correct against ABFT off on one length under the same conditions:
+    rounds of `reps` back-to-back launches of each mode, alternating (HIP
+    events around each round), best round of each mode; ms per launch."""
+    best = {}
+    for ft in (tf.FT_OFF, tf.FT_CORRECT):
+        launch(N, ft)
+    torch.cuda.synchronize()
+    for _ in range(rounds):
+        for ft in (tf.FT_OFF, tf.FT_CORRECT):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(reps):
+                launch(N, ft)
+            b.record(stream)
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b) / reps
+            best[ft] = min(best.get(ft, ms), ms)
+    return best[tf.FT_CORRECT], best[tf.FT_OFF]
 
 
 def injection_run(tf, torch, np, stream, counts, launch, y, N, batch, ft_ms, rng, dtype,
