@@ -73,7 +73,7 @@ void cis_neg(long long num, long long den, long double* re, long double* im) {
 struct SubTables {
     void* tw = nullptr;
     void* left = nullptr;
-    void* cot = nullptr;             // cotangent form of the left vector (KernelEntry::cot)
+    void* cot = nullptr;             // cotangent form of the left vector (single passes)
     long double c2[2] = {0, 0};      // its factor (1 - w_M^N) / 2
 };
 struct PassTwiddle { void* hi = nullptr; void* lo = nullptr; int bits = 0; };
@@ -90,7 +90,7 @@ std::mutex g_mu;
 std::vector<KernelEntry>* g_entries = nullptr;
 std::map<std::tuple<int, int, int, int, int>, const KernelEntry*> g_by_key;   // (prec, kind, Ns, ft, variant)
 std::map<std::pair<int, int>, const KernelEntry*> g_ragged_by_key;      // (ragged plan id, ft)
-std::map<std::tuple<int, int, int, long long, int>, SubTables> g_sub;    // (prec, Ns, device, radices, cot lanes)
+std::map<std::tuple<int, int, int, long long, int>, SubTables> g_sub;    // (prec, Ns, device, radices, single-pass lanes)
 std::map<std::tuple<int, long long, int>, PassTwiddle> g_pass;           // (prec, N, device)
 struct DeviceAlloc {
     bool operator()(void** p, size_t bytes) const {
@@ -426,6 +426,7 @@ template <class R> int build_left(long long N, void** out) {
 template <class R> int build_cot(long long N, int P, int E, SubTables* out) {
     const long long M = (N % 3 == 0) ? 5 : 3;
     const int G = 16 / (int)sizeof(R);
+    if (E % G != 0 || (long long)P * E != N) return TFFT_EINVAL;
     const long double pi = 3.141592653589793238462643383279502884L;
     std::vector<R> cot((size_t)P * (size_t)E);
     for (int r = 0; r < E; ++r)
@@ -461,7 +462,11 @@ template <class R> int build_sub(const KernelEntry& e, SubTables* out) {
     int rc = upload(tw, &out->tw);
     if (rc != TFFT_OK) return rc;
     rc = build_left<R>(N, &out->left);
-    if (rc != TFFT_OK || !e.cot) return rc;
+    // single passes: the cotangent form too, so that every mode of the plan
+    // (those that read it and those that do not) shares one set of tables;
+    // its layout needs whole 16-byte runs per lane (the kernels that read it
+    // have them)
+    if (rc != TFFT_OK || e.kind != kSingle || e.E % (16 / (int)sizeof(R)) != 0) return rc;
     return build_cot<R>(N, e.P, e.E, out);
 }
 
@@ -508,13 +513,14 @@ long long radix_signature(const KernelEntry& e) {
 }
 
 int get_sub(const KernelEntry& e, bool may_alloc, SubTables** out) {
-    auto key = std::make_tuple(e.precision, e.Ns, current_device(), radix_signature(e), e.cot ? e.P : 0);
+    auto key = std::make_tuple(e.precision, e.Ns, current_device(), radix_signature(e), e.kind == kSingle ? e.P : 0);
     auto it = g_sub.find(key);
     if (it != g_sub.end()) { *out = &it->second; return TFFT_OK; }
     if (!may_alloc) return TFFT_ECAPTURE;
     SubTables t;
     int rc = e.precision == TFFT_FP32 ? build_sub<float>(e, &t) : build_sub<double>(e, &t);
     if (rc != TFFT_OK) return rc;
+    if (e.cot && !t.cot) return TFFT_EINVAL;   // a kernel that reads the cotangent table needs it
     *out = &(g_sub[key] = t);
     return TFFT_OK;
 }
