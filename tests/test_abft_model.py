@@ -49,6 +49,35 @@ def test_left_vector_cotangent_form(N):
     assert abs(p - ref @ x) <= 1e-10 * N * np.linalg.norm(x)
 
 
+@pytest.mark.parametrize("N", [1024, 6144, 8192, 16384])
+def test_cotangent_form_rounding_in_fp32(N):
+    """Reading 27's claim that the cotangent form rounds like the complex
+    table: the input checksum p = a^T x computed in complex64 from each
+    table, rounded once, over 20 seeded U[-1,1) signals.  Both errors stay a
+    fraction of the fp32 threshold tau (kappa = 8) and the cotangent form's
+    is within 1.5x of the complex table's."""
+    M = am.choose_M(N)
+    a = am.left_vector(N, M)
+    n = np.arange(N)
+    k = (N + M * n) % (M * N)
+    cot32 = (np.cos(np.pi * k / (M * N)) / np.sin(np.pi * k / (M * N))).astype(np.float32)
+    c2 = np.complex64((1 - np.exp(-2j * np.pi * N / M)) / 2)
+    a32 = a.astype(np.complex64)
+    worst_c = worst_t = 0.0
+    for seed in range(20):
+        rng = np.random.default_rng(seed)
+        x = (rng.uniform(-1, 1, N) + 1j * rng.uniform(-1, 1, N)).astype(np.complex64)
+        p = a @ x.astype(np.complex128)
+        tau = am.threshold(N, float(np.sum(np.abs(x.astype(np.complex128)) ** 2)), "fp32", 8.0)
+        pc = (a32 * x).sum(dtype=np.complex64)
+        S, C = x.sum(dtype=np.complex64), (cot32 * x).sum(dtype=np.complex64)
+        pt = c2 * np.complex64(complex(S.real + C.imag, S.imag - C.real))
+        worst_c = max(worst_c, abs(pc - p) / tau)
+        worst_t = max(worst_t, abs(pt - p) / tau)
+    assert worst_c < 0.5 and worst_t < 0.5, (worst_c, worst_t)
+    assert worst_t <= 1.5 * worst_c, (worst_c, worst_t)
+
+
 @pytest.mark.parametrize("N,M", [(8, 3), (64, 3), (256, 3), (12, 5), (96, 5), (48, 7), (1024, 5)])
 def test_left_vector_closed_form_and_norm(N, M):
     for d in (-1, +1):
